@@ -1,0 +1,376 @@
+"""Pins for the FP64 oracle (CPU only).
+
+Each check ties the oracle to something other than itself: a library FFT,
+the DFT definition, an exact matrix identity printed in the paper, the
+paper's gate-count table and Fig. 1 circuit, closed forms, invariants and
+brute force on tiny inputs.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle as O
+from paper_2606_18981_amd import inputs as I
+
+TOL = 1e-12
+
+
+# --------------------------------------------------------------------------
+# the definition and the library special case
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", list(range(0, 11)))
+def test_naive_dft_is_numpy_fft(n):
+    x = I.gaussian(n, 100 + n)
+    assert O.rel_l2(O.dft_naive(x, "unitary"), np.fft.fft(x, norm="ortho")) < TOL
+    assert O.rel_l2(O.dft_naive(x, "none"), np.fft.fft(x)) < TOL
+    assert O.rel_l2(O.dft_naive(x, "inv_n"), np.fft.fft(x, norm="forward")) < TOL
+
+
+@pytest.mark.parametrize("n", list(range(1, 11)))
+@pytest.mark.parametrize("norm", O.NORMS)
+def test_exact_circuit_is_dft(n, norm):
+    x = I.uniform_pm1(n, 200 + n)
+    y = O.qft_circuit(x, None, norm, "natural")
+    assert O.rel_l2(y, O.dft_naive(x, norm)) < TOL
+    yb = O.qft_circuit(x, None, norm, "bitrev")
+    assert O.rel_l2(yb, O.dft_naive(x, norm, "bitrev")) < TOL
+
+
+def test_bitrev_order_is_index_permutation():
+    n = 7
+    x = I.gaussian(n, 3)
+    y = O.qft_circuit(x, None, "unitary", "natural")
+    yb = O.qft_circuit(x, None, "unitary", "bitrev")
+    for k in range(1 << n):
+        assert yb[O.bitrev_index(k, n)] == pytest.approx(y[k], abs=1e-14)
+
+
+# --------------------------------------------------------------------------
+# special inputs (Sec. 4 correctness inputs and closed forms)
+# --------------------------------------------------------------------------
+
+def test_delta_to_constant():
+    n = 10
+    y = O.qft_circuit(I.delta(n, 0))
+    assert np.allclose(y, 1.0 / math.sqrt(1 << n), atol=1e-15, rtol=0)
+
+
+@pytest.mark.parametrize("j", [1, 5, 37, 1000])
+def test_shifted_delta_is_twiddle_row(j):
+    n = 10
+    N = 1 << n
+    k = np.arange(N)
+    expect = np.exp(-2j * np.pi * ((j * k) % N) / N) / math.sqrt(N)
+    assert O.rel_l2(O.qft_circuit(I.delta(n, j)), expect) < TOL
+
+
+@pytest.mark.parametrize("n,k0", [(10, 37), (6, 2), (12, 2)])
+def test_tone_to_spike(n, k0):
+    N = 1 << n
+    y = O.qft_circuit(I.tone(n, k0))
+    expect = np.zeros(N, dtype=complex)
+    expect[k0] = math.sqrt(N)
+    assert np.max(np.abs(y - expect)) < 1e-12 * math.sqrt(N)
+
+
+def test_multi_tone_bins():
+    n = 12
+    N = 1 << n
+    x, bins, amp, ph = I.multi_tone(n, 1002, count=8, noise_var=0.01)
+    y = O.qft_circuit(x, None, "unitary")
+    # each tone contributes A e^{i phi} sqrt(N) at its bin; the noise floor
+    # per bin is ~ sqrt(2 * 0.01) = 0.14
+    for b, a, p in zip(bins, amp, ph):
+        assert abs(y[b] - a * np.exp(1j * p) * math.sqrt(N)) < 1.0
+    mask = np.ones(N, bool)
+    mask[bins] = False
+    assert np.max(np.abs(y[mask])) < 1.0
+
+
+def test_zero_input_gives_zero():
+    y = O.qft_circuit(np.zeros(16, complex))
+    assert np.all(y == 0)
+
+
+# --------------------------------------------------------------------------
+# invariants
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cutoff", [None, 0, 1, 2, 4, 7])
+def test_parseval_and_linearity(cutoff):
+    n = 9
+    N = 1 << n
+    x1 = I.gaussian(n, 11)
+    x2 = I.uniform_pm1(n, 12)
+    for norm, s in (("unitary", 1.0), ("none", math.sqrt(N)), ("inv_n", 1 / math.sqrt(N))):
+        y1 = O.qft_circuit(x1, cutoff, norm)
+        assert np.linalg.norm(y1) == pytest.approx(s * np.linalg.norm(x1), rel=1e-13)
+    a, b = 0.3 - 1.2j, -2.0 + 0.5j
+    lhs = O.qft_circuit(a * x1 + b * x2, cutoff)
+    rhs = a * O.qft_circuit(x1, cutoff) + b * O.qft_circuit(x2, cutoff)
+    assert O.rel_l2(lhs, rhs) < TOL
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6])
+@pytest.mark.parametrize("cutoff", [None, 0, 1, 2])
+def test_circuit_is_unitary(n, cutoff):
+    U = O.qft_circuit_matrix(n, cutoff)
+    assert np.max(np.abs(U.conj().T @ U - np.eye(1 << n))) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# the paper's circuit, table and matrix identities
+# --------------------------------------------------------------------------
+
+def _read_golden(path):
+    rows = []
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def test_fig1_gate_list(golden_dir):
+    rows = _read_golden(os.path.join(golden_dir, "fig1_qft3_gates.txt"))
+    expect = [(r[0],) + tuple(int(v) for v in r[1:]) for r in rows]
+    assert O.qft_gate_list(3, None) == expect
+    # cutoff k = 1 drops R_3 only; k = 2 is exact for three wires
+    assert O.qft_gate_list(3, 1) == [g for g in expect if g != ("CR", 0, 2, 3)]
+    assert O.qft_gate_list(3, 2) == expect
+
+
+def test_aqft_gate_count_table(golden_dir):
+    rows = _read_golden(os.path.join(golden_dir, "aqft_gate_counts_n22.txt"))
+    assert len(rows) == 7
+    for k, count, pct in rows:
+        k, count, pct = int(k), int(count), float(pct)
+        c = O.gate_counts(22, k)
+        assert c["CR"] == count
+        assert c["H"] == 22 and c["SWAP"] == 11
+        assert round(100.0 * count / 231, 1) == pct
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 10, 24, 28, 30])
+def test_gate_count_formula(n):
+    for k in range(0, n):
+        keff = min(k, n - 1)
+        assert O.gate_counts(n, k)["CR"] == keff * n - keff * (keff + 1) // 2
+    assert O.gate_counts(n, None)["CR"] == n * (n - 1) // 2
+
+
+def _L(K, M):
+    """Stride permutation L^{KM}_K read as a gather: y[iM + j] = x[jK + i]."""
+    P = np.zeros((K * M, K * M))
+    for i in range(K):
+        for j in range(M):
+            P[i * M + j, j * K + i] = 1.0
+    return P
+
+
+def _T(K, M):
+    """Twiddle T^{KM}_M = diag(w_{KM}^{ij}) at index iM + j."""
+    d = np.empty(K * M, dtype=complex)
+    for i in range(K):
+        for j in range(M):
+            d[i * M + j] = np.exp(-2j * np.pi * i * j / (K * M))
+    return np.diag(d)
+
+
+H2 = np.array([[1.0, 1.0], [1.0, -1.0]])
+
+
+@pytest.mark.parametrize("K,M", [(2, 2), (4, 2), (2, 4), (4, 4), (8, 4)])
+def test_cooley_tukey_rule(K, M):
+    """Eq. (Cooley-Tukey): DFT_KM = (DFT_K (x) I_M) T^{KM}_M (I_K (x) DFT_M) L^{KM}_K."""
+    lhs = O.dft_matrix(K * M)
+    rhs = (np.kron(O.dft_matrix(K), np.eye(M)) @ _T(K, M)
+           @ np.kron(np.eye(K), O.dft_matrix(M)) @ _L(K, M))
+    assert np.max(np.abs(lhs - rhs)) < 1e-13
+
+
+def test_dft8_factorisation():
+    """Eq. (DFT_8): [(H (x) I2) T^4_2 (I2 (x) H) L^4_2] (x) I2 T^8_2 (I4 (x) H) L^8_4."""
+    dft4 = np.kron(H2, np.eye(2)) @ _T(2, 2) @ np.kron(np.eye(2), H2) @ _L(2, 2)
+    assert np.max(np.abs(dft4 - O.dft_matrix(4))) < 1e-14
+    dft8 = np.kron(dft4, np.eye(2)) @ _T(4, 2) @ np.kron(np.eye(4), H2) @ _L(4, 2)
+    assert np.max(np.abs(dft8 - O.dft_matrix(8))) < 1e-14
+
+
+E1 = np.diag([1.0, 0.0])
+E2 = np.diag([0.0, 1.0])
+
+
+def _R(j):
+    return np.diag([1.0, np.exp(-2j * np.pi / 2 ** j)])
+
+
+def _gate_matrix(n, gate):
+    """Matrix of one oracle gate, column by column."""
+    N = 1 << n
+    G = np.empty((N, N), dtype=complex)
+    for j in range(N):
+        e = np.zeros(N, dtype=complex)
+        e[j] = 1.0
+        if gate[0] == "CR":
+            O.qft_oracle._apply_cr(e, n, gate[1], gate[2], gate[3])
+        elif gate[0] == "H":
+            O.qft_oracle._apply_h(e, n, gate[1])
+        G[:, j] = e
+    return G
+
+
+def test_two_level_twiddle_factors_are_the_circuit_phases():
+    """T~^4_2 and T~^8_2 (Sec. 2 worked examples) equal the CR gates of Fig. 1."""
+    I2 = np.eye(2)
+    T4 = np.kron(I2, E1) + np.kron(_R(2), E2)
+    T8 = ((np.kron(np.kron(I2, I2), E1) + np.kron(np.kron(_R(3), I2), E2))
+          @ (np.kron(np.kron(I2, E1), I2) + np.kron(np.kron(_R(2), E2), I2)))
+    # T~^8_2 = diag over (b2 b1 b0) of w_8^{b2 (2 b1 + b0)}
+    d = [np.exp(-2j * np.pi * ((i >> 2) & 1) * (i & 3) / 8) for i in range(8)]
+    assert np.max(np.abs(T8 - np.diag(d))) < 1e-15
+    # the target-2 controlled phases of the 3-qubit circuit
+    cr = _gate_matrix(3, ("CR", 1, 2, 2)) @ _gate_matrix(3, ("CR", 0, 2, 3))
+    assert np.max(np.abs(cr - T8)) < 1e-15
+    assert np.max(np.abs(_gate_matrix(2, ("CR", 0, 1, 2)) - T4)) < 1e-15
+    # 1-wire gate on q_j is I_{2^{n-1-j}} (x) U (x) I_{2^j}
+    h = _gate_matrix(3, ("H", 1))
+    assert np.max(np.abs(h - np.kron(np.kron(I2, H2 / math.sqrt(2)), I2))) < 1e-15
+
+
+def _dft_star(N):
+    """DFT*_N = (I_2 (x) DFT*_{N/2}) T~^N_2 (H (x) I_{N/2}), DFT*_2 = H."""
+    if N == 2:
+        return H2.astype(complex)
+    half = N // 2
+    tw = np.array([np.exp(-2j * np.pi * ((i // half) * (i % half)) / N) for i in range(N)])
+    return np.kron(np.eye(2), _dft_star(half)) @ np.diag(tw) @ np.kron(H2, np.eye(half))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6])
+def test_radix2_block_form(n):
+    """Radix-2 block form: the circuit without swaps is DFT*_N / sqrt(N), and
+    the product of L's is the bit reversal."""
+    N = 1 << n
+    Ub = O.qft_circuit_matrix(n, None, "bitrev")
+    assert np.max(np.abs(Ub * math.sqrt(N) - _dft_star(N))) < 1e-12
+    P = np.zeros((N, N))
+    for k in range(N):
+        P[k, O.bitrev_index(k, n)] = 1.0
+    assert np.max(np.abs(P @ _dft_star(N) - O.dft_matrix(N))) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# cutoff semantics
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [2, 5, 8])
+def test_large_or_negative_cutoff_is_exact(n):
+    x = I.gaussian(n, 7)
+    ref = O.qft_circuit(x, None)
+    for k in (n - 1, n, n + 5, -1, -7):
+        assert np.array_equal(O.qft_circuit(x, k), ref)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 6, 8])
+def test_cutoff_zero_is_walsh_hadamard_plus_bitreversal(n):
+    N = 1 << n
+    x = I.gaussian(n, 8)
+    wht = scipy.linalg.hadamard(N) @ x / math.sqrt(N)
+    assert O.rel_l2(O.qft_circuit(x, 0, "unitary", "natural"), wht[O.bitrev_perm(n)]) < TOL
+    assert O.rel_l2(O.qft_circuit(x, 0, "unitary", "bitrev"), wht) < TOL
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_closed_form_matches_circuit(n):
+    for k in list(range(0, n)) + [None]:
+        assert np.max(np.abs(O.aqft_matrix(n, k) - O.qft_circuit_matrix(n, k))) < 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 3, 8, 10])
+def test_fused_targets_match_circuit(n):
+    x = I.gaussian(n, 9)
+    for k in list(range(0, n)) + [None]:
+        for norm in O.NORMS:
+            for order in O.ORDERS:
+                a = O.qft_circuit(x, k, norm, order)
+                b = O.qft_fused_targets(x, k, norm, order)
+                assert O.rel_l2(b, a) < TOL
+
+
+def test_bins_helpers_match_full_transforms():
+    n = 12
+    x = I.gaussian(n, 10)
+    rng = np.random.default_rng(0)
+    bins = rng.choice(1 << n, 16, replace=False)
+    assert O.c_oracle_available(), "oracle C helper not built (run oracle/build_oracle.py)"
+    full = O.dft_naive(x)
+    assert O.rel_l2(O.dft_bins(x, bins), full[bins]) < TOL
+    for k in (0, 3, 6, None):
+        ref = O.qft_circuit(x, k)
+        assert O.rel_l2(O.aqft_bins(x, bins, k), ref[bins]) < TOL
+    small = I.gaussian(8, 11)
+    b8 = np.arange(256)
+    assert O.rel_l2(O.aqft_bins(small, b8, 2), O.qft_circuit(small, 2)) < TOL
+    assert O.rel_l2(O.dft_bins(small, b8, "none"), O.dft_naive(small, "none")) < TOL
+
+
+# --------------------------------------------------------------------------
+# AQFT error behaviour (Sec. 2 "Approximate QFT", Coppersmith-style bound)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [4, 6])
+def test_error_bound_and_frobenius_formula(n):
+    N = 1 << n
+    U = O.qft_circuit_matrix(n, None)
+    for k in range(0, n - 1):
+        D = U - O.qft_circuit_matrix(n, k)
+        assert np.linalg.norm(D, 2) <= O.aqft_error_bound(n, k) + 1e-12
+        fro = np.linalg.norm(D, "fro") / math.sqrt(N)
+        assert fro == pytest.approx(O.aqft_expected_relerr_gaussian(n, k), rel=1e-10)
+
+
+def test_aqft_error_shrinks_with_k():
+    for n in (8, 12, 16, 22, 24, 28, 30):
+        # the formula sums over 2^(n-1-k) terms: keep n-1-k <= 18 here
+        errs = [O.aqft_expected_relerr_gaussian(n, k) for k in range(max(3, n - 19), n - 1)]
+        assert all(b <= a for a, b in zip(errs, errs[1:]))
+        assert O.aqft_expected_relerr_gaussian(n, n - 1) == 0.0
+    # measured on seeded Gaussian inputs: strictly decreasing for k >= 4 and
+    # close to the expected value
+    n = 14
+    x = I.gaussian(n, 1003)
+    ref = O.qft_fused_targets(x, None)
+    prev = None
+    for k in range(4, 12):
+        e = O.rel_l2(O.qft_fused_targets(x, k), ref)
+        assert e == pytest.approx(O.aqft_expected_relerr_gaussian(n, k), rel=0.05)
+        if prev is not None:
+            assert e < prev
+        prev = e
+
+
+def test_single_tone_fidelity_equals_leakage():
+    """For an integer-bin tone the exact output is one spike, so 1-F equals
+    the top-bin leakage (the close tracking noted in Sec. 5)."""
+    n = 12
+    x = I.tone(n, 2)
+    ref = O.qft_fused_targets(x, None)
+    for k in (2, 4, 6, 8):
+        y = O.qft_fused_targets(x, k)
+        assert 1 - O.fidelity(y, ref) == pytest.approx(O.top_bin_leakage(y, ref), rel=1e-6, abs=1e-15)
+
+
+def test_metrics_definitions():
+    ref = np.array([3.0, 0.0, 4.0j, 0.0])
+    y = ref + np.array([0.0, 0.5, 0.0, 0.0])
+    assert O.rel_l2(y, ref) == pytest.approx(0.1)
+    assert O.max_err(y, ref) == pytest.approx(0.5 / (5.0 / 2.0))
+    assert O.fidelity(ref, ref) == pytest.approx(1.0)
+    assert O.top_bin_leakage(y, ref) == pytest.approx(1 - 16.0 / 25.25)
