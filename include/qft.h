@@ -1,0 +1,182 @@
+/*
+ * qft.h - C ABI of the MI355X (gfx950) QFT->FFT library (libqft.so).
+ *
+ * The library computes the discrete Fourier transform of a 2^n-element
+ * complex array by executing the gate schedule of the n-qubit quantum Fourier
+ * transform circuit (Hadamard butterflies, controlled-phase diagonals, final
+ * qubit-reversal swaps) on the array as a state vector, optionally truncated
+ * to the range-k approximate QFT.  The paper this follows is "Not Your Usual
+ * FFT: QFT->FFT via Classical Quantum-Circuit Simulation" (Markidis et al.).
+ *
+ * Conventions (paper Sec. 2 and Sec. 3):
+ *  - element i of the array is the amplitude of basis state |b_{n-1}...b_0>
+ *    with qubit q_j = bit j of i (Sec. 3 step 1; Sec. 2 one-wire gate on q_j
+ *    = I_{2^{n-1-j}} (x) U (x) I_{2^j});
+ *  - forward sign: y_k = s * sum_j x_j exp(-2 pi i j k / N) (Sec. 2,
+ *    w_N = exp(-2 pi i / N), R_k = diag(1, exp(-2 pi i / 2^k)));
+ *  - the scale s is chosen by `norm` (Sec. 3 steps 3 and 4);
+ *  - the cutoff keeps controlled phases whose control-target distance is
+ *    <= cutoff (Sec. 2 "Approximate QFT"); the paper's scale_in
+ *    normalisation (Sec. 3 step 1) is not applied: the map is linear, so the
+ *    result equals the paper's decoded output up to rounding.
+ *
+ * Memory: all data pointers are device pointers (hipMalloc'd or torch CUDA
+ * tensors) owned by the caller unless stated.  Arrays are interleaved
+ * (re, im) complex, contiguous, 2^n elements, complex64 (2 x float) or
+ * complex128 (2 x double), at least 16-byte aligned.  Transforms are in place.
+ *
+ * Streams: `qft_stream_t` is a hipStream_t passed as void* (NULL = the null
+ * stream).  Execute calls only enqueue work; they never synchronise the host.
+ *
+ * Errors: functions return QFT_OK (0) or a negative QFT_ERR_* code, or NULL
+ * for constructors; qft_last_error() returns the calling thread's last
+ * message.  No C++ exception crosses this interface.
+ */
+#ifndef QFT_MI355X_H
+#define QFT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qft_plan_s qft_plan_t;
+typedef void *qft_stream_t; /* hipStream_t */
+
+/* ---- norm: output scale (Sec. 3 steps 3-4) ------------------------------ */
+#define QFT_NORM_UNITARY 0 /* y = DFT_N x / sqrt(N)  (the unit-norm QFT U)   */
+#define QFT_NORM_NONE 1    /* y = DFT_N x            (unnormalised FFT)      */
+#define QFT_NORM_INV_N 2   /* y = DFT_N x / N        (1/N convention)        */
+
+/* ---- layout flags (OR them together) ------------------------------------ */
+#define QFT_C64 0x0            /* complex64 data, FP32 arithmetic             */
+#define QFT_C128 0x1           /* complex128 data, FP64 arithmetic            */
+#define QFT_ORDER_NATURAL 0x0  /* y[k] = bin k: final swaps applied (Fig. 1)  */
+#define QFT_ORDER_BITREV 0x2   /* y[rev_n(k)] = bin k: swaps left to the
+                                  caller as an index permutation (Sec. 3
+                                  step 2)                                     */
+#define QFT_SCHEDULE_FUSED 0x0 /* fused HBM passes (default)                  */
+#define QFT_SCHEDULE_GATES 0x4 /* one sweep per gate: H, controlled-R_m and
+                                  SWAP in circuit order (Fig. 1), unfused     */
+
+#define QFT_CUTOFF_EXACT (-1) /* any cutoff < 0 or >= n-1 is exact            */
+#define QFT_MAX_QUBITS 31
+#define QFT_MAX_PASSES 8
+
+/* ---- error codes --------------------------------------------------------- */
+#define QFT_OK 0
+#define QFT_ERR_INVALID (-1)     /* bad argument value                        */
+#define QFT_ERR_UNSUPPORTED (-2) /* valid but unsupported combination         */
+#define QFT_ERR_NOMEM (-3)       /* device allocation failed                  */
+#define QFT_ERR_HIP (-4)         /* HIP runtime or launch error               */
+#define QFT_ERR_POINTER (-5)     /* NULL or misaligned pointer                */
+#define QFT_ERR_BUSY (-6)        /* resource limit (admission, queue)         */
+
+/* Kernel configuration of the fused schedule.  Zero fields mean "default";
+ * a negative spec_log2 / rev_spec_log2 requests 0 spectator bits.
+ * tile_log2:   elements per workgroup tile (2^tile_log2), 1..15
+ * radix_log2:  qubits applied in registers between LDS exchanges, 1..5
+ * spec_log2:   contiguous low-order elements kept in each tile of the
+ *              high-order passes (coalescing width 2^spec_log2)
+ * rev_spec_log2: contiguous output elements per run in the final
+ *              bit-reversing pass (natural order only)                       */
+typedef struct qft_config {
+  int tile_log2;
+  int radix_log2;
+  int spec_log2;
+  int rev_spec_log2;
+} qft_config_t;
+
+/* Description of a plan.  Gate counts are those of the circuit before any
+ * fusion (the paper's aggregate 1- and 2-qubit counters, Sec. 3.1).          */
+typedef struct qft_plan_info {
+  int n;
+  int cutoff;          /* effective cutoff: n-1 for the exact transform      */
+  int norm;
+  int layout;
+  int num_passes;      /* kernel launches per execute (fused) or gate sweeps */
+  int pass_lo[QFT_MAX_PASSES];   /* lowest qubit applied by pass p           */
+  int pass_bits[QFT_MAX_PASSES]; /* qubits applied by pass p                 */
+  int pass_spec[QFT_MAX_PASSES]; /* spectator (coalescing) bits of pass p    */
+  int pass_reverse[QFT_MAX_PASSES]; /* pass p writes bit-reversed addresses  */
+  qft_config_t config;
+  long long gates_h, gates_cr, gates_swap;
+  size_t state_bytes;     /* 2^n * element size                              */
+  size_t workspace_bytes; /* plan-owned scratch (natural order, >1 pass)     */
+  size_t table_bytes;     /* plan-owned twiddle tables on the device         */
+  size_t hbm_bytes;       /* algorithmic HBM bytes per execute: 2 * state
+                             bytes per pass (read + write)                   */
+} qft_plan_info_t;
+
+/* ---- core ---------------------------------------------------------------- */
+
+/* Build a plan for 2^n-point transforms (host planning in FP64, then a
+ * one-time upload of its twiddle tables to the current device).
+ * n: 1..QFT_MAX_QUBITS.  cutoff: AQFT range k (see QFT_CUTOFF_EXACT).
+ * norm: QFT_NORM_*.  layout: dtype | order | schedule flags.
+ * Returns NULL on error (see qft_last_error).                               */
+qft_plan_t *qft_plan(int n, int cutoff, int norm, int layout);
+
+/* As qft_plan with an explicit kernel configuration (NULL = default).      */
+qft_plan_t *qft_plan_config(int n, int cutoff, int norm, int layout,
+                            const qft_config_t *config);
+
+/* Transform dev_ptr (2^n elements, in place) asynchronously on `stream`.
+ * Uses the plan's own workspace, so executes of one plan must be ordered on
+ * one stream.                                                              */
+int qft_execute(qft_plan_t *plan, void *dev_ptr, qft_stream_t stream);
+
+/* As qft_execute with a caller-owned workspace of info.workspace_bytes
+ * (may be NULL when that is 0), so one plan can run on several streams.    */
+int qft_execute_ws(qft_plan_t *plan, void *dev_ptr, void *workspace,
+                   qft_stream_t stream);
+
+/* Free the plan and its device memory (NULL-safe).  The caller must ensure
+ * no enqueued execute of the plan is still pending.                         */
+void qft_destroy(qft_plan_t *plan);
+
+/* Thread-local message describing the last error ("" if none).             */
+const char *qft_last_error(void);
+
+int qft_plan_info(const qft_plan_t *plan, qft_plan_info_t *out);
+
+/* Run only the host planner (no device use) and describe the plan that
+ * qft_plan_config would build.                                             */
+int qft_plan_describe(int n, int cutoff, int norm, int layout,
+                      const qft_config_t *config, qft_plan_info_t *out);
+
+/* ---- measurement --------------------------------------------------------- */
+
+/* When enabled, qft_execute records a HIP event pair around every kernel
+ * launch it enqueues and accumulates per-pass device times.                 */
+int qft_plan_set_timing(qft_plan_t *plan, int enable);
+/* Synchronises on the recorded events and returns the mean milliseconds per
+ * execute of each pass in ms[0..count) (count = min(max, num_passes)) and
+ * the number of timed executes; the accumulators are then cleared.          */
+int qft_plan_pass_times(qft_plan_t *plan, double *ms, int max, long long *execs);
+
+/* ---- batched uneven sizes (one persistent launch) ------------------------ */
+
+/* Transform count arrays, dev_ptrs[i] with plans[i], in one persistent
+ * kernel launch.  Work items (transform, pass, tile) are ordered so that a
+ * transform's pass p+1 waits only on its own pass p.  The launch for a given
+ * (plans, dev_ptrs) set is captured once into a HIP graph and replayed.
+ * Plans must be fused-schedule plans; NATURAL plans with more than one pass
+ * need their own workspace (they use it).                                   */
+int qft_execute_batch(qft_plan_t *const *plans, void *const *dev_ptrs,
+                      int count, qft_stream_t stream);
+
+/* ---- device input generation (Philox-4x32-10, Salmon et al. 2011) -------- */
+#define QFT_RNG_GAUSSIAN 0 /* re, im ~ N(0, 1) (Box-Muller in FP64)          */
+#define QFT_RNG_UNIFORM 1  /* re, im ~ U[-1, 1)                              */
+/* Fill dev_ptr (2^n elements, layout dtype bit) with amplitude i drawn from
+ * Philox(counter = (i, stream_id), key = seed).                              */
+int qft_fill_random(void *dev_ptr, int n, int layout, int dist, uint64_t seed,
+                    uint64_t stream_id, qft_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QFT_MI355X_H */

@@ -1,0 +1,269 @@
+// C ABI of libqft.so: plan / execute / destroy, plan description, per-pass
+// timing and the device input generator.  See include/qft.h.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qft.h"
+#include "qft_kernels.h"
+#include "qft_planner.h"
+#include "qft_runtime.h"
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+namespace qft {
+
+int set_error(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_error(hipError_t e, const char *what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? QFT_ERR_NOMEM : QFT_ERR_HIP;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+// Enqueue the kernels of a plan.  `ws` may be NULL when the plan needs none.
+int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s) {
+  const HostPlan &hp = p->hp;
+  hipError_t e = hipSuccess;
+  size_t li = 0;
+  auto mark = [&](size_t i) {
+    if (p->timing) hipEventRecord(p->timer.slot(i), s);
+  };
+  if (p->timing) p->timer.begin(p->num_launches());
+  if (hp.schedule == Schedule::Fused) {
+    for (const PassLaunch &L : p->launches) {
+      mark(li);
+      const void *in = L.in_ws ? ws : dev;
+      void *out = L.out_ws ? ws : dev;
+      e = launch_fused_pass(L, hp.c128, in, out, s);
+      if (e != hipSuccess) return hip_error(e, "fused pass launch");
+      ++li;
+    }
+  } else {
+    for (const Gate &g : hp.gates) {
+      mark(li);
+      if (g.kind == 0) e = launch_h(dev, hp.n, g.a, hp.c128, s);
+      else if (g.kind == 1) e = launch_cphase(dev, hp.n, g.a, g.b, g.re, g.im, hp.c128, s);
+      else e = launch_swap(dev, hp.n, g.a, g.b, hp.c128, s);
+      if (e != hipSuccess) return hip_error(e, "gate sweep launch");
+      ++li;
+    }
+    if (hp.gate_norm != 1.0) {
+      mark(li);
+      e = launch_scale(dev, hp.n, hp.gate_norm, hp.c128, s);
+      if (e != hipSuccess) return hip_error(e, "scale launch");
+      ++li;
+    }
+  }
+  mark(li);
+  if (p->timing) p->timer.end();
+  return QFT_OK;
+}
+
+// ---- per-launch timing ---------------------------------------------------
+
+hipEvent_t LaunchTimer::slot(size_t i) { return events[cur_base + i]; }
+
+void LaunchTimer::begin(int launches) {
+  nl = launches;
+  const size_t need = (size_t)(execs + 1) * (size_t)(launches + 1);
+  while (events.size() < need) {
+    hipEvent_t ev;
+    hipEventCreate(&ev);
+    events.push_back(ev);
+  }
+  cur_base = (size_t)execs * (size_t)(launches + 1);
+}
+
+void LaunchTimer::end() { ++execs; }
+
+void LaunchTimer::release() {
+  for (hipEvent_t ev : events) hipEventDestroy(ev);
+  events.clear();
+  execs = 0;
+}
+
+}  // namespace qft
+
+using namespace qft;
+
+static qft_plan_t *make_plan(int n, int cutoff, int norm, int layout, const qft_config_t *cfg) {
+  clear_error();
+  qft_plan_t *p = new (std::nothrow) qft_plan_s();
+  if (!p) {
+    set_error(QFT_ERR_NOMEM, "host allocation failed");
+    return nullptr;
+  }
+  std::string err;
+  int rc = build_host_plan(n, cutoff, norm, layout, cfg, p->hp, err);
+  if (rc != QFT_OK) {
+    set_error(rc, err);
+    delete p;
+    return nullptr;
+  }
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    hip_error(e, "hipGetDevice");
+    delete p;
+    return nullptr;
+  }
+  HostPlan &hp = p->hp;
+  if (!hp.tables.empty()) {
+    e = hipMalloc(&p->d_tables, hp.tables.size());
+    if (e != hipSuccess) {
+      hip_error(e, "table allocation");
+      delete p;
+      return nullptr;
+    }
+    e = hipMemcpy(p->d_tables, hp.tables.data(), hp.tables.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      hip_error(e, "table upload");
+      hipFree(p->d_tables);
+      delete p;
+      return nullptr;
+    }
+  }
+  if (hp.ws_bytes) {
+    e = hipMalloc(&p->d_ws, hp.ws_bytes);
+    if (e != hipSuccess) {
+      hip_error(e, "workspace allocation");
+      if (p->d_tables) hipFree(p->d_tables);
+      delete p;
+      return nullptr;
+    }
+  }
+  p->launches = hp.passes;
+  for (PassLaunch &L : p->launches) {
+    unsigned char *t = (unsigned char *)p->d_tables;
+    L.d.tw_int = t + hp.off_int;
+    L.d.tw_lo = t + hp.off_lo;
+    L.d.tw_hi = t + hp.off_hi;
+  }
+  return p;
+}
+
+extern "C" {
+
+qft_plan_t *qft_plan(int n, int cutoff, int norm, int layout) {
+  return make_plan(n, cutoff, norm, layout, nullptr);
+}
+
+qft_plan_t *qft_plan_config(int n, int cutoff, int norm, int layout, const qft_config_t *config) {
+  return make_plan(n, cutoff, norm, layout, config);
+}
+
+int qft_execute_ws(qft_plan_t *plan, void *dev_ptr, void *workspace, qft_stream_t stream) {
+  clear_error();
+  if (!plan) return set_error(QFT_ERR_INVALID, "plan is NULL");
+  if (!dev_ptr) return set_error(QFT_ERR_POINTER, "data pointer is NULL");
+  if ((uintptr_t)dev_ptr % plan->hp.elem_bytes)
+    return set_error(QFT_ERR_POINTER, "data pointer is not aligned to the element size");
+  if (plan->hp.ws_bytes && !workspace)
+    return set_error(QFT_ERR_POINTER, "this plan needs a workspace");
+  if (workspace && (uintptr_t)workspace % plan->hp.elem_bytes)
+    return set_error(QFT_ERR_POINTER, "workspace pointer is not aligned to the element size");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  if (dev != plan->device)
+    return set_error(QFT_ERR_INVALID, "the current device is not the plan's device");
+  return enqueue_plan(plan, dev_ptr, workspace, (hipStream_t)stream);
+}
+
+int qft_execute(qft_plan_t *plan, void *dev_ptr, qft_stream_t stream) {
+  if (!plan) {
+    clear_error();
+    return set_error(QFT_ERR_INVALID, "plan is NULL");
+  }
+  return qft_execute_ws(plan, dev_ptr, plan->d_ws, stream);
+}
+
+void qft_destroy(qft_plan_t *plan) {
+  if (!plan) return;
+  plan->timer.release();
+  if (plan->d_tables) hipFree(plan->d_tables);
+  if (plan->d_ws) hipFree(plan->d_ws);
+  delete plan;
+}
+
+const char *qft_last_error(void) { return g_last_error.c_str(); }
+
+int qft_plan_info(const qft_plan_t *plan, qft_plan_info_t *out) {
+  clear_error();
+  if (!plan || !out) return set_error(QFT_ERR_INVALID, "NULL argument");
+  describe_plan(plan->hp, out);
+  return QFT_OK;
+}
+
+int qft_plan_describe(int n, int cutoff, int norm, int layout, const qft_config_t *config,
+                      qft_plan_info_t *out) {
+  clear_error();
+  if (!out) return set_error(QFT_ERR_INVALID, "NULL argument");
+  HostPlan hp;
+  std::string err;
+  int rc = build_host_plan(n, cutoff, norm, layout, config, hp, err);
+  if (rc != QFT_OK) return set_error(rc, err);
+  describe_plan(hp, out);
+  return QFT_OK;
+}
+
+int qft_plan_set_timing(qft_plan_t *plan, int enable) {
+  clear_error();
+  if (!plan) return set_error(QFT_ERR_INVALID, "plan is NULL");
+  plan->timing = enable != 0;
+  return QFT_OK;
+}
+
+int qft_plan_pass_times(qft_plan_t *plan, double *ms, int max, long long *execs) {
+  clear_error();
+  if (!plan) return set_error(QFT_ERR_INVALID, "plan is NULL");
+  LaunchTimer &t = plan->timer;
+  const int nl = plan->num_launches();
+  std::vector<double> acc(nl, 0.0);
+  if (t.execs > 0) {
+    hipError_t e = hipEventSynchronize(t.events[(size_t)t.execs * (nl + 1) - 1]);
+    if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
+    for (long long x = 0; x < t.execs; ++x) {
+      for (int i = 0; i < nl; ++i) {
+        float f = 0.f;
+        e = hipEventElapsedTime(&f, t.events[(size_t)x * (nl + 1) + i],
+                                t.events[(size_t)x * (nl + 1) + i + 1]);
+        if (e != hipSuccess) return hip_error(e, "hipEventElapsedTime");
+        acc[i] += f;
+      }
+    }
+  }
+  if (ms)
+    for (int i = 0; i < nl && i < max; ++i) ms[i] = t.execs ? acc[i] / (double)t.execs : 0.0;
+  if (execs) *execs = t.execs;
+  t.execs = 0;
+  return QFT_OK;
+}
+
+int qft_fill_random(void *dev_ptr, int n, int layout, int dist, uint64_t seed, uint64_t stream_id,
+                    qft_stream_t stream) {
+  clear_error();
+  if (n < 1 || n > QFT_MAX_QUBITS) return set_error(QFT_ERR_INVALID, "n out of range");
+  if (dist != QFT_RNG_GAUSSIAN && dist != QFT_RNG_UNIFORM)
+    return set_error(QFT_ERR_INVALID, "unknown distribution");
+  if (!dev_ptr) return set_error(QFT_ERR_POINTER, "data pointer is NULL");
+  const bool c128 = (layout & QFT_C128) != 0;
+  if ((uintptr_t)dev_ptr % (c128 ? 16 : 8))
+    return set_error(QFT_ERR_POINTER, "data pointer is not aligned to the element size");
+  hipError_t e = launch_fill_random(dev_ptr, n, c128, dist, seed, stream_id, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_error(e, "fill_random launch");
+  return QFT_OK;
+}
+
+}  // extern "C"

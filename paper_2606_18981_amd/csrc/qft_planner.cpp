@@ -1,0 +1,463 @@
+// Host planner for the QFT->FFT schedule (pure C++, FP64 tables).
+//
+// Gate list (Fig. 1; cutoff semantics of Sec. 2 "Approximate QFT"):
+//   for t = n-1 .. 0: H(t), then controlled-R_{d+1}(control t-d, target t)
+//   for every distance d = 1 .. t with d <= k; finally swaps q_a <-> q_{n-1-a}.
+//
+// Fused schedule.  The targets are split, most significant first, into HBM
+// passes of m consecutive qubits.  Within a pass every controlled phase whose
+// control lies below the pass depends only on the target bit and on index
+// bits no butterfly of the pass touches, so all of them commute to the end of
+// the pass and collapse into one diagonal per element (Sec. 2 gate fusion:
+// commuting diagonals collapse to one diagonal).  For the exact transform
+// that diagonal is w_{2^{lo+m}}^{v rev_m(p)} (v = index bits below the pass,
+// p = pass bits after the pass); for the AQFT each target's contribution
+// keeps only the control bits within distance k.  The controlled phases with
+// both qubits inside the pass become the twiddles of a 2^m-point
+// decimation-in-frequency transform (Sec. 2 "From FFT to QFT": the diagonal
+// T~ between two butterfly banks is the product of the two-level controlled
+// phases).  The final swaps become the output addressing of the last pass
+// (Sec. 3 step 2: the permutation is an index mapping, not a gate).
+#include "qft_planner.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+namespace qft {
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct PassGeom {
+  int lo = 0;
+  int m = 0;
+  std::vector<int> spec_g;  // global positions of the spectator bits
+  bool reverse = false;
+};
+
+void put_cplx(std::vector<unsigned char> &buf, size_t off, size_t idx, bool c128,
+              double re, double im) {
+  if (c128) {
+    double v[2] = {re, im};
+    memcpy(buf.data() + off + idx * 16, v, 16);
+  } else {
+    float v[2] = {(float)re, (float)im};
+    memcpy(buf.data() + off + idx * 8, v, 8);
+  }
+}
+
+int check_config(const qft_config_t &c, std::string &err) {
+  if (c.radix_log2 < 1 || c.radix_log2 > kMaxRadix) {
+    err = "radix_log2 must be in [1, 5]";
+    return QFT_ERR_INVALID;
+  }
+  if (c.tile_log2 < c.radix_log2 || c.tile_log2 > kMaxTile) {
+    err = "tile_log2 must be in [radix_log2, 15]";
+    return QFT_ERR_INVALID;
+  }
+  if (c.spec_log2 < 0 || c.spec_log2 >= c.tile_log2 || c.rev_spec_log2 < 0 ||
+      c.rev_spec_log2 >= c.tile_log2) {
+    err = "spec_log2 and rev_spec_log2 must be in [0, tile_log2)";
+    return QFT_ERR_INVALID;
+  }
+  if ((1 << (c.tile_log2 - c.radix_log2)) > (c.radix_log2 >= 5 ? 512 : 1024)) {
+    err = "too many threads per workgroup (2^(tile_log2 - radix_log2) must be <= 1024, "
+          "or <= 512 for radix_log2 = 5)";
+    return QFT_ERR_INVALID;
+  }
+  return QFT_OK;
+}
+
+// Register/thread maps of one pass.  See qft_internal.h for the meaning of
+// the e-positions.  Groups apply the pass bits top-down, r at a time; the
+// last (lowest) group may apply fewer and then also holds already-applied
+// bits (or spectators) in its spare registers, which do not enter the
+// twiddles of the lower targets.
+void build_groups(PassLaunch &L, const PassGeom &g, int r, int n) {
+  PassDesc &d = L.d;
+  const int nspec = (int)g.spec_g.size();
+  const int m = g.m;
+  const int T = nspec + m;
+  std::vector<int> gpos(T), outpos(T);
+  for (int q = 0; q < T; ++q) {
+    gpos[q] = q < nspec ? g.spec_g[q] : g.lo + (q - nspec);
+    outpos[q] = g.reverse ? n - 1 - gpos[q] : gpos[q];
+  }
+  const int ng = (m + r - 1) / r;
+  std::vector<GroupMap> groups;
+  std::vector<std::vector<int>> thr_orders;
+  for (int i = 0; i < ng; ++i) {
+    const int top = m - i * r;
+    const int bot = std::max(0, top - r);
+    const int nst = top - bot;
+    std::vector<int> regs;
+    for (int q = 0; q < nst; ++q) regs.push_back(nspec + bot + q);
+    if (nst < r) {
+      // spare registers: applied pass bits above, then spectators
+      std::vector<int> cand;
+      for (int q = nspec + nst; q < nspec + m; ++q) cand.push_back(q);
+      for (int q = 0; q < nspec; ++q) cand.push_back(q);
+      for (int q : cand) {
+        if ((int)regs.size() == r) break;
+        if (std::find(regs.begin(), regs.end(), q) == regs.end()) regs.push_back(q);
+      }
+    }
+    std::vector<int> thr;
+    for (int q = 0; q < T; ++q)
+      if (std::find(regs.begin(), regs.end(), q) == regs.end()) thr.push_back(q);
+    if (i == 0) {
+      std::stable_sort(thr.begin(), thr.end(), [&](int a, int b) { return gpos[a] < gpos[b]; });
+    } else if (i == ng - 1) {
+      std::stable_sort(thr.begin(), thr.end(), [&](int a, int b) { return outpos[a] < outpos[b]; });
+    }
+    GroupMap gm;
+    memset(&gm, 0, sizeof(gm));
+    for (int q = 0; q < r; ++q) gm.reg_pos[q] = (uint8_t)regs[q];
+    for (size_t b = 0; b < thr.size(); ++b) gm.thr_pos[b] = (uint8_t)thr[b];
+    gm.jbase = (int8_t)bot;
+    gm.nst = (int8_t)nst;
+    groups.push_back(gm);
+    thr_orders.push_back(thr);
+  }
+  // A single group loads in input order; if the output order differs, add an
+  // exchange-only group that stores in output order.
+  if (ng == 1) {
+    std::vector<int> thr = thr_orders[0];
+    std::vector<int> by_out = thr;
+    std::stable_sort(by_out.begin(), by_out.end(), [&](int a, int b) { return outpos[a] < outpos[b]; });
+    if (by_out != thr) {
+      GroupMap gm = groups[0];
+      for (size_t b = 0; b < by_out.size(); ++b) gm.thr_pos[b] = (uint8_t)by_out[b];
+      gm.nst = 0;
+      gm.jbase = 0;
+      groups.push_back(gm);
+    }
+  }
+  d.ngroups = (uint8_t)groups.size();
+  for (size_t i = 0; i < groups.size(); ++i) d.grp[i] = groups[i];
+  for (int q = 0; q < T; ++q) d.gpos[q] = (uint8_t)gpos[q];
+  const GroupMap &g0 = groups.front();
+  const GroupMap &gl = groups.back();
+  for (int b = 0; b < T - r; ++b) {
+    d.ld_thr_g[b] = (uint8_t)gpos[g0.thr_pos[b]];
+    d.st_thr_g[b] = (uint8_t)outpos[gl.thr_pos[b]];
+  }
+  for (int q = 0; q < r; ++q) {
+    d.ld_reg_g[q] = (uint8_t)gpos[g0.reg_pos[q]];
+    d.st_reg_g[q] = (uint8_t)outpos[gl.reg_pos[q]];
+  }
+}
+
+int plan_fused(HostPlan &p, std::string &err) {
+  const int n = p.n;
+  const qft_config_t &c = p.cfg;
+  int rc = check_config(c, err);
+  if (rc) return rc;
+  const int T = c.tile_log2;
+
+  // ---- pass partition --------------------------------------------------
+  std::vector<PassGeom> geo;
+  if (n <= T) {
+    PassGeom g;
+    g.lo = 0;
+    g.m = n;
+    g.reverse = !p.bitrev;
+    geo.push_back(g);
+  } else {
+    const int b_eff = p.bitrev ? 0 : c.rev_spec_log2;
+    const int amax = T - b_eff;
+    const int hmax = T - c.spec_log2;
+    int P = 1;
+    while (amax + (P - 1) * hmax < n) ++P;
+    if (P > kMaxPasses) {
+      err = "too many passes for this tile configuration";
+      return QFT_ERR_UNSUPPORTED;
+    }
+    const int a = std::min(amax, n - (P - 1));
+    const int H = n - a;
+    const int Ph = P - 1;
+    std::vector<int> hs(Ph, H / Ph);
+    for (int i = 0; i < H % Ph; ++i) hs[i]++;
+    int top = n;
+    for (int i = 0; i < Ph; ++i) {
+      PassGeom g;
+      g.m = hs[i];
+      g.lo = top - g.m;
+      const int nspec = std::min(T - g.m, g.lo);
+      for (int q = 0; q < nspec; ++q) g.spec_g.push_back(q);
+      geo.push_back(g);
+      top = g.lo;
+    }
+    PassGeom g;
+    g.lo = 0;
+    g.m = a;
+    g.reverse = !p.bitrev;
+    const int nspec = std::min(T - a, n - a);
+    if (p.bitrev) {
+      for (int q = 0; q < nspec; ++q) g.spec_g.push_back(a + q);
+    } else {
+      for (int q = 0; q < nspec; ++q) g.spec_g.push_back(n - nspec + q);
+    }
+    geo.push_back(g);
+  }
+
+  // ---- tables ------------------------------------------------------------
+  int MI = 1;
+  bool need_ext = false;
+  for (const PassGeom &g : geo) {
+    MI = std::max(MI, g.m);
+    if (g.lo > 0) need_ext = true;
+  }
+  MI = std::max(MI, std::min(c.radix_log2, n));
+  p.MI = MI;
+  p.need_ext = need_ext;
+  p.L = need_ext ? (n + 1) / 2 : 0;
+  const size_t es = p.elem_bytes;
+  const size_t n_int = (size_t)1 << (MI - 1);
+  const size_t n_lo = need_ext ? ((size_t)1 << p.L) : 0;
+  const size_t n_hi = need_ext ? ((size_t)1 << (n - p.L)) : 0;
+  p.off_int = 0;
+  p.off_lo = align_up(p.off_int + n_int * es, 256);
+  p.off_hi = align_up(p.off_lo + n_lo * es, 256);
+  p.tables.assign(align_up(p.off_hi + n_hi * es, 256), 0);
+  for (size_t y = 0; y < n_int; ++y) {
+    double re, im;
+    omega_pow2(MI, y, &re, &im);
+    put_cplx(p.tables, p.off_int, y, p.c128, re, im);
+  }
+  for (size_t x = 0; x < n_lo; ++x) {
+    double re, im;
+    omega_pow2(n, x, &re, &im);
+    put_cplx(p.tables, p.off_lo, x, p.c128, re, im);
+  }
+  for (size_t x = 0; x < n_hi; ++x) {
+    double re, im;
+    omega_pow2(n, (uint64_t)x << p.L, &re, &im);
+    put_cplx(p.tables, p.off_hi, x, p.c128, re, im);
+  }
+
+  // ---- output scale: unit-norm butterflies folded per pass ---------------
+  // total factor F = 2^{-n/2} * norm factor; passes other than the last get
+  // the exact power of two 2^{-floor(m/2)}, the last gets the remainder.
+  double F;
+  if (p.norm == QFT_NORM_UNITARY) F = pow(2.0, -0.5 * n);
+  else if (p.norm == QFT_NORM_NONE) F = 1.0;
+  else F = pow(2.0, -1.0 * n);
+  std::vector<double> scales(geo.size());
+  double used = 1.0;
+  for (size_t i = 0; i + 1 < geo.size(); ++i) {
+    scales[i] = ldexp(1.0, -(geo[i].m / 2));
+    used *= scales[i];
+  }
+  scales.back() = F / used;
+
+  // ---- launches ------------------------------------------------------------
+  const bool natural_multi = !p.bitrev && geo.size() > 1;
+  p.ws_bytes = natural_multi ? p.state_bytes : 0;
+  for (size_t i = 0; i < geo.size(); ++i) {
+    const PassGeom &g = geo[i];
+    PassLaunch L;
+    memset(&L, 0, sizeof(L));
+    PassDesc &d = L.d;
+    const int Te = (int)g.spec_g.size() + g.m;
+    const int r = std::min(c.radix_log2, Te);
+    d.n = (uint8_t)n;
+    d.T = (uint8_t)Te;
+    d.r = (uint8_t)r;
+    d.m = (uint8_t)g.m;
+    d.pbase = (uint8_t)g.spec_g.size();
+    d.lo = (uint8_t)g.lo;
+    d.reverse = g.reverse ? 1 : 0;
+    d.ext_tw = g.lo > 0 ? 1 : 0;
+    d.aqft = p.keff < n - 1 ? 1 : 0;
+    d.k = (int8_t)p.keff;
+    d.MI = (uint8_t)MI;
+    d.L = (uint8_t)p.L;
+    build_groups(L, g, r, n);
+    // non-tile bits, ascending
+    std::vector<int> in_tile(n, 0);
+    for (int q = 0; q < Te; ++q) in_tile[d.gpos[q]] = 1;
+    int nf = 0;
+    for (int b = 0; b < n; ++b)
+      if (!in_tile[b]) d.free_pos[nf++] = (uint8_t)b;
+    d.nfree = (uint8_t)nf;
+    d.ntiles = 1u << nf;
+    d.xcd_remap = (d.ntiles >= 8) ? 1 : 0;
+    d.scale = scales[i];
+    L.threads = 1 << (Te - r);
+    L.lds_bytes = d.ngroups > 1 ? (int)(((size_t)1 << Te) * es) : 0;
+    L.grid = d.ntiles;
+    if (natural_multi) {
+      L.in_ws = i == 0 ? 0 : 1;
+      L.out_ws = i + 1 == geo.size() ? 0 : 1;
+    }
+    p.passes.push_back(L);
+  }
+  return QFT_OK;
+}
+
+void plan_gates(HostPlan &p) {
+  const int n = p.n;
+  for (int t = n - 1; t >= 0; --t) {
+    Gate h{0, t, 0, 0, 0.0, 0.0};
+    p.gates.push_back(h);
+    for (int d = 1; d <= t; ++d) {
+      if (d > p.keff) break;
+      Gate g{1, t - d, t, d + 1, 0.0, 0.0};
+      omega_pow2(d + 1, 1, &g.re, &g.im);  // R_{d+1}: exp(-2 pi i / 2^{d+1})
+      p.gates.push_back(g);
+    }
+  }
+  if (!p.bitrev)
+    for (int a = 0; a < n / 2; ++a) p.gates.push_back(Gate{2, a, n - 1 - a, 0, 0.0, 0.0});
+  if (p.norm == QFT_NORM_UNITARY) p.gate_norm = 1.0;
+  else if (p.norm == QFT_NORM_NONE) p.gate_norm = pow(2.0, 0.5 * n);
+  else p.gate_norm = pow(2.0, -0.5 * n);
+}
+
+}  // namespace
+
+qft_config_t default_config(bool c128) {
+  qft_config_t c;
+  if (c128) {
+    c.tile_log2 = 12;
+    c.radix_log2 = 3;
+    c.spec_log2 = 2;
+    c.rev_spec_log2 = 2;
+  } else {
+    c.tile_log2 = 13;
+    c.radix_log2 = 4;
+    c.spec_log2 = 3;
+    c.rev_spec_log2 = 3;
+  }
+  return c;
+}
+
+void omega_pow2(int logN, uint64_t m, double *re, double *im) {
+  if (logN <= 0) {
+    *re = 1.0;
+    *im = 0.0;
+    return;
+  }
+  const uint64_t N = 1ULL << logN;
+  m &= N - 1;
+  // m = q N/4 + r with 0 <= r < N/4; w_N^m = (-i)^q w_N^r
+  int q;
+  uint64_t r;
+  if (logN >= 2) {
+    q = (int)(m >> (logN - 2));
+    r = m & ((N >> 2) - 1);
+  } else {
+    q = (int)(2 * m);  // N = 2: w_2 = -1 = (-i)^2
+    r = 0;
+  }
+  const long double twopi = 6.283185307179586476925286766559L;
+  long double cs, sn;  // cos and sin of 2 pi r / N, first octant reduced
+  if (logN >= 3 && r > (N >> 3)) {
+    const long double a = twopi * (long double)((N >> 2) - r) / (long double)N;
+    cs = sinl(a);
+    sn = cosl(a);
+  } else {
+    const long double a = twopi * (long double)r / (long double)N;
+    cs = cosl(a);
+    sn = sinl(a);
+  }
+  long double zr = cs, zi = -sn;
+  for (int i = 0; i < q; ++i) {  // multiply by -i
+    const long double t = zr;
+    zr = zi;
+    zi = -t;
+  }
+  *re = (double)zr;
+  *im = (double)zi;
+}
+
+size_t HostPlan::hbm_bytes() const {
+  if (schedule == Schedule::Fused) return 2 * state_bytes * passes.size();
+  size_t b = 0;
+  for (const Gate &g : gates) {
+    if (g.kind == 0) b += 2 * state_bytes;      // every pair read and written
+    else if (g.kind == 1) b += state_bytes / 2; // quarter of the amplitudes
+    else b += state_bytes;                      // half of the amplitudes move
+  }
+  if (gate_norm != 1.0) b += 2 * state_bytes;
+  return b;
+}
+
+int build_host_plan(int n, int cutoff, int norm, int layout, const qft_config_t *cfg,
+                    HostPlan &p, std::string &err) {
+  if (n < 1 || n > QFT_MAX_QUBITS) {
+    err = "n must be in [1, " + std::to_string(QFT_MAX_QUBITS) + "]";
+    return QFT_ERR_INVALID;
+  }
+  if (norm != QFT_NORM_UNITARY && norm != QFT_NORM_NONE && norm != QFT_NORM_INV_N) {
+    err = "norm must be QFT_NORM_UNITARY, QFT_NORM_NONE or QFT_NORM_INV_N";
+    return QFT_ERR_INVALID;
+  }
+  if (layout & ~0x7) {
+    err = "unknown layout flag bits";
+    return QFT_ERR_INVALID;
+  }
+  p = HostPlan();
+  p.n = n;
+  p.keff = (cutoff < 0 || cutoff >= n - 1) ? n - 1 : cutoff;
+  p.norm = norm;
+  p.layout = layout;
+  p.c128 = (layout & QFT_C128) != 0;
+  p.bitrev = (layout & QFT_ORDER_BITREV) != 0;
+  p.schedule = (layout & QFT_SCHEDULE_GATES) ? Schedule::Gates : Schedule::Fused;
+  p.elem_bytes = p.c128 ? 16 : 8;
+  p.state_bytes = p.elem_bytes << n;
+  p.gates_h = n;
+  p.gates_cr = (long long)p.keff * n - (long long)p.keff * (p.keff + 1) / 2;
+  p.gates_swap = n / 2;
+  qft_config_t def = default_config(p.c128);
+  qft_config_t c = def;
+  if (cfg) {
+    if (cfg->tile_log2) c.tile_log2 = cfg->tile_log2;
+    if (cfg->radix_log2) c.radix_log2 = cfg->radix_log2;
+    if (cfg->spec_log2) c.spec_log2 = cfg->spec_log2 < 0 ? 0 : cfg->spec_log2;
+    if (cfg->rev_spec_log2) c.rev_spec_log2 = cfg->rev_spec_log2 < 0 ? 0 : cfg->rev_spec_log2;
+    c.spec_log2 = std::min(c.spec_log2, c.tile_log2 - 1);
+    c.rev_spec_log2 = std::min(c.rev_spec_log2, c.tile_log2 - 1);
+  }
+  p.cfg = c;
+  if (p.schedule == Schedule::Gates) {
+    plan_gates(p);
+    return QFT_OK;
+  }
+  return plan_fused(p, err);
+}
+
+void describe_plan(const HostPlan &p, qft_plan_info_t *o) {
+  memset(o, 0, sizeof(*o));
+  o->n = p.n;
+  o->cutoff = p.keff;
+  o->norm = p.norm;
+  o->layout = p.layout;
+  o->config = p.cfg;
+  o->gates_h = p.gates_h;
+  o->gates_cr = p.gates_cr;
+  o->gates_swap = p.bitrev ? 0 : p.gates_swap;
+  o->state_bytes = p.state_bytes;
+  o->workspace_bytes = p.ws_bytes;
+  o->table_bytes = p.tables.size();
+  o->hbm_bytes = p.hbm_bytes();
+  if (p.schedule == Schedule::Fused) {
+    o->num_passes = (int)p.passes.size();
+    for (size_t i = 0; i < p.passes.size() && i < QFT_MAX_PASSES; ++i) {
+      const PassDesc &d = p.passes[i].d;
+      o->pass_lo[i] = d.lo;
+      o->pass_bits[i] = d.m;
+      o->pass_spec[i] = d.pbase;
+      o->pass_reverse[i] = d.reverse;
+    }
+  } else {
+    o->num_passes = (int)p.gates.size() + (p.gate_norm != 1.0 ? 1 : 0);
+  }
+}
+
+}  // namespace qft

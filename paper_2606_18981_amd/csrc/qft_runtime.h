@@ -1,0 +1,48 @@
+// Runtime-side plan object and helpers shared by the C ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/qft.h"
+#include "qft_internal.h"
+#include "qft_planner.h"
+
+namespace qft {
+
+// Event pairs around every launch of timed executes.
+struct LaunchTimer {
+  std::vector<hipEvent_t> events;
+  long long execs = 0;
+  size_t cur_base = 0;
+  int nl = 0;
+  hipEvent_t slot(size_t i);
+  void begin(int launches);
+  void end();
+  void release();
+};
+
+int set_error(int code, const std::string &msg);
+int hip_error(hipError_t e, const char *what);
+void clear_error();
+
+}  // namespace qft
+
+struct qft_plan_s {
+  qft::HostPlan hp;
+  int device = 0;
+  void *d_tables = nullptr;
+  void *d_ws = nullptr;
+  std::vector<qft::PassLaunch> launches;  // table pointers resolved
+  bool timing = false;
+  qft::LaunchTimer timer;
+  int num_launches() const {
+    if (hp.schedule == qft::Schedule::Fused) return (int)launches.size();
+    return (int)hp.gates.size() + (hp.gate_norm != 1.0 ? 1 : 0);
+  }
+};
+
+namespace qft {
+int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s);
+}

@@ -1,0 +1,272 @@
+"""ctypes binding of libqft.so (the C ABI in include/qft.h).
+
+Argument marshalling only: every step of the transform runs in the library's
+HIP kernels.  PyTorch is used for device memory and streams.  If the shared
+library is missing this module raises at import time; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqft.so")
+
+QFT_NORM_UNITARY = 0
+QFT_NORM_NONE = 1
+QFT_NORM_INV_N = 2
+QFT_C64 = 0x0
+QFT_C128 = 0x1
+QFT_ORDER_NATURAL = 0x0
+QFT_ORDER_BITREV = 0x2
+QFT_SCHEDULE_FUSED = 0x0
+QFT_SCHEDULE_GATES = 0x4
+QFT_CUTOFF_EXACT = -1
+QFT_MAX_PASSES = 8
+QFT_RNG_GAUSSIAN = 0
+QFT_RNG_UNIFORM = 1
+
+QFT_OK = 0
+QFT_ERR_INVALID = -1
+QFT_ERR_UNSUPPORTED = -2
+QFT_ERR_NOMEM = -3
+QFT_ERR_HIP = -4
+QFT_ERR_POINTER = -5
+QFT_ERR_BUSY = -6
+
+NORMS = {"unitary": QFT_NORM_UNITARY, "none": QFT_NORM_NONE, "inv_n": QFT_NORM_INV_N}
+
+
+class QftError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libqft error {code}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("tile_log2", ctypes.c_int), ("radix_log2", ctypes.c_int),
+                ("spec_log2", ctypes.c_int), ("rev_spec_log2", ctypes.c_int)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int), ("cutoff", ctypes.c_int), ("norm", ctypes.c_int),
+        ("layout", ctypes.c_int), ("num_passes", ctypes.c_int),
+        ("pass_lo", ctypes.c_int * QFT_MAX_PASSES),
+        ("pass_bits", ctypes.c_int * QFT_MAX_PASSES),
+        ("pass_spec", ctypes.c_int * QFT_MAX_PASSES),
+        ("pass_reverse", ctypes.c_int * QFT_MAX_PASSES),
+        ("config", Config),
+        ("gates_h", ctypes.c_longlong), ("gates_cr", ctypes.c_longlong),
+        ("gates_swap", ctypes.c_longlong),
+        ("state_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
+        ("table_bytes", ctypes.c_size_t), ("hbm_bytes", ctypes.c_size_t),
+    ]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            if isinstance(v, Config):
+                v = {f: getattr(v, f) for f, _ in Config._fields_}
+            elif hasattr(v, "__len__"):
+                v = list(v)[: self.num_passes]
+            d[name] = v
+        return d
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2606_18981_amd.build` "
+            "(there is no fallback implementation)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    sig = {
+        "qft_plan": (P, [I, I, I, I]),
+        "qft_plan_config": (P, [I, I, I, I, ctypes.POINTER(Config)]),
+        "qft_execute": (I, [P, P, P]),
+        "qft_execute_ws": (I, [P, P, P, P]),
+        "qft_destroy": (None, [P]),
+        "qft_last_error": (ctypes.c_char_p, []),
+        "qft_plan_info": (I, [P, ctypes.POINTER(PlanInfo)]),
+        "qft_plan_describe": (I, [I, I, I, I, ctypes.POINTER(Config), ctypes.POINTER(PlanInfo)]),
+        "qft_plan_set_timing": (I, [P, I]),
+        "qft_plan_pass_times": (I, [P, ctypes.POINTER(ctypes.c_double), I,
+                                    ctypes.POINTER(ctypes.c_longlong)]),
+        "qft_execute_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(P), I, P]),
+        "qft_fill_random": (I, [P, I, I, I, ctypes.c_uint64, ctypes.c_uint64, P]),
+        "qft_debug_pass_desc_size": (ctypes.c_size_t, []),
+        "qft_debug_pass": (I, [I, I, I, I, ctypes.POINTER(Config), I, P, ctypes.c_size_t,
+                               ctypes.POINTER(ctypes.c_int)]),
+        "qft_debug_tables": (I, [I, I, I, I, ctypes.POINTER(Config), P, ctypes.c_size_t,
+                                 ctypes.POINTER(ctypes.c_size_t)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return (lib.qft_last_error() or b"").decode()
+
+
+def _check(rc: int):
+    if rc != QFT_OK:
+        raise QftError(rc, last_error())
+
+
+def layout_flags(dtype="c64", order="natural", schedule="fused") -> int:
+    f = 0
+    if dtype in ("c128", "complex128") or str(dtype) == "torch.complex128":
+        f |= QFT_C128
+    elif not (dtype in ("c64", "complex64") or str(dtype) == "torch.complex64"):
+        raise ValueError(f"unsupported dtype {dtype!r}")
+    if order == "bitrev":
+        f |= QFT_ORDER_BITREV
+    elif order != "natural":
+        raise ValueError(f"unknown order {order!r}")
+    if schedule == "gates":
+        f |= QFT_SCHEDULE_GATES
+    elif schedule != "fused":
+        raise ValueError(f"unknown schedule {schedule!r}")
+    return f
+
+
+def _norm(norm) -> int:
+    return NORMS[norm] if isinstance(norm, str) else int(norm)
+
+
+def _config(config) -> Optional[Config]:
+    if config is None:
+        return None
+    if isinstance(config, Config):
+        return config
+    return Config(**{k: int(v) for k, v in dict(config).items()})
+
+
+def describe(n: int, cutoff: int = -1, norm="unitary", dtype="c64", order="natural",
+             schedule="fused", config=None) -> PlanInfo:
+    """Host-only planner description (no device use)."""
+    info = PlanInfo()
+    c = _config(config)
+    _check(lib.qft_plan_describe(n, cutoff, _norm(norm), layout_flags(dtype, order, schedule),
+                                 ctypes.byref(c) if c is not None else None, ctypes.byref(info)))
+    return info
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A planned 2^n-point transform (owns device tables and workspace)."""
+
+    def __init__(self, n: int, cutoff: int = -1, norm="unitary", dtype="c64",
+                 order="natural", schedule="fused", config=None):
+        self.n = n
+        self.cutoff = cutoff
+        self.layout = layout_flags(dtype, order, schedule)
+        self.c128 = bool(self.layout & QFT_C128)
+        c = _config(config)
+        h = lib.qft_plan_config(n, cutoff, _norm(norm), self.layout,
+                                ctypes.byref(c) if c is not None else None)
+        if not h:
+            raise QftError(QFT_ERR_INVALID, last_error())
+        self._h = ctypes.c_void_p(h)
+        self.info = PlanInfo()
+        _check(lib.qft_plan_info(self._h, ctypes.byref(self.info)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _check_tensor(self, x):
+        import torch
+        want = torch.complex128 if self.c128 else torch.complex64
+        if not x.is_cuda:
+            raise ValueError("tensor must be on the GPU")
+        if x.dtype != want:
+            raise ValueError(f"tensor dtype {x.dtype} does not match the plan ({want})")
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        if x.numel() != (1 << self.n):
+            raise ValueError(f"tensor has {x.numel()} elements, plan needs {1 << self.n}")
+
+    def execute(self, x, stream=None, workspace=None):
+        """In-place transform of the CUDA tensor x (complex64/128, 2^n elements)."""
+        self._check_tensor(x)
+        if workspace is None:
+            rc = lib.qft_execute(self._h, ctypes.c_void_p(x.data_ptr()), _stream_handle(stream))
+        else:
+            if workspace.numel() * workspace.element_size() < self.info.workspace_bytes:
+                raise ValueError("workspace too small")
+            rc = lib.qft_execute_ws(self._h, ctypes.c_void_p(x.data_ptr()),
+                                    ctypes.c_void_p(workspace.data_ptr()), _stream_handle(stream))
+        _check(rc)
+        return x
+
+    def set_timing(self, enable: bool = True):
+        _check(lib.qft_plan_set_timing(self._h, int(bool(enable))))
+
+    def pass_times(self):
+        """(mean ms per launch list, number of timed executes); clears them."""
+        k = max(1, self.info.num_passes)
+        buf = (ctypes.c_double * k)()
+        ex = ctypes.c_longlong(0)
+        _check(lib.qft_plan_pass_times(self._h, buf, k, ctypes.byref(ex)))
+        return list(buf), int(ex.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.qft_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def execute_batch(plans: Sequence[Plan], tensors, stream=None):
+    """One persistent launch over uneven transforms (plans[i] on tensors[i])."""
+    if len(plans) != len(tensors):
+        raise ValueError("plans and tensors differ in length")
+    for p, t in zip(plans, tensors):
+        p._check_tensor(t)
+    cnt = len(plans)
+    ph = (ctypes.c_void_p * cnt)(*[p.handle.value for p in plans])
+    tp = (ctypes.c_void_p * cnt)(*[t.data_ptr() for t in tensors])
+    _check(lib.qft_execute_batch(ph, tp, cnt, _stream_handle(stream)))
+
+
+def fill_random(x, dist="gaussian", seed: int = 0, stream_id: int = 0, stream=None):
+    """Fill a CUDA complex tensor of 2^n elements from the device Philox generator."""
+    import torch
+    n = x.numel().bit_length() - 1
+    if x.numel() != (1 << n) or not x.is_cuda or not x.is_contiguous():
+        raise ValueError("need a contiguous CUDA tensor of 2^n elements")
+    if x.dtype == torch.complex128:
+        lay = QFT_C128
+    elif x.dtype == torch.complex64:
+        lay = QFT_C64
+    else:
+        raise ValueError("need complex64 or complex128")
+    d = QFT_RNG_GAUSSIAN if dist == "gaussian" else QFT_RNG_UNIFORM
+    _check(lib.qft_fill_random(ctypes.c_void_p(x.data_ptr()), n, lay, d, seed, stream_id,
+                               _stream_handle(stream)))
+    return x

@@ -1,0 +1,216 @@
+"""Test-only CPU emulation of the fused-pass kernel over the planner's maps.
+
+This is NOT a product path and is never called by the library, smoke() or
+bench.py.  It replays, with numpy, what k_fused_pass does for every
+(tile, thread, register) of every launch the host planner emits: the same
+index deposits, LDS exchanges, butterflies, table twiddles, final diagonal
+and output addressing.  Tests use it to check the planner's pass partition
+and maps, and the twiddle bookkeeping, against the oracle on a machine
+without a GPU.
+"""
+
+import ctypes
+
+import numpy as np
+
+from paper_2606_18981_amd import qft as Q
+
+u8 = ctypes.c_uint8
+i8 = ctypes.c_int8
+
+MAX_TILE = 15
+MAX_RADIX = 5
+MAX_GROUPS = 15
+
+
+class GroupMap(ctypes.Structure):
+    _fields_ = [("reg_pos", u8 * MAX_RADIX), ("thr_pos", u8 * MAX_TILE),
+                ("jbase", i8), ("nst", i8)]
+
+
+class PassDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", u8), ("T", u8), ("r", u8), ("m", u8), ("pbase", u8), ("lo", u8),
+        ("ngroups", u8), ("reverse", u8), ("ext_tw", u8), ("aqft", u8), ("k", i8),
+        ("nfree", u8), ("MI", u8), ("L", u8), ("xcd_remap", u8), ("pad_", u8),
+        ("ntiles", ctypes.c_uint32),
+        ("gpos", u8 * MAX_TILE), ("free_pos", u8 * 32),
+        ("ld_thr_g", u8 * MAX_TILE), ("ld_reg_g", u8 * MAX_RADIX),
+        ("st_thr_g", u8 * MAX_TILE), ("st_reg_g", u8 * MAX_RADIX),
+        ("grp", GroupMap * MAX_GROUPS),
+        ("scale", ctypes.c_double),
+        ("tw_int", ctypes.c_void_p), ("tw_lo", ctypes.c_void_p), ("tw_hi", ctypes.c_void_p),
+    ]
+
+
+def desc_size_matches() -> bool:
+    return ctypes.sizeof(PassDesc) == Q.lib.qft_debug_pass_desc_size()
+
+
+def get_pass(n, cutoff, norm, layout, config, p):
+    d = PassDesc()
+    launch = (ctypes.c_int * 5)()
+    c = Q._config(config)
+    rc = Q.lib.qft_debug_pass(n, cutoff, Q._norm(norm), layout,
+                              ctypes.byref(c) if c is not None else None, p,
+                              ctypes.byref(d), ctypes.sizeof(d), launch)
+    Q._check(rc)
+    return d, list(launch)
+
+
+def get_tables(n, cutoff, norm, layout, config):
+    off = (ctypes.c_size_t * 4)()
+    c = Q._config(config)
+    cref = ctypes.byref(c) if c is not None else None
+    Q._check(Q.lib.qft_debug_tables(n, cutoff, Q._norm(norm), layout, cref, None, 0, off))
+    buf = (ctypes.c_uint8 * max(1, off[3]))()
+    Q._check(Q.lib.qft_debug_tables(n, cutoff, Q._norm(norm), layout, cref, buf, off[3], off))
+    dt = np.complex128 if layout & Q.QFT_C128 else np.complex64
+    raw = np.frombuffer(bytes(buf), dtype=np.uint8)
+    es = np.dtype(dt).itemsize
+
+    def tab(a, b):
+        return raw[a:b].view(dt).astype(np.complex128) if b > a else np.zeros(0, np.complex128)
+
+    return tab(off[0], off[1]), tab(off[1], off[2]), tab(off[2], off[3]), es
+
+
+def _swizzle(e, c128):
+    sw = 3 if c128 else 4
+    h = (e >> sw) ^ (e >> (2 * sw)) ^ (e >> (3 * sw)) ^ (e >> (4 * sw))
+    return e ^ (h & ((1 << sw) - 1))
+
+
+def _bitrev(x, n):
+    r = np.zeros_like(x)
+    for b in range(n):
+        r |= ((x >> b) & 1) << (n - 1 - b)
+    return r
+
+
+def run_pass(d, launch, src, tables, c128, check=True):
+    """Emulate one launch; returns (output indices, values) for all tiles."""
+    W, tlo, thi, _ = tables
+    T, RB = d.T, d.r
+    R = 1 << RB
+    TR = T - RB
+    NT = 1 << TR
+    assert launch[0] == NT
+    blocks = np.arange(d.ntiles, dtype=np.int64)
+    if d.xcd_remap:
+        per = d.ntiles >> 3
+        tile = (blocks & 7) * per + (blocks >> 3)
+    else:
+        tile = blocks
+    base = np.zeros_like(tile)
+    for b in range(d.nfree):
+        base |= ((tile >> b) & 1) << d.free_pos[b]
+    tid = np.arange(NT, dtype=np.int64)
+
+    def dep_tid(pos):
+        e = np.zeros(NT, dtype=np.int64)
+        for b in range(TR):
+            e |= ((tid >> b) & 1) << pos[b]
+        return e
+
+    def dep_reg(rho, pos):
+        o = 0
+        for q in range(RB):
+            if (rho >> q) & 1:
+                o |= 1 << pos[q]
+        return o
+
+    g = base[:, None] | dep_tid(d.ld_thr_g)[None, :]
+    ld_idx = [g | dep_reg(rho, d.ld_reg_g) for rho in range(R)]
+    if check:
+        allidx = np.concatenate([a.ravel() for a in ld_idx])
+        assert np.unique(allidx).size == allidx.size == (1 << d.n), "loads are not a permutation"
+    v = [src[i].astype(np.complex128) for i in ld_idx]
+
+    for gi in range(d.ngroups):
+        G = d.grp[gi]
+        e_thr = dep_tid(G.thr_pos)
+        if gi > 0:
+            P = d.grp[gi - 1]
+            e_prev = dep_tid(P.thr_pos)
+            lds = np.full((d.ntiles, 1 << T), np.nan + 0j)
+            seen = np.zeros(1 << T, dtype=np.int64)
+            for rho in range(R):
+                a = _swizzle(e_prev | dep_reg(rho, P.reg_pos), c128)
+                lds[:, a] = v[rho]
+                np.add.at(seen, a, 1)
+            if check:
+                assert np.all(seen == 1), "LDS exchange does not cover the tile once"
+            v = [lds[:, _swizzle(e_thr | dep_reg(rho, G.reg_pos), c128)] for rho in range(R)]
+        # stages
+        nst, jbase = G.nst, G.jbase
+        u_thr = (e_thr >> d.pbase) & ((1 << jbase) - 1)
+        MI1 = d.MI - 1
+        for q in range(RB - 1, -1, -1):
+            if q >= nst:
+                continue
+            jl = jbase + q
+            clear = max(0, jl - d.k) if d.aqft else 0
+            x_thr = np.zeros_like(u_thr) if clear >= jbase else (u_thr >> clear) << clear
+            rclear = clear - jbase if clear > jbase else 0
+            tw = [W[x_thr << (MI1 - jl)]]
+            for a in range(1, 1 << q):
+                xr = (a >> rclear) << rclear
+                tw.append(tw[0] * W[xr << (MI1 - q)])
+            for rho in range(R):
+                if rho & (1 << q):
+                    continue
+                hi = rho | (1 << q)
+                a, b = v[rho], v[hi]
+                v[rho] = a + b
+                v[hi] = (a - b) * tw[rho & ((1 << q) - 1)][None, :]
+
+    obase = _bitrev(base, d.n) if d.reverse else base
+    g = obase[:, None] | dep_tid(d.st_thr_g)[None, :]
+    out_idx, out_val = [], []
+    for rho in range(R):
+        idx = g | dep_reg(rho, d.st_reg_g)
+        val = v[rho]
+        if d.ext_tw:
+            vv = idx & ((1 << d.lo) - 1)
+            p = (idx >> d.lo) & ((1 << d.m) - 1)
+            if not d.aqft:
+                E = (vv * _bitrev(p, d.m)) << (d.n - d.lo - d.m)
+            else:
+                E = np.zeros_like(idx)
+                for j in range(d.m):
+                    s = d.lo + j - d.k
+                    if s <= 0:
+                        tv = vv
+                    elif s >= d.lo:
+                        tv = np.zeros_like(vv)
+                    else:
+                        tv = (vv >> s) << s
+                    E = (E + np.where((p >> j) & 1, tv << (d.n - 1 - d.lo - j), 0)) & ((1 << d.n) - 1)
+            w = tlo[E & ((1 << d.L) - 1)] * thi[E >> d.L]
+            val = val * w * d.scale
+        else:
+            val = val * d.scale
+        out_idx.append(idx.ravel())
+        out_val.append(val.ravel())
+    out_idx = np.concatenate(out_idx)
+    out_val = np.concatenate(out_val)
+    if check:
+        assert np.unique(out_idx).size == out_idx.size == (1 << d.n), "stores are not a permutation"
+    return out_idx, out_val
+
+
+def emulate(x, n, cutoff=-1, norm="unitary", dtype="c64", order="natural", config=None):
+    layout = Q.layout_flags(dtype, order, "fused")
+    c128 = bool(layout & Q.QFT_C128)
+    info = Q.describe(n, cutoff, norm, dtype, order, "fused", config)
+    tables = get_tables(n, cutoff, norm, layout, config)
+    state = np.asarray(x, dtype=np.complex128).copy()
+    ws = np.zeros_like(state)
+    for p in range(info.num_passes):
+        d, launch = get_pass(n, cutoff, norm, layout, config, p)
+        src = ws if launch[3] else state
+        dst = ws if launch[4] else state
+        idx, val = run_pass(d, launch, src, tables, c128)
+        dst[idx] = val
+    return state

@@ -1,0 +1,226 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (relative L2 against the oracle): complex128 <= 1e-12,
+complex64 <= 1e-5 (both at every n tested here).  Inputs are seeded
+synthetic arrays from paper_2606_18981_amd.inputs.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_18981_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": 1e-5, "c128": 1e-12}
+NPDT = {"c64": np.complex64, "c128": np.complex128}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2606_18981_amd import qft
+    return qft
+
+
+def run_gpu(torch, Q, x, n, cutoff=-1, norm="unitary", dtype="c64", order="natural",
+            schedule="fused", config=None):
+    print(f"[gpu] n={n} cutoff={cutoff} norm={norm} dtype={dtype} order={order} "
+          f"schedule={schedule} config={config}", flush=True)
+    plan = Q.Plan(n, cutoff, norm, dtype, order, schedule, config)
+    t = torch.from_numpy(np.asarray(x).astype(NPDT[dtype])).to("cuda")
+    plan.execute(t)
+    torch.cuda.synchronize()
+    y = t.cpu().numpy().astype(np.complex128)
+    plan.close()
+    return y
+
+
+def oracle_ref(x, cutoff, norm, order):
+    n = int(np.log2(len(x)))
+    k = None if cutoff < 0 else cutoff
+    if n <= 11:
+        return O.qft_circuit(x, k, norm, order)
+    return O.qft_fused_targets(x, k, norm, order)
+
+
+# ---- config 1: plain exact n = 10, complex128, gate by gate ---------------
+
+@pytest.mark.parametrize("schedule", ["gates", "fused"])
+@pytest.mark.parametrize("which", ["uniform", "delta", "tone37"])
+def test_n10_c128_three_inputs(torch_cuda, Q, schedule, which):
+    n = 10
+    x = {"uniform": I.uniform_pm1(n, 1001), "delta": I.delta(n, 0),
+         "tone37": I.tone(n, 37)}[which]
+    y = run_gpu(torch_cuda, Q, x, n, -1, "unitary", "c128", "natural", schedule)
+    ref = O.dft_naive(x)
+    assert O.rel_l2(y, ref) <= 1e-12
+    if which == "delta":
+        assert np.max(np.abs(y - 1.0 / 32)) < 1e-14
+    if which == "tone37":
+        spike = np.zeros(1 << n, complex)
+        spike[37] = 32.0
+        assert np.max(np.abs(y - spike)) < 1e-12
+
+
+# ---- sweep of sizes, dtypes, orders and norms -------------------------------
+
+SWEEP = []
+for n in list(range(1, 21)):
+    for dt in ("c64", "c128"):
+        SWEEP.append((n, dt, "natural", "unitary"))
+for n in (3, 12, 13, 14, 17):
+    for dt in ("c64", "c128"):
+        SWEEP.append((n, dt, "bitrev", "unitary"))
+        SWEEP.append((n, dt, "natural", "none"))
+        SWEEP.append((n, dt, "bitrev", "inv_n"))
+
+
+@pytest.mark.parametrize("n,dtype,order,norm", SWEEP)
+def test_exact_sweep(torch_cuda, Q, n, dtype, order, norm):
+    x = I.gaussian(n, 2000 + n)
+    y = run_gpu(torch_cuda, Q, x, n, -1, norm, dtype, order)
+    assert O.rel_l2(y, oracle_ref(x, -1, norm, order)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("n", [4, 9, 12, 16, 20])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 6, 10])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_aqft_sweep(torch_cuda, Q, n, k, dtype):
+    x = I.gaussian(n, 3000 + n)
+    y = run_gpu(torch_cuda, Q, x, n, k, "unitary", dtype, "natural")
+    assert O.rel_l2(y, oracle_ref(x, k, "unitary", "natural")) <= TOL[dtype]
+
+
+CONFIGS = [
+    dict(tile_log2=6, radix_log2=1, spec_log2=2, rev_spec_log2=2),
+    dict(tile_log2=8, radix_log2=3, spec_log2=-1, rev_spec_log2=-1),
+    dict(tile_log2=9, radix_log2=5, spec_log2=4, rev_spec_log2=4),
+    dict(tile_log2=12, radix_log2=4, spec_log2=4, rev_spec_log2=4),
+    dict(tile_log2=13, radix_log2=5, spec_log2=3, rev_spec_log2=3),
+]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS)
+@pytest.mark.parametrize("n,k,order", [(11, -1, "natural"), (19, 4, "natural"),
+                                       (20, -1, "bitrev")])
+def test_kernel_configs(torch_cuda, Q, cfg, n, k, order):
+    for dt in ("c64", "c128"):
+        x = I.uniform_pm1(n, 4000 + n)
+        y = run_gpu(torch_cuda, Q, x, n, k, "unitary", dt, order, "fused", cfg)
+        assert O.rel_l2(y, oracle_ref(x, k, "unitary", order)) <= TOL[dt]
+
+
+def test_gate_schedule_matches_fused_on_gpu(torch_cuda, Q):
+    n = 12
+    x = I.gaussian(n, 5)
+    for k in (-1, 3):
+        a = run_gpu(torch_cuda, Q, x, n, k, "unitary", "c128", "natural", "gates")
+        b = run_gpu(torch_cuda, Q, x, n, k, "unitary", "c128", "natural", "fused")
+        assert O.rel_l2(a, b) <= 1e-13
+        assert O.rel_l2(a, oracle_ref(x, k, "unitary", "natural")) <= 1e-12
+
+
+# ---- config 2: n = 24, both dtypes, Gaussian and multi-tone ----------------
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_n24_gaussian_and_tones(torch_cuda, Q, dtype):
+    n = 24
+    x = I.gaussian(n, 1002, unit_norm=True)
+    y = run_gpu(torch_cuda, Q, x, n, -1, "unitary", dtype, "natural")
+    ref = O.qft_fused_targets(x)
+    assert O.rel_l2(y, ref) <= TOL[dtype]
+    xt, bins, amp, ph = I.multi_tone(n, 1002, 8, 0.01)
+    y = run_gpu(torch_cuda, Q, xt, n, -1, "unitary", dtype, "natural")
+    sample = np.concatenate([bins, np.random.default_rng(1).choice(1 << n, 24, replace=False)])
+    assert O.rel_l2(y[sample], O.dft_bins(xt, sample)) <= TOL[dtype]
+    assert np.linalg.norm(y) == pytest.approx(np.linalg.norm(xt), rel=1e-5)
+    for b, a, p in zip(bins, amp, ph):
+        assert abs(y[b] - a * np.exp(1j * p) * 2 ** (n / 2)) < 1.0
+
+
+# ---- config 3: n = 28 exact and AQFT, sampled outputs ----------------------
+
+@pytest.mark.parametrize("k", [-1, 6, 14])
+def test_n28_sampled_bins(torch_cuda, Q, k):
+    n = 28
+    x = I.gaussian(n, 1003)
+    y = run_gpu(torch_cuda, Q, x, n, k, "unitary", "c64", "natural")
+    bins = np.random.default_rng(28).choice(1 << n, 12, replace=False)
+    ref = O.dft_bins(x, bins) if k < 0 else O.aqft_bins(x, bins, k)
+    assert O.rel_l2(y[bins], ref) <= TOL["c64"]
+    # the AQFT is unitary: Parseval at any size
+    assert np.linalg.norm(y) == pytest.approx(np.linalg.norm(x), rel=1e-5)
+
+
+# ---- device input generator ------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_device_philox_matches_host(torch_cuda, Q, dtype):
+    torch = torch_cuda
+    n = 16
+    t = torch.empty(1 << n, dtype=torch.complex128 if dtype == "c128" else torch.complex64,
+                    device="cuda")
+    Q.fill_random(t, "uniform", seed=1234, stream_id=7)
+    torch.cuda.synchronize()
+    host = I.philox_uniform_pm1(n, 1234, 7).astype(NPDT[dtype])
+    assert np.array_equal(t.cpu().numpy(), host)
+    Q.fill_random(t, "gaussian", seed=99, stream_id=3)
+    torch.cuda.synchronize()
+    host = I.philox_gaussian(n, 99, 3)
+    got = t.cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(got - host)) <= (1e-13 if dtype == "c128" else 1e-6)
+
+
+# ---- ABI behaviour on the device ------------------------------------------
+
+def test_abi_errors_and_workspace(torch_cuda, Q):
+    torch = torch_cuda
+    import ctypes
+    n = 18
+    plan = Q.Plan(n, -1, "unitary", "c64", "natural")
+    t = torch.zeros((1 << n) + 1, dtype=torch.complex64, device="cuda")
+    # misaligned pointer -> QFT_ERR_POINTER, nothing launched
+    rc = Q.lib.qft_execute(plan.handle, ctypes.c_void_p(t.data_ptr() + 4), None)
+    assert rc == Q.QFT_ERR_POINTER
+    rc = Q.lib.qft_execute(plan.handle, None, None)
+    assert rc == Q.QFT_ERR_POINTER
+    rc = Q.lib.qft_execute_ws(plan.handle, ctypes.c_void_p(t.data_ptr()), None, None)
+    assert rc == Q.QFT_ERR_POINTER  # this plan needs a workspace
+    # caller workspaces on two streams give the plan's own result
+    x = I.gaussian(n, 9)
+    a = torch.from_numpy(x.astype(np.complex64)).cuda()
+    b = a.clone()
+    c = a.clone()
+    ws1 = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    ws2 = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    plan.execute(a)
+    plan.execute(b, stream=s1, workspace=ws1)
+    plan.execute(c, stream=s2, workspace=ws2)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)
+    plan.close()
+
+
+def test_timing_api(torch_cuda, Q):
+    torch = torch_cuda
+    n = 22
+    plan = Q.Plan(n, -1, "unitary", "c64", "natural")
+    t = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    Q.fill_random(t, "gaussian", seed=1)
+    plan.set_timing(True)
+    for _ in range(3):
+        plan.execute(t)
+    ms, ex = plan.pass_times()
+    assert ex == 3
+    assert len(ms) == plan.info.num_passes and all(m > 0 for m in ms)
+    plan.close()

@@ -1,0 +1,185 @@
+"""Host-side checks of libqft.so that need no GPU.
+
+* the library loads and exports every function declared in include/*.h;
+* argument validation and error codes of the host planner;
+* pass partition: every qubit applied exactly once, in descending order;
+* gate counts before fusion (the paper's aggregate counters);
+* twiddle tables against FP64 numpy within the dtype's rounding;
+* a test-only numpy replay of the fused kernel over the planner's maps
+  (tests/plan_emulator.py) against the oracle, for many configurations.
+"""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_18981_amd import inputs as I
+from paper_2606_18981_amd import qft as Q
+
+import plan_emulator as E
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(inc, fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(qft_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_function():
+    names = _declared_functions()
+    assert "qft_plan" in names and "qft_execute" in names and "qft_destroy" in names
+    lib = ctypes.CDLL(Q.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+
+
+def test_descriptor_layout_matches():
+    assert E.desc_size_matches()
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=0), dict(n=32), dict(n=-3), dict(norm=7), dict(layout=0x10),
+])
+def test_invalid_arguments(bad):
+    args = dict(n=10, cutoff=-1, norm=0, layout=0)
+    args.update(bad)
+    info = Q.PlanInfo()
+    rc = Q.lib.qft_plan_describe(args["n"], args["cutoff"], args["norm"], args["layout"],
+                                 None, ctypes.byref(info))
+    assert rc == Q.QFT_ERR_INVALID
+    assert Q.last_error() != ""
+
+
+def test_invalid_config():
+    for cfg in (dict(radix_log2=6), dict(tile_log2=16), dict(tile_log2=12, radix_log2=1)):
+        with pytest.raises(Q.QftError) as e:
+            Q.describe(16, config=cfg)
+        assert e.value.code == Q.QFT_ERR_INVALID
+
+
+def test_null_plan_is_rejected_without_gpu():
+    assert Q.lib.qft_execute(None, None, None) == Q.QFT_ERR_INVALID
+    Q.lib.qft_destroy(None)  # NULL-safe
+    info = Q.PlanInfo()
+    assert Q.lib.qft_plan_info(None, ctypes.byref(info)) == Q.QFT_ERR_INVALID
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 10, 13, 14, 20, 22, 24, 26, 28, 30, 31])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("order", ["natural", "bitrev"])
+def test_pass_partition_covers_each_qubit_once(n, dtype, order):
+    info = Q.describe(n, -1, "unitary", dtype, order)
+    P = info.num_passes
+    assert 1 <= P <= Q.QFT_MAX_PASSES
+    top = n
+    for p in range(P):
+        lo, m = info.pass_lo[p], info.pass_bits[p]
+        assert m >= 1 and lo + m == top  # descending, contiguous
+        top = lo
+        assert info.pass_reverse[p] == (1 if (order == "natural" and p == P - 1) else 0)
+    assert top == 0
+    es = 16 if dtype == "c128" else 8
+    assert info.state_bytes == es << n
+    assert info.hbm_bytes == 2 * P * info.state_bytes
+    assert info.workspace_bytes == (info.state_bytes if (order == "natural" and P > 1) else 0)
+
+
+def test_headline_pass_counts():
+    # n = 28 and 30 in three HBM passes for both element sizes; n <= 13
+    # (complex64) or <= 12 (complex128) in one
+    for dt in ("c64", "c128"):
+        assert Q.describe(28, dtype=dt).num_passes == 3
+        assert Q.describe(30, dtype=dt).num_passes == 3
+    assert Q.describe(13, dtype="c64").num_passes == 1
+    assert Q.describe(12, dtype="c128").num_passes == 1
+
+
+@pytest.mark.parametrize("n,k", [(22, 21), (22, 16), (22, 12), (22, 10), (22, 8), (22, 6),
+                                 (22, 4), (28, 6), (30, -1), (3, 1)])
+def test_gate_counts_before_fusion(n, k):
+    info = Q.describe(n, k)
+    ref = O.gate_counts(n, k)
+    assert (info.gates_h, info.gates_cr, info.gates_swap) == (ref["H"], ref["CR"], ref["SWAP"])
+    assert info.cutoff == O.effective_cutoff(n, k)
+
+
+def test_gate_schedule_description():
+    info = Q.describe(10, -1, "unitary", "c128", "natural", "gates")
+    assert info.num_passes == 10 + 45 + 5
+    info = Q.describe(10, -1, "none", "c128", "bitrev", "gates")
+    assert info.num_passes == 10 + 45 + 1  # no swaps, one output scale
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_twiddle_tables(dtype):
+    n = 20
+    layout = Q.layout_flags(dtype)
+    W, tlo, thi, es = E.get_tables(n, -1, "unitary", layout, None)
+    # numpy evaluates exp(-2 pi i x / N) with its own ~1 ulp angle rounding
+    ulp = 4 * 2.0 ** -52 if dtype == "c128" else 2.0 ** -23
+    MI = int(math.log2(W.size)) + 1
+    y = np.arange(W.size)
+    assert np.max(np.abs(W - np.exp(-2j * np.pi * y / 2 ** MI))) < ulp
+    L = int(math.log2(tlo.size))
+    x = np.arange(tlo.size)
+    assert np.max(np.abs(tlo - np.exp(-2j * np.pi * x / 2 ** n))) < ulp
+    x = np.arange(thi.size)
+    assert np.max(np.abs(thi - np.exp(-2j * np.pi * (x << L) / 2 ** n))) < ulp
+    # exact values at the quarter turns
+    assert W[0] == 1 and tlo[0] == 1
+    assert thi[thi.size // 4] == -1j and thi[thi.size // 2] == -1
+
+
+CASES = []
+for n in (1, 2, 3, 4, 6, 9, 13, 14, 15, 17):
+    for k in (None, 0, 1, 2, 5):
+        CASES.append((n, k, "unitary", "c128", "natural", None))
+for n in (5, 12, 16):
+    for norm in O.NORMS:
+        for order in O.ORDERS:
+            CASES.append((n, 3, norm, "c64", order, None))
+CONFIGS = [
+    dict(tile_log2=6, radix_log2=1, spec_log2=2, rev_spec_log2=2),
+    dict(tile_log2=7, radix_log2=2, spec_log2=3, rev_spec_log2=1),
+    dict(tile_log2=8, radix_log2=3, spec_log2=-1, rev_spec_log2=-1),
+    dict(tile_log2=9, radix_log2=5, spec_log2=4, rev_spec_log2=4),
+    dict(tile_log2=10, radix_log2=4, spec_log2=5, rev_spec_log2=3),
+]
+for cfg in CONFIGS:
+    for n, k in ((11, None), (16, 4), (19, 2), (20, None)):
+        for order in O.ORDERS:
+            CASES.append((n, k, "unitary", "c128", order, cfg))
+
+
+@pytest.mark.parametrize("n,k,norm,dtype,order,cfg", CASES)
+def test_emulated_kernel_matches_oracle(n, k, norm, dtype, order, cfg):
+    x = I.gaussian(n, 1000 + n)
+    cut = -1 if k is None else k
+    y = E.emulate(x, n, cut, norm, dtype, order, cfg)
+    ref = O.qft_fused_targets(x, k, norm, order)
+    tol = 1e-12 if dtype == "c128" else 2e-6
+    assert O.rel_l2(y, ref) < tol
+
+
+def test_emulated_three_pass_plan():
+    # a three-pass plan at n = 21 (complex64 default tiles) and an AQFT one
+    n = 21
+    x = I.gaussian(n, 7)
+    assert Q.describe(n, dtype="c64").num_passes == 3
+    for k in (None, 8):
+        y = E.emulate(x, n, -1 if k is None else k, "unitary", "c64", "natural")
+        assert O.rel_l2(y, O.qft_fused_targets(x, k)) < 2e-6
