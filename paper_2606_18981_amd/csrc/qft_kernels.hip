@@ -44,10 +44,12 @@ __device__ __forceinline__ uint32_t rev_bits(uint32_t x, int n) {
   return __builtin_bitreverse32(x) >> (32 - n);
 }
 
-// LDS address of tile element e: the low SW bits are XORed with a fold of the
-// higher bits, a bijection that spreads power-of-two strides over the banks.
+// LDS slot of tile element e: the low SW bits are XORed with a fold of the
+// higher bits.  The map is linear over GF(2) (and a bijection), so the slot of
+// e_thr | e_reg is slot(e_thr) ^ slot(e_reg): one XOR per element against a
+// wave-uniform term.
 template <typename Real>
-__device__ __forceinline__ uint32_t lds_swizzle(uint32_t e) {
+__host__ __device__ __forceinline__ uint32_t lds_swizzle(uint32_t e) {
   constexpr int SW = sizeof(Real) == 4 ? 4 : 3;
   const uint32_t h = (e >> SW) ^ (e >> (2 * SW)) ^ (e >> (3 * SW)) ^ (e >> (4 * SW));
   return e ^ (h & ((1u << SW) - 1u));
@@ -68,52 +70,108 @@ __device__ __forceinline__ uint32_t deposit_reg(int rho, const uint8_t *pos) {
   return o;
 }
 
-// Apply the stages (targets) of one register group.
-// Register bit q holds local pass bit jbase + q.  The twiddle of target
-// jl = jbase + q on element (thread, rho) is w_{2^{jl+1}}^{u}, u = local pass
-// bits below jl with the bits below jl - k cleared (AQFT); u splits into the
-// thread's bits below jbase and the register bits below q, so
-//   w_{2^{jl+1}}^{u} = w_{2^{jl+1}}^{u_thr} * w_{2^{q+1}}^{rho mod 2^q}.
+// cos(2 pi j / 32), j = 0..8
+__device__ constexpr double kCos32[9] = {
+    1.0, 0.98078528040323044913, 0.92387953251128675613, 0.83146961230254523708,
+    0.70710678118654752440, 0.55557023301960222474, 0.38268343236508977173,
+    0.19509032201612826785, 0.0};
+
+// z * w_32^J with w_32 = exp(-2 pi i / 32), 0 <= J < 16 (J is a constant after
+// unrolling, so the branches fold away).
+template <typename Real>
+__device__ __forceinline__ cplx<Real> mul_w32(cplx<Real> z, int J) {
+  if (J == 0) return z;
+  if (J == 8) return {z.y, -z.x};  // -i
+  const Real h = (Real)0.70710678118654752440;
+  if (J == 4) return {(z.x + z.y) * h, (z.y - z.x) * h};
+  if (J == 12) return {(z.y - z.x) * h, -(z.x + z.y) * h};
+  // w_32^J = c - i s with c = cos(2 pi J/32), s = sin(2 pi J/32)
+  const Real c = J <= 8 ? (Real)kCos32[J] : -(Real)kCos32[16 - J];
+  const Real sn = J <= 8 ? (Real)kCos32[8 - J] : (Real)kCos32[J - 8];
+  return {z.x * c + z.y * sn, z.y * c - z.x * sn};
+}
+
+// Radix-2^nst decimation-in-frequency network on register bits nst-1 .. 0:
+// for target register bit q the butterfly (a, b) -> (a + b, (a - b) w) with
+// the twiddle w = w_{2^{q+1}}^{rho mod 2^q} of the controlled phases whose
+// controls are the register bits below q.  Controls held by other threads are
+// applied afterwards by apply_factors (they commute with these butterflies).
 template <typename Real, int RB>
-__device__ __forceinline__ void apply_stages(cplx<Real> (&v)[1 << RB], const PassDesc &d,
-                                             const GroupMap &G, uint32_t e_thr) {
-  using C = cplx<Real>;
+__device__ __forceinline__ void radix_network(cplx<Real> (&v)[1 << RB], int nst) {
   constexpr int R = 1 << RB;
-  const int nst = G.nst;
-  const int jbase = G.jbase;
-  const C *__restrict__ W = (const C *)d.tw_int;
-  const uint32_t u_thr = (e_thr >> d.pbase) & ((1u << jbase) - 1u);
-  const int MI1 = d.MI - 1;
 #pragma unroll
   for (int q = RB - 1; q >= 0; --q) {
     if (q < nst) {
-      const int jl = jbase + q;
-      int clear = d.aqft ? jl - d.k : 0;
-      clear = clear < 0 ? 0 : clear;
-      const uint32_t x_thr = clear >= jbase ? 0u : ((u_thr >> clear) << clear);
-      const int rclear = clear > jbase ? clear - jbase : 0;
-      C tw[R / 2];
-      tw[0] = W[x_thr << (MI1 - jl)];
-#pragma unroll
-      for (int a = 1; a < (1 << q); ++a) {
-        const uint32_t xr = ((uint32_t)a >> rclear) << rclear;
-        tw[a] = cmul(tw[0], W[xr << (MI1 - q)]);
-      }
 #pragma unroll
       for (int rho = 0; rho < R; ++rho) {
         if (rho & (1 << q)) continue;
         const int hi = rho | (1 << q);
-        const C a = v[rho];
-        const C b = v[hi];
+        const cplx<Real> a = v[rho];
+        const cplx<Real> b = v[hi];
         v[rho] = cadd(a, b);
-        v[hi] = cmul(csub(a, b), tw[rho & ((1 << q) - 1)]);
+        v[hi] = mul_w32(csub(a, b), (rho & ((1 << q) - 1)) << (4 - q));
       }
     }
   }
 }
 
+// v[rho] *= F(rho), F(rho) = f0 * prod_{q : bit q of rho set} f[q].  The
+// products are built separately for the low and the high half of the register
+// bits (two small subset-product tables), so that about two complex
+// multiplies per element suffice and few registers stay live.  With
+// apply0 == false, f0 is taken as 1.
 template <typename Real, int RB>
-__global__ void __launch_bounds__(RB >= 5 ? 512 : 1024)
+__device__ __forceinline__ void apply_factors(cplx<Real> (&v)[1 << RB], const cplx<Real> (&f)[RB],
+                                              cplx<Real> f0, bool apply0) {
+  constexpr int R = 1 << RB;
+  constexpr int SL = RB / 2;
+  constexpr int NL = 1 << SL;
+  constexpr int NH = 1 << (RB - SL);
+  cplx<Real> Fl[NL], Fh[NH];
+  Fl[0] = f0;
+#pragma unroll
+  for (int a = 1; a < NL; ++a) {
+    const int top = 31 - __builtin_clz(a);
+    const int rest = a & ~(1 << top);
+    Fl[a] = (rest == 0 && !apply0) ? f[top] : cmul(Fl[rest], f[top]);
+  }
+  Fh[0] = cplx<Real>{(Real)1, (Real)0};
+#pragma unroll
+  for (int b = 1; b < NH; ++b) {
+    const int top = 31 - __builtin_clz(b);
+    const int rest = b & ~(1 << top);
+    Fh[b] = rest == 0 ? f[SL + top] : cmul(Fh[rest], f[SL + top]);
+  }
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho) {
+    const int a = rho & (NL - 1);
+    const int b = rho >> SL;
+    if (b == 0) {
+      if (a != 0 || apply0) v[rho] = cmul(v[rho], Fl[a]);
+    } else if (a == 0 && !apply0) {
+      v[rho] = cmul(v[rho], Fh[b]);
+    } else {
+      v[rho] = cmul(v[rho], cmul(Fl[a], Fh[b]));
+    }
+  }
+}
+
+template <typename Real>
+__device__ __forceinline__ cplx<Real> omega_n(const PassDesc &d, uint32_t E) {
+  const cplx<Real> *__restrict__ tlo = (const cplx<Real> *)d.tw_lo;
+  const cplx<Real> *__restrict__ thi = (const cplx<Real> *)d.tw_hi;
+  return cmul(tlo[E & ((1u << d.L) - 1u)], thi[E >> d.L]);
+}
+
+// Pass kernel.  Per register group: radix network on the group's register
+// bits, then the controlled phases whose controls are this thread's lower pass
+// bits (deferred to the end of the group), then an LDS exchange to the next
+// group's mapping.  At the end: the diagonal of the controls below the pass
+// (high passes), the folded scale, and the store (bit-reversed addresses in
+// the final pass of a natural-order plan).
+template <typename Real, int RB>
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? (RB >= 5 ? 256 : RB >= 4 ? 512 : 1024)
+                                                   : (RB >= 5 ? 512 : 1024))
 k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
   using C = cplx<Real>;
   constexpr int R = 1 << RB;
@@ -133,67 +191,95 @@ k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
 
   C v[R];
   {
-    const uint32_t g = base | deposit_tid(tid, d.ld_thr_g, TR);
+    const C *src = in + (base | deposit_tid(tid, d.ld_thr_g, TR));
 #pragma unroll
-    for (int rho = 0; rho < R; ++rho) v[rho] = in[g | deposit_reg<RB>(rho, d.ld_reg_g)];
+    for (int rho = 0; rho < R; ++rho) v[rho] = src[deposit_reg<RB>(rho, d.ld_reg_g)];
   }
 
+  const C *__restrict__ W = (const C *)d.tw_int;
+  const int MI1 = d.MI - 1;
   for (int gi = 0; gi < d.ngroups; ++gi) {
     const GroupMap &G = d.grp[gi];
     const uint32_t e_thr = deposit_tid(tid, G.thr_pos, TR);
     if (gi > 0) {
       const GroupMap &P = d.grp[gi - 1];
-      const uint32_t e_prev = deposit_tid(tid, P.thr_pos, TR);
+      const uint32_t sp = lds_swizzle<Real>(deposit_tid(tid, P.thr_pos, TR));
 #pragma unroll
       for (int rho = 0; rho < R; ++rho)
-        lds[lds_swizzle<Real>(e_prev | deposit_reg<RB>(rho, P.reg_pos))] = v[rho];
+        lds[sp ^ lds_swizzle<Real>(deposit_reg<RB>(rho, P.reg_pos))] = v[rho];
       __syncthreads();
+      const uint32_t sg = lds_swizzle<Real>(e_thr);
 #pragma unroll
       for (int rho = 0; rho < R; ++rho)
-        v[rho] = lds[lds_swizzle<Real>(e_thr | deposit_reg<RB>(rho, G.reg_pos))];
+        v[rho] = lds[sg ^ lds_swizzle<Real>(deposit_reg<RB>(rho, G.reg_pos))];
       __syncthreads();
     }
-    apply_stages<Real, RB>(v, d, G, e_thr);
+    const int nst = G.nst;
+    radix_network<Real, RB>(v, nst);
+    const int jbase = G.jbase;
+    if (jbase > 0 && nst > 0) {
+      // controls among this thread's pass bits below jbase: target jl = jbase+q
+      // gets w_{2^{jl+1}}^{u} on elements with register bit q set, u = those
+      // bits with the ones below jl - k cleared (AQFT)
+      const uint32_t u_thr = (e_thr >> d.pbase) & ((1u << jbase) - 1u);
+      C f[RB];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        const int jl = jbase + q;
+        int clear = d.aqft ? jl - d.k : 0;
+        clear = clear < 0 ? 0 : clear;
+        const uint32_t x = clear >= jbase ? 0u : ((u_thr >> clear) << clear);
+        f[q] = q < nst ? W[x << (MI1 - jl)] : C{(Real)1, (Real)0};
+      }
+      apply_factors<Real, RB>(v, f, C{(Real)1, (Real)0}, false);
+    }
   }
 
   const Real scale = (Real)d.scale;
   const uint32_t obase = d.reverse ? rev_bits(base, d.n) : base;
-  const uint32_t g = obase | deposit_tid(tid, d.st_thr_g, TR);
-  const uint32_t nmask = d.n >= 32 ? 0xffffffffu : ((1u << d.n) - 1u);
-#pragma unroll
-  for (int rho = 0; rho < R; ++rho) {
-    const uint32_t idx = g | deposit_reg<RB>(rho, d.st_reg_g);
-    C val = v[rho];
-    if (d.ext_tw) {
-      // diagonal of the controlled phases with controls below the pass:
-      // w_N^E, E = sum over pass bits j set of trunc_{lo+j-k}(v) 2^{n-1-lo-j}
-      const uint32_t vv = idx & ((1u << d.lo) - 1u);
-      const uint32_t p = (idx >> d.lo) & ((1u << d.m) - 1u);
-      uint32_t E;
-      if (!d.aqft) {
-        E = (vv * rev_bits(p, d.m)) << (d.n - d.lo - d.m);
-      } else {
-        E = 0;
-        for (int j = 0; j < d.m; ++j) {
-          if ((p >> j) & 1u) {
-            const int s = d.lo + j - d.k;
-            const uint32_t tv = s <= 0 ? vv : (s >= d.lo ? 0u : ((vv >> s) << s));
-            E = (E + (tv << (d.n - 1 - d.lo - j))) & nmask;
-          }
+  C *dst = out + (obase | deposit_tid(tid, d.st_thr_g, TR));
+  if (d.ext_tw) {
+    // diagonal of the controlled phases whose controls lie below the pass:
+    // w_N^E with E = sum over set pass bits j of trunc_{lo+j-k}(vv) 2^{n-1-lo-j}
+    // (vv = index bits below the pass).  All register bits are pass bits here,
+    // so E = E_thr + sum over set register bits q of c_q.
+    const uint32_t nmask = d.n >= 32 ? 0xffffffffu : ((1u << d.n) - 1u);
+    const uint32_t g = base | deposit_tid(tid, d.st_thr_g, TR);
+    const uint32_t vv = g & ((1u << d.lo) - 1u);
+    const uint32_t pt = (g >> d.lo) & ((1u << d.m) - 1u);
+    uint32_t Et = 0;
+    if (!d.aqft) {
+      Et = (vv * rev_bits(pt, d.m)) << (d.n - d.lo - d.m);
+    } else {
+      for (int j = 0; j < d.m; ++j) {
+        if ((pt >> j) & 1u) {
+          const int s = d.lo + j - d.k;
+          const uint32_t tv = s <= 0 ? vv : (s >= d.lo ? 0u : ((vv >> s) << s));
+          Et = (Et + (tv << (d.n - 1 - d.lo - j))) & nmask;
         }
       }
-      const C *__restrict__ tlo = (const C *)d.tw_lo;
-      const C *__restrict__ thi = (const C *)d.tw_hi;
-      C w = cmul(tlo[E & ((1u << d.L) - 1u)], thi[E >> d.L]);
-      w.x *= scale;
-      w.y *= scale;
-      val = cmul(val, w);
-    } else {
-      val.x *= scale;
-      val.y *= scale;
     }
-    out[idx] = val;
+    C f[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int j = d.st_reg_g[q] - d.lo;
+      const int s = d.lo + j - d.k;
+      const uint32_t tv = (!d.aqft || s <= 0) ? vv : (s >= d.lo ? 0u : ((vv >> s) << s));
+      f[q] = omega_n<Real>(d, (tv << (d.n - 1 - d.lo - j)) & nmask);
+    }
+    C f0 = omega_n<Real>(d, Et);
+    f0.x *= scale;
+    f0.y *= scale;
+    apply_factors<Real, RB>(v, f, f0, true);
+  } else if (scale != (Real)1) {
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) {
+      v[rho].x *= scale;
+      v[rho].y *= scale;
+    }
   }
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho) dst[deposit_reg<RB>(rho, d.st_reg_g)] = v[rho];
 }
 
 template <typename Real, int RB>

@@ -151,12 +151,26 @@ void build_groups(PassLaunch &L, const PassGeom &g, int r, int n) {
   }
 }
 
+// log2 of the largest workgroup the kernel instance for (r, dtype) allows
+// (its launch bounds keep the register tile of 2^r elements free of spills)
+int max_thread_bits(int r, bool c128) {
+  if (c128) return r >= 5 ? 8 : r >= 4 ? 9 : 10;
+  return r >= 5 ? 9 : 10;
+}
+
 int plan_fused(HostPlan &p, std::string &err) {
   const int n = p.n;
   const qft_config_t &c = p.cfg;
   int rc = check_config(c, err);
   if (rc) return rc;
-  const int T = c.tile_log2;
+  // Register radix: the controlled phases among a thread's register bits are
+  // compile-time constants of the radix network, so for an AQFT every
+  // register group must fit inside the cutoff distance (r <= k + 1).
+  int r_cfg = c.radix_log2;
+  if (p.keff < n - 1) r_cfg = std::min(r_cfg, p.keff + 1);
+  const int T = std::min(c.tile_log2, r_cfg + max_thread_bits(r_cfg, p.c128));
+  const int spec = std::min(c.spec_log2, T - 1);
+  const int rspec = std::min(c.rev_spec_log2, T - 1);
 
   // ---- pass partition --------------------------------------------------
   std::vector<PassGeom> geo;
@@ -167,9 +181,9 @@ int plan_fused(HostPlan &p, std::string &err) {
     g.reverse = !p.bitrev;
     geo.push_back(g);
   } else {
-    const int b_eff = p.bitrev ? 0 : c.rev_spec_log2;
+    const int b_eff = p.bitrev ? 0 : rspec;
     const int amax = T - b_eff;
-    const int hmax = T - c.spec_log2;
+    const int hmax = T - spec;
     int P = 1;
     while (amax + (P - 1) * hmax < n) ++P;
     if (P > kMaxPasses) {
@@ -186,7 +200,11 @@ int plan_fused(HostPlan &p, std::string &err) {
       PassGeom g;
       g.m = hs[i];
       g.lo = top - g.m;
-      const int nspec = std::min(T - g.m, g.lo);
+      // a high pass applies the diagonal of lower controls per register
+      // group, which needs every register bit to be a pass bit (r <= m)
+      const int r = std::min(r_cfg, g.m);
+      const int Tp = std::min(T, r + max_thread_bits(r, p.c128));
+      const int nspec = std::min(Tp - g.m, g.lo);
       for (int q = 0; q < nspec; ++q) g.spec_g.push_back(q);
       geo.push_back(g);
       top = g.lo;
@@ -211,7 +229,7 @@ int plan_fused(HostPlan &p, std::string &err) {
     MI = std::max(MI, g.m);
     if (g.lo > 0) need_ext = true;
   }
-  MI = std::max(MI, std::min(c.radix_log2, n));
+  MI = std::max(MI, std::min(r_cfg, n));
   p.MI = MI;
   p.need_ext = need_ext;
   p.L = need_ext ? (n + 1) / 2 : 0;
@@ -263,7 +281,8 @@ int plan_fused(HostPlan &p, std::string &err) {
     memset(&L, 0, sizeof(L));
     PassDesc &d = L.d;
     const int Te = (int)g.spec_g.size() + g.m;
-    const int r = std::min(c.radix_log2, Te);
+    int r = std::min(r_cfg, Te);
+    if (g.lo > 0) r = std::min(r, g.m);
     d.n = (uint8_t)n;
     d.T = (uint8_t)Te;
     d.r = (uint8_t)r;

@@ -142,57 +142,75 @@ def run_pass(d, launch, src, tables, c128, check=True):
             if check:
                 assert np.all(seen == 1), "LDS exchange does not cover the tile once"
             v = [lds[:, _swizzle(e_thr | dep_reg(rho, G.reg_pos), c128)] for rho in range(R)]
-        # stages
+        # radix network with the constant twiddles of the register bits
         nst, jbase = G.nst, G.jbase
-        u_thr = (e_thr >> d.pbase) & ((1 << jbase) - 1)
-        MI1 = d.MI - 1
         for q in range(RB - 1, -1, -1):
             if q >= nst:
                 continue
-            jl = jbase + q
-            clear = max(0, jl - d.k) if d.aqft else 0
-            x_thr = np.zeros_like(u_thr) if clear >= jbase else (u_thr >> clear) << clear
-            rclear = clear - jbase if clear > jbase else 0
-            tw = [W[x_thr << (MI1 - jl)]]
-            for a in range(1, 1 << q):
-                xr = (a >> rclear) << rclear
-                tw.append(tw[0] * W[xr << (MI1 - q)])
             for rho in range(R):
                 if rho & (1 << q):
                     continue
                 hi = rho | (1 << q)
                 a, b = v[rho], v[hi]
                 v[rho] = a + b
-                v[hi] = (a - b) * tw[rho & ((1 << q) - 1)][None, :]
+                J = (rho & ((1 << q) - 1)) << (4 - q)
+                v[hi] = (a - b) * np.exp(-2j * np.pi * J / 32)
+        # deferred phases of the thread's lower pass bits
+        if jbase > 0 and nst > 0:
+            u_thr = (e_thr >> d.pbase) & ((1 << jbase) - 1)
+            MI1 = d.MI - 1
+            f = []
+            for q in range(RB):
+                jl = jbase + q
+                clear = max(0, jl - d.k) if d.aqft else 0
+                x = np.zeros_like(u_thr) if clear >= jbase else (u_thr >> clear) << clear
+                f.append(W[x << (MI1 - jl)] if q < nst else np.ones(NT, complex))
+            for rho in range(1, R):
+                F = np.ones(NT, complex)
+                for q in range(RB):
+                    if (rho >> q) & 1:
+                        F = F * f[q]
+                v[rho] = v[rho] * F[None, :]
 
     obase = _bitrev(base, d.n) if d.reverse else base
     g = obase[:, None] | dep_tid(d.st_thr_g)[None, :]
+    nmask = (1 << d.n) - 1
+
+    def omega(E):
+        return tlo[E & ((1 << d.L) - 1)] * thi[E >> d.L]
+
+    if d.ext_tw:
+        vv = g & ((1 << d.lo) - 1)
+        pt = (g >> d.lo) & ((1 << d.m) - 1)
+        if not d.aqft:
+            Et = (vv * _bitrev(pt, d.m)) << (d.n - d.lo - d.m)
+        else:
+            Et = np.zeros_like(g)
+            for j in range(d.m):
+                s = d.lo + j - d.k
+                tv = vv if s <= 0 else (np.zeros_like(vv) if s >= d.lo else (vv >> s) << s)
+                Et = (Et + np.where((pt >> j) & 1, tv << (d.n - 1 - d.lo - j), 0)) & nmask
+        fq = []
+        for q in range(RB):
+            j = d.st_reg_g[q] - d.lo
+            assert 0 <= j < d.m, "a register bit of the store map is not a pass bit"
+            s = d.lo + j - d.k
+            tv = vv if (not d.aqft or s <= 0) else (np.zeros_like(vv) if s >= d.lo else (vv >> s) << s)
+            fq.append(omega((tv << (d.n - 1 - d.lo - j)) & nmask))
+        f0 = omega(Et) * d.scale
+        for rho in range(R):
+            F = f0.copy()
+            for q in range(RB):
+                if (rho >> q) & 1:
+                    F = F * fq[q]
+            v[rho] = v[rho] * F
+    else:
+        v = [x * d.scale for x in v]
     out_idx, out_val = [], []
     for rho in range(R):
         idx = g | dep_reg(rho, d.st_reg_g)
-        val = v[rho]
-        if d.ext_tw:
-            vv = idx & ((1 << d.lo) - 1)
-            p = (idx >> d.lo) & ((1 << d.m) - 1)
-            if not d.aqft:
-                E = (vv * _bitrev(p, d.m)) << (d.n - d.lo - d.m)
-            else:
-                E = np.zeros_like(idx)
-                for j in range(d.m):
-                    s = d.lo + j - d.k
-                    if s <= 0:
-                        tv = vv
-                    elif s >= d.lo:
-                        tv = np.zeros_like(vv)
-                    else:
-                        tv = (vv >> s) << s
-                    E = (E + np.where((p >> j) & 1, tv << (d.n - 1 - d.lo - j), 0)) & ((1 << d.n) - 1)
-            w = tlo[E & ((1 << d.L) - 1)] * thi[E >> d.L]
-            val = val * w * d.scale
-        else:
-            val = val * d.scale
         out_idx.append(idx.ravel())
-        out_val.append(val.ravel())
+        out_val.append(v[rho].ravel())
     out_idx = np.concatenate(out_idx)
     out_val = np.concatenate(out_val)
     if check:
