@@ -191,6 +191,7 @@ int qft_execute(qft_plan_t *plan, void *dev_ptr, qft_stream_t stream) {
 
 void qft_destroy(qft_plan_t *plan) {
   if (!plan) return;
+  batch_forget_plan(plan);
   plan->timer.release();
   if (plan->d_tables) hipFree(plan->d_tables);
   if (plan->d_ws) hipFree(plan->d_ws);

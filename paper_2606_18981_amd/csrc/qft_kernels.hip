@@ -163,37 +163,32 @@ __device__ __forceinline__ cplx<Real> omega_n(const PassDesc &d, uint32_t E) {
   return cmul(tlo[E & ((1u << d.L) - 1u)], thi[E >> d.L]);
 }
 
-// Pass kernel.  Per register group: radix network on the group's register
-// bits, then the controlled phases whose controls are this thread's lower pass
-// bits (deferred to the end of the group), then an LDS exchange to the next
-// group's mapping.  At the end: the diagonal of the controls below the pass
-// (high passes), the folded scale, and the store (bit-reversed addresses in
-// the final pass of a natural-order plan).
+// One tile of one pass.  Per register group: radix network on the group's
+// register bits, then the controlled phases whose controls are this thread's
+// lower pass bits (deferred to the end of the group), then an LDS exchange to
+// the next group's mapping.  At the end: the diagonal of the controls below
+// the pass (high passes), the folded scale, and the store (bit-reversed
+// addresses in the final pass of a natural-order plan).  Threads with
+// active == false (workgroups larger than the tile needs) only take part in
+// the barriers.
 template <typename Real, int RB>
-__global__ void __launch_bounds__(sizeof(Real) == 8 ? (RB >= 5 ? 256 : RB >= 4 ? 512 : 1024)
-                                                   : (RB >= 5 ? 512 : 1024))
-k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
+__device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, const cplx<Real> *in,
+                                          cplx<Real> *out, cplx<Real> *lds, uint32_t tid,
+                                          bool active) {
   using C = cplx<Real>;
   constexpr int R = 1 << RB;
-  extern __shared__ __align__(16) unsigned char qft_smem[];
-  C *lds = reinterpret_cast<C *>(qft_smem);
-  const uint32_t tid = threadIdx.x;
   const int TR = d.T - RB;
-
-  uint32_t tile = blockIdx.x;
-  if (d.xcd_remap) {
-    // consecutive tiles on one XCD (workgroups are dealt round-robin to 8 XCDs)
-    const uint32_t per = d.ntiles >> 3;
-    tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
-  }
   uint32_t base = 0;
   for (int b = 0; b < d.nfree; ++b) base |= ((tile >> b) & 1u) << d.free_pos[b];
 
   C v[R];
-  {
+  if (active) {
     const C *src = in + (base | deposit_tid(tid, d.ld_thr_g, TR));
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) v[rho] = src[deposit_reg<RB>(rho, d.ld_reg_g)];
+  } else {
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) v[rho] = C{(Real)0, (Real)0};
   }
 
   const C *__restrict__ W = (const C *)d.tw_int;
@@ -203,21 +198,25 @@ k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
     const uint32_t e_thr = deposit_tid(tid, G.thr_pos, TR);
     if (gi > 0) {
       const GroupMap &P = d.grp[gi - 1];
-      const uint32_t sp = lds_swizzle<Real>(deposit_tid(tid, P.thr_pos, TR));
+      if (active) {
+        const uint32_t sp = lds_swizzle<Real>(deposit_tid(tid, P.thr_pos, TR));
 #pragma unroll
-      for (int rho = 0; rho < R; ++rho)
-        lds[sp ^ lds_swizzle<Real>(deposit_reg<RB>(rho, P.reg_pos))] = v[rho];
+        for (int rho = 0; rho < R; ++rho)
+          lds[sp ^ lds_swizzle<Real>(deposit_reg<RB>(rho, P.reg_pos))] = v[rho];
+      }
       __syncthreads();
-      const uint32_t sg = lds_swizzle<Real>(e_thr);
+      if (active) {
+        const uint32_t sg = lds_swizzle<Real>(e_thr);
 #pragma unroll
-      for (int rho = 0; rho < R; ++rho)
-        v[rho] = lds[sg ^ lds_swizzle<Real>(deposit_reg<RB>(rho, G.reg_pos))];
+        for (int rho = 0; rho < R; ++rho)
+          v[rho] = lds[sg ^ lds_swizzle<Real>(deposit_reg<RB>(rho, G.reg_pos))];
+      }
       __syncthreads();
     }
     const int nst = G.nst;
     radix_network<Real, RB>(v, nst);
     const int jbase = G.jbase;
-    if (jbase > 0 && nst > 0) {
+    if (jbase > 0 && nst > 0 && active) {
       // controls among this thread's pass bits below jbase: target jl = jbase+q
       // gets w_{2^{jl+1}}^{u} on elements with register bit q set, u = those
       // bits with the ones below jl - k cleared (AQFT)
@@ -234,6 +233,7 @@ k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
       apply_factors<Real, RB>(v, f, C{(Real)1, (Real)0}, false);
     }
   }
+  if (!active) return;
 
   const Real scale = (Real)d.scale;
   const uint32_t obase = d.reverse ? rev_bits(base, d.n) : base;
@@ -283,6 +283,21 @@ k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
 }
 
 template <typename Real, int RB>
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? (RB >= 5 ? 256 : RB >= 4 ? 512 : 1024)
+                                                   : (RB >= 5 ? 512 : 1024))
+k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  uint32_t tile = blockIdx.x;
+  if (d.xcd_remap) {
+    // consecutive tiles on one XCD (workgroups are dealt round-robin to 8 XCDs)
+    const uint32_t per = d.ntiles >> 3;
+    tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  }
+  tile_body<Real, RB>(d, tile, in, out, reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x,
+                      true);
+}
+
+template <typename Real, int RB>
 static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, hipStream_t s) {
   auto fn = k_fused_pass<Real, RB>;
   if (L.lds_bytes > 65536) {
@@ -320,6 +335,131 @@ hipError_t launch_fused_pass(const PassLaunch &L, bool c128, const void *in, voi
     }
   }
   return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// persistent batch kernel
+// ---------------------------------------------------------------------------
+
+// Work items are (transform, pass, tile) triples laid out segment by segment:
+// all first passes, then all second passes, and so on, so an item only waits
+// for items that were claimed before it (no deadlock, whatever the number of
+// resident workgroups).  counters[0] is the claim counter, counters[1 + j]
+// the number of finished tiles of transform j, counters[1 + njobs] an error
+// flag set when a wait exceeds its spin limit (then every workgroup leaves).
+template <typename Real, int MAXRB>
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? (MAXRB >= 5 ? 256 : MAXRB >= 4 ? 512 : 1024)
+                                                   : (MAXRB >= 5 ? 512 : 1024))
+k_batch(const BatchSeg *__restrict__ segs, int nseg, uint32_t total,
+        const PassDesc *__restrict__ descs, const BatchIO *__restrict__ io, uint32_t *counters,
+        int njobs, uint32_t spin_limit) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_abort;
+  cplx<Real> *lds = reinterpret_cast<cplx<Real> *>(qft_smem);
+  const uint32_t tid = threadIdx.x;
+  uint32_t *err_flag = counters + 1 + njobs;
+  for (;;) {
+    if (tid == 0) {
+      s_abort = __hip_atomic_load(err_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_item = atomicAdd(&counters[0], 1u);
+    }
+    __syncthreads();
+    const uint32_t item = s_item;
+    const uint32_t abort_now = s_abort;
+    __syncthreads();
+    if (item >= total || abort_now) break;
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (segs[mid].first <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchSeg sg = segs[lo];
+    if (sg.wait) {
+      if (tid == 0) {
+        uint32_t spins = 0;
+        s_abort = 0;
+        while (__hip_atomic_load(&counters[1 + sg.job], __ATOMIC_ACQUIRE,
+                                 __HIP_MEMORY_SCOPE_AGENT) < sg.wait) {
+          __builtin_amdgcn_s_sleep(2);
+          if (++spins > spin_limit) {
+            __hip_atomic_store(err_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_abort = 1;
+            break;
+          }
+        }
+      }
+      __syncthreads();
+      if (s_abort) break;
+      __threadfence();
+    }
+    const PassDesc &d = descs[sg.desc];
+    const BatchIO b = io[sg.desc];
+    const uint32_t t = item - sg.first;
+    const bool active = tid < sg.threads;
+    const cplx<Real> *in = (const cplx<Real> *)b.in;
+    cplx<Real> *out = (cplx<Real> *)b.out;
+    switch (d.r) {
+      case 1: tile_body<Real, 1>(d, t, in, out, lds, tid, active); break;
+      case 2: tile_body<Real, 2>(d, t, in, out, lds, tid, active); break;
+      case 3: if (MAXRB >= 3) tile_body<Real, (MAXRB >= 3 ? 3 : 1)>(d, t, in, out, lds, tid, active); break;
+      case 4: if (MAXRB >= 4) tile_body<Real, (MAXRB >= 4 ? 4 : 1)>(d, t, in, out, lds, tid, active); break;
+      case 5: if (MAXRB >= 5) tile_body<Real, (MAXRB >= 5 ? 5 : 1)>(d, t, in, out, lds, tid, active); break;
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0)
+      __hip_atomic_fetch_add(&counters[1 + sg.job], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t value) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+template <typename Real, int MAXRB>
+static const void *batch_fn() {
+  return reinterpret_cast<const void *>(k_batch<Real, MAXRB>);
+}
+
+const void *batch_kernel(bool c128, int maxrb) {
+  if (c128) {
+    switch (maxrb) {
+      case 1: case 2: case 3: return batch_fn<double, 3>();
+      case 4: return batch_fn<double, 4>();
+      default: return batch_fn<double, 5>();
+    }
+  }
+  switch (maxrb) {
+    case 1: case 2: case 3: return batch_fn<float, 3>();
+    case 4: return batch_fn<float, 4>();
+    default: return batch_fn<float, 5>();
+  }
+}
+
+hipError_t launch_batch(bool c128, int maxrb, const BatchLaunch &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, b.counters, (uint32_t)(b.njobs + 2), 0u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const void *fn = batch_kernel(c128, maxrb);
+  if (b.lds_bytes > 65536) {
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+    if (e != hipSuccess) return e;
+  }
+  int nseg = b.nseg;
+  uint32_t total = b.total;
+  int njobs = b.njobs;
+  uint32_t spin = b.spin_limit;
+  void *args[] = {(void *)&b.segs, &nseg, &total, (void *)&b.descs, (void *)&b.io,
+                  (void *)&b.counters, &njobs, &spin};
+  return hipLaunchKernel(fn, dim3(b.grid), dim3(b.block), args, b.lds_bytes, s);
+}
+
+int batch_max_block(bool c128, int maxrb) {
+  if (c128) return maxrb >= 5 ? 256 : maxrb >= 4 ? 512 : 1024;
+  return maxrb >= 5 ? 512 : 1024;
 }
 
 // ---------------------------------------------------------------------------

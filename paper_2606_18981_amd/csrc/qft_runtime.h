@@ -45,4 +45,6 @@ struct qft_plan_s {
 
 namespace qft {
 int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s);
+// drop cached batch launches that use this plan
+void batch_forget_plan(qft_plan_s *plan);
 }

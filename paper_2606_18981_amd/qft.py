@@ -27,6 +27,7 @@ QFT_CUTOFF_EXACT = -1
 QFT_MAX_PASSES = 8
 QFT_RNG_GAUSSIAN = 0
 QFT_RNG_UNIFORM = 1
+QFT_BATCH_EAGER = 0x1
 
 QFT_OK = 0
 QFT_ERR_INVALID = -1
@@ -98,6 +99,8 @@ def _load():
         "qft_plan_pass_times": (I, [P, ctypes.POINTER(ctypes.c_double), I,
                                     ctypes.POINTER(ctypes.c_longlong)]),
         "qft_execute_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(P), I, P]),
+        "qft_execute_batch_ex": (I, [ctypes.POINTER(P), ctypes.POINTER(P), I, I, P]),
+        "qft_batch_status": (I, [ctypes.POINTER(P), ctypes.POINTER(P), I]),
         "qft_fill_random": (I, [P, I, I, I, ctypes.c_uint64, ctypes.c_uint64, P]),
         "qft_debug_pass_desc_size": (ctypes.c_size_t, []),
         "qft_debug_pass": (I, [I, I, I, I, ctypes.POINTER(Config), I, P, ctypes.c_size_t,
@@ -242,8 +245,7 @@ class Plan:
             pass
 
 
-def execute_batch(plans: Sequence[Plan], tensors, stream=None):
-    """One persistent launch over uneven transforms (plans[i] on tensors[i])."""
+def _batch_arrays(plans, tensors):
     if len(plans) != len(tensors):
         raise ValueError("plans and tensors differ in length")
     for p, t in zip(plans, tensors):
@@ -251,7 +253,23 @@ def execute_batch(plans: Sequence[Plan], tensors, stream=None):
     cnt = len(plans)
     ph = (ctypes.c_void_p * cnt)(*[p.handle.value for p in plans])
     tp = (ctypes.c_void_p * cnt)(*[t.data_ptr() for t in tensors])
-    _check(lib.qft_execute_batch(ph, tp, cnt, _stream_handle(stream)))
+    return ph, tp, cnt
+
+
+def execute_batch(plans: Sequence[Plan], tensors, stream=None, graph: bool = True):
+    """One persistent launch over uneven transforms (plans[i] on tensors[i]).
+
+    graph=True replays a captured HIP graph (captured on the first call for
+    this set of plans and tensors); graph=False launches directly."""
+    ph, tp, cnt = _batch_arrays(plans, tensors)
+    flags = 0 if graph else QFT_BATCH_EAGER
+    _check(lib.qft_execute_batch_ex(ph, tp, cnt, flags, _stream_handle(stream)))
+
+
+def batch_status(plans: Sequence[Plan], tensors):
+    """Raise if the cached batch launch for this set gave up on a wait."""
+    ph, tp, cnt = _batch_arrays(plans, tensors)
+    _check(lib.qft_batch_status(ph, tp, cnt))
 
 
 def fill_random(x, dist="gaussian", seed: int = 0, stream_id: int = 0, stream=None):
