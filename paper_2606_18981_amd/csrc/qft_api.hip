@@ -106,6 +106,9 @@ static qft_plan_t *make_plan(int n, int cutoff, int norm, int layout, const qft_
     return nullptr;
   }
   std::string err;
+  qft_config_t tuned;
+  if (!cfg && !(layout & QFT_SCHEDULE_GATES) && tune_table_lookup(n, cutoff, layout, &tuned))
+    cfg = &tuned;
   int rc = build_host_plan(n, cutoff, norm, layout, cfg, p->hp, err);
   if (rc != QFT_OK) {
     set_error(rc, err);

@@ -47,4 +47,6 @@ namespace qft {
 int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s);
 // drop cached batch launches that use this plan
 void batch_forget_plan(qft_plan_s *plan);
+// tuned configuration for a plan shape, if the tuning table has one
+bool tune_table_lookup(int n, int cutoff, int layout, qft_config_t *out);
 }

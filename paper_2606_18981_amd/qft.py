@@ -102,6 +102,15 @@ def _load():
         "qft_execute_batch_ex": (I, [ctypes.POINTER(P), ctypes.POINTER(P), I, I, P]),
         "qft_batch_status": (I, [ctypes.POINTER(P), ctypes.POINTER(P), I]),
         "qft_fill_random": (I, [P, I, I, I, ctypes.c_uint64, ctypes.c_uint64, P]),
+        "qft_tune": (I, [I, I, I, I, P, I, ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_double)]),
+        "qft_tune_batch": (I, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), I, I, I,
+                               ctypes.POINTER(P), I, ctypes.POINTER(Config),
+                               ctypes.POINTER(ctypes.c_double)]),
+        "qft_tune_lookup": (I, [I, I, I, ctypes.POINTER(Config)]),
+        "qft_tune_insert": (I, [I, I, I, ctypes.POINTER(Config), ctypes.c_double]),
+        "qft_tune_clear": (I, []),
+        "qft_tune_save": (I, [ctypes.c_char_p]),
+        "qft_tune_load": (I, [ctypes.c_char_p]),
         "qft_debug_pass_desc_size": (ctypes.c_size_t, []),
         "qft_debug_pass": (I, [I, I, I, I, ctypes.POINTER(Config), I, P, ctypes.c_size_t,
                                ctypes.POINTER(ctypes.c_int)]),
@@ -288,3 +297,60 @@ def fill_random(x, dist="gaussian", seed: int = 0, stream_id: int = 0, stream=No
     _check(lib.qft_fill_random(ctypes.c_void_p(x.data_ptr()), n, lay, d, seed, stream_id,
                                _stream_handle(stream)))
     return x
+
+
+# ---- autotuner ------------------------------------------------------------
+
+def _cfg_dict(c: Config) -> dict:
+    return {f: getattr(c, f) for f, _ in Config._fields_}
+
+
+def tune(n: int, cutoff: int = -1, norm="unitary", dtype="c64", order="natural",
+         data=None, reps: int = 3):
+    """Time the candidate configurations on `data` (a CUDA tensor of 2^n
+    elements, overwritten) and record the fastest in the tuning table."""
+    lay = layout_flags(dtype, order)
+    best = Config()
+    ms = ctypes.c_double(0)
+    _check(lib.qft_tune(n, cutoff, _norm(norm), lay, ctypes.c_void_p(data.data_ptr()), reps,
+                        ctypes.byref(best), ctypes.byref(ms)))
+    return _cfg_dict(best), ms.value
+
+
+def tune_batch(ns, cutoffs, tensors, norm="unitary", dtype="c64", order="natural", reps=3):
+    """One configuration for a whole batch (timed through the batched launch)."""
+    cnt = len(ns)
+    na = (ctypes.c_int * cnt)(*[int(v) for v in ns])
+    ka = (ctypes.c_int * cnt)(*[int(v) for v in cutoffs])
+    da = (ctypes.c_void_p * cnt)(*[t.data_ptr() for t in tensors])
+    best = Config()
+    ms = ctypes.c_double(0)
+    _check(lib.qft_tune_batch(na, ka, cnt, _norm(norm), layout_flags(dtype, order), da, reps,
+                              ctypes.byref(best), ctypes.byref(ms)))
+    return _cfg_dict(best), ms.value
+
+
+def tune_lookup(n, cutoff=-1, dtype="c64", order="natural"):
+    c = Config()
+    rc = lib.qft_tune_lookup(n, cutoff, layout_flags(dtype, order), ctypes.byref(c))
+    return _cfg_dict(c) if rc == QFT_OK else None
+
+
+def tune_insert(n, cutoff, dtype, order, config, ms=0.0):
+    c = _config(config)
+    _check(lib.qft_tune_insert(n, cutoff, layout_flags(dtype, order), ctypes.byref(c), ms))
+
+
+def tune_clear():
+    lib.qft_tune_clear()
+
+
+def tune_save(path):
+    _check(lib.qft_tune_save(str(path).encode()))
+
+
+def tune_load(path) -> int:
+    rc = lib.qft_tune_load(str(path).encode())
+    if rc < 0:
+        raise QftError(rc, last_error())
+    return rc
