@@ -51,6 +51,109 @@ def cpu_baseline(n_sample: int = 24):
     }
 
 
+def time_plan(torch, Q, plan, x, steps, warmup):
+    """Mean ms per execute (HIP events on the current stream)."""
+    for _ in range(warmup):
+        plan.execute(x)
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(steps):
+        plan.execute(x)
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / steps
+
+
+def bench_aqft(torch, Q, n, dtype, cutoffs, steps):
+    """Runtime of the n-qubit transform for each AQFT cutoff (and exact)."""
+    N = 1 << n
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    x = torch.empty(N, dtype=tdt, device="cuda")
+    Q.fill_random(x, "gaussian", seed=1003)
+    rows = []
+    for k in cutoffs:
+        plan = Q.Plan(n, k, "unitary", dtype, "natural")
+        ms = time_plan(torch, Q, plan, x, steps, 2)
+        rows.append({"cutoff": k, "ms": ms, "gflops_equiv": 5.0 * N * n / (ms * 1e-3) / 1e9,
+                     "hbm_gbs": plan.info.hbm_bytes / (ms * 1e-3) / 1e9,
+                     "gates_cr": plan.info.gates_cr})
+        plan.close()
+    del x
+    torch.cuda.empty_cache()
+    return rows
+
+
+def bench_batch(torch, Q, reps=10):
+    """512 uneven transforms: one persistent graph launch vs one launch each."""
+    from paper_2606_18981_amd import inputs as I
+    ns, cuts = I.batch_sizes(1004, count=512, lo=8, hi=20, aqft_frac=0.25, aqft_k=8)
+    plans, xs, cache = [], [], {}
+    for n, k in zip(ns.tolist(), cuts.tolist()):
+        if (n, k) not in cache:
+            cache[(n, k)] = Q.Plan(n, k, "unitary", "c64", "natural")
+        plans.append(cache[(n, k)])
+        t = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+        Q.fill_random(t, "uniform", seed=1004 + len(xs))
+        xs.append(t)
+    total_bytes = sum(p.info.hbm_bytes for p in plans)
+    elems = sum(1 << n for n in ns.tolist())
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    res = {"transforms": 512, "total_amplitudes": int(elems),
+           "algorithmic_hbm_bytes": int(total_bytes)}
+    for mode in ("graph", "eager", "per_launch"):
+        def run():
+            if mode == "per_launch":
+                for p, t in zip(plans, xs):
+                    p.execute(t)
+            else:
+                Q.execute_batch(plans, xs, graph=(mode == "graph"))
+        run()
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(reps):
+            run()
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / reps
+        res[mode] = {"ms": ms, "transforms_per_s": 512 / (ms * 1e-3),
+                     "hbm_gbs": total_bytes / (ms * 1e-3) / 1e9}
+    Q.batch_status(plans, xs)
+    res["speedup_graph_vs_per_launch"] = res["per_launch"]["ms"] / res["graph"]["ms"]
+    for p in cache.values():
+        p.close()
+    del xs
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_serve(torch, Q, seconds, rate=2000.0):
+    """Poisson request stream: continuous batching vs one transform at a time."""
+    from paper_2606_18981_amd import inputs as I
+    from paper_2606_18981_amd import serve as S
+    trace = I.served_trace(1005, rate=rate, duration=seconds, n_lo=10, n_hi=26)
+    reqs = S.requests_from_trace(trace)
+    out = {"requests": len(reqs), "rate_per_s": rate, "seconds": seconds,
+           "budget_bytes": 200 << 30}
+    for name, slots, streams in (("continuous", 64, 4), ("one_at_a_time", 1, 1)):
+        srv = S.Server(200 << 30, slots, streams)
+        srv.prepare(reqs)
+        res, st = srv.run(reqs)
+        summ = S.latency_summary(res)
+        summ.update({"completed": st["completed"], "failed": st["failed"],
+                     "peak_inflight": st["peak_inflight"],
+                     "peak_reserved_gb": st["peak_reserved_bytes"] / 1e9,
+                     "wall_s": st["wall_seconds"],
+                     "hbm_gbs": st["hbm_bytes"] / st["wall_seconds"] / 1e9})
+        out[name] = summ
+        srv.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,7 +162,10 @@ def main():
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
     ap.add_argument("--cutoff", type=int, default=-1)
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -152,7 +258,19 @@ def main():
     plan.close()
     del x
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        print("[bench] aqft sweep", file=sys.stderr, flush=True)
+        out["aqft_n28_c64"] = bench_aqft(torch, Q, 28, "c64", [-1, 6, 10, 14, 18], 10)
+        print("[bench] complex128", file=sys.stderr, flush=True)
+        out["exact_n28_c128"] = bench_aqft(torch, Q, 28, "c128", [-1], 10)[0]
+        print("[bench] batch", file=sys.stderr, flush=True)
+        out["batch_512"] = bench_batch(torch, Q)
+        print("[bench] serve", file=sys.stderr, flush=True)
+        out["serve"] = bench_serve(torch, Q, args.serve_seconds)
+        out["p50_ms"] = out["serve"]["continuous"].get("p50_ms")
+        out["p99_ms"] = out["serve"]["continuous"].get("p99_ms")
     if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 

@@ -60,6 +60,9 @@ typedef void *qft_stream_t; /* hipStream_t */
 #define QFT_SCHEDULE_FUSED 0x0 /* fused HBM passes (default)                  */
 #define QFT_SCHEDULE_GATES 0x4 /* one sweep per gate: H, controlled-R_m and
                                   SWAP in circuit order (Fig. 1), unfused     */
+#define QFT_PLAN_NO_WORKSPACE 0x8 /* the plan allocates no workspace: run it
+                                  with qft_execute_ws (qft_execute then fails
+                                  with QFT_ERR_POINTER if one is needed)      */
 
 #define QFT_CUTOFF_EXACT (-1) /* any cutoff < 0 or >= n-1 is exact            */
 #define QFT_MAX_QUBITS 31

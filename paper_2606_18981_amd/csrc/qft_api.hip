@@ -137,7 +137,7 @@ static qft_plan_t *make_plan(int n, int cutoff, int norm, int layout, const qft_
       return nullptr;
     }
   }
-  if (hp.ws_bytes) {
+  if (hp.ws_bytes && !(layout & QFT_PLAN_NO_WORKSPACE)) {
     e = hipMalloc(&p->d_ws, hp.ws_bytes);
     if (e != hipSuccess) {
       hip_error(e, "workspace allocation");
@@ -173,7 +173,8 @@ int qft_execute_ws(qft_plan_t *plan, void *dev_ptr, void *workspace, qft_stream_
   if ((uintptr_t)dev_ptr % plan->hp.elem_bytes)
     return set_error(QFT_ERR_POINTER, "data pointer is not aligned to the element size");
   if (plan->hp.ws_bytes && !workspace)
-    return set_error(QFT_ERR_POINTER, "this plan needs a workspace");
+    return set_error(QFT_ERR_POINTER,
+                     "this plan needs a workspace (pass one with qft_execute_ws)");
   if (workspace && (uintptr_t)workspace % plan->hp.elem_bytes)
     return set_error(QFT_ERR_POINTER, "workspace pointer is not aligned to the element size");
   int dev = -1;

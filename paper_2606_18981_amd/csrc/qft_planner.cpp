@@ -416,7 +416,7 @@ int build_host_plan(int n, int cutoff, int norm, int layout, const qft_config_t 
     err = "norm must be QFT_NORM_UNITARY, QFT_NORM_NONE or QFT_NORM_INV_N";
     return QFT_ERR_INVALID;
   }
-  if (layout & ~0x7) {
+  if (layout & ~0xF) {
     err = "unknown layout flag bits";
     return QFT_ERR_INVALID;
   }

@@ -220,7 +220,8 @@ int qft_server_prepare(qft_server_t *server, const qft_request_t *reqs, int coun
       return set_error(QFT_ERR_UNSUPPORTED, "the server runs fused-schedule plans");
     PlanKey k = server->key(r);
     if (server->plans.count(k)) continue;
-    qft_plan_t *p = qft_plan(r.n, r.cutoff, r.norm, r.layout);
+    // requests bring their own workspace from the server's pool
+    qft_plan_t *p = qft_plan(r.n, r.cutoff, r.norm, r.layout | QFT_PLAN_NO_WORKSPACE);
     if (!p) return QFT_ERR_INVALID;
     server->plans[k] = p;
   }

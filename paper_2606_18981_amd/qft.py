@@ -23,6 +23,7 @@ QFT_ORDER_NATURAL = 0x0
 QFT_ORDER_BITREV = 0x2
 QFT_SCHEDULE_FUSED = 0x0
 QFT_SCHEDULE_GATES = 0x4
+QFT_PLAN_NO_WORKSPACE = 0x8
 QFT_CUTOFF_EXACT = -1
 QFT_MAX_PASSES = 8
 QFT_RNG_GAUSSIAN = 0
@@ -188,10 +189,12 @@ class Plan:
     """A planned 2^n-point transform (owns device tables and workspace)."""
 
     def __init__(self, n: int, cutoff: int = -1, norm="unitary", dtype="c64",
-                 order="natural", schedule="fused", config=None):
+                 order="natural", schedule="fused", config=None, workspace: bool = True):
         self.n = n
         self.cutoff = cutoff
         self.layout = layout_flags(dtype, order, schedule)
+        if not workspace:
+            self.layout |= QFT_PLAN_NO_WORKSPACE
         self.c128 = bool(self.layout & QFT_C128)
         c = _config(config)
         h = lib.qft_plan_config(n, cutoff, _norm(norm), self.layout,
