@@ -166,6 +166,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline measurement")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="also time a plain device copy of the state (read + write of "
+                         "N*S bytes each) as the reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -255,6 +258,23 @@ def main():
             "algorithmic_bytes_per_launch": per_launch_bytes,
         },
     }
+    if args.copy_ref:
+        y = torch.empty_like(x)
+        ms_copy = None
+        for _ in range(3):
+            y.copy_(x)
+        cs = torch.cuda.Event(enable_timing=True)
+        ce = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        cs.record()
+        for _ in range(10):
+            y.copy_(x)
+        ce.record()
+        torch.cuda.synchronize()
+        ms_copy = cs.elapsed_time(ce) / 10
+        out["copy_ref"] = {"bytes_read": state_bytes, "bytes_written": state_bytes,
+                           "ms": ms_copy, "gbs": 2 * state_bytes / (ms_copy * 1e-3) / 1e9}
+        del y
     plan.close()
     del x
     torch.cuda.empty_cache()

@@ -1,0 +1,58 @@
+"""GPU tests of the autotuner: the tuned configuration is recorded, used by
+later plans, and gives oracle-correct results."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_18981_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2606_18981_amd import qft as Q
+    assert torch.cuda.is_available()
+    Q.tune_clear()
+    yield torch, Q
+    Q.tune_clear()
+
+
+def test_tune_shape_and_reuse(env, tmp_path):
+    torch, Q = env
+    n = 18
+    buf = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    Q.fill_random(buf, "gaussian", seed=3)
+    best, ms = Q.tune(n, -1, "unitary", "c64", "natural", data=buf, reps=2)
+    print(f"[gpu] tuned n={n}: {best} {ms:.4f} ms", flush=True)
+    assert ms > 0
+    assert Q.tune_lookup(n, -1, "c64") == best
+    plan = Q.Plan(n, -1, "unitary", "c64", "natural")
+    assert {f: getattr(plan.info.config, f) for f, _ in Q.Config._fields_} == best
+    x = I.gaussian(n, 4)
+    t = torch.from_numpy(x.astype(np.complex64)).cuda()
+    plan.execute(t)
+    torch.cuda.synchronize()
+    assert O.rel_l2(t.cpu().numpy().astype(np.complex128), O.qft_fused_targets(x)) <= 1e-5
+    plan.close()
+    path = tmp_path / "wisdom.jsonl"
+    Q.tune_save(path)
+    Q.tune_clear()
+    assert Q.tune_load(path) == 1
+    assert Q.tune_lookup(n, -1, "c64") == best
+
+
+def test_tune_batch(env):
+    torch, Q = env
+    ns, cuts = I.batch_sizes(1004, count=24, lo=8, hi=14, aqft_frac=0.25, aqft_k=8)
+    xs = [torch.empty(1 << int(n), dtype=torch.complex64, device="cuda") for n in ns]
+    for i, t in enumerate(xs):
+        Q.fill_random(t, "uniform", seed=10 + i)
+    best, ms = Q.tune_batch(ns.tolist(), cuts.tolist(), xs, reps=1)
+    print(f"[gpu] tuned batch: {best} {ms:.4f} ms", flush=True)
+    assert ms > 0
+    for n, k in zip(ns.tolist(), cuts.tolist()):
+        assert Q.tune_lookup(int(n), int(k), "c64") == best
+    Q.tune_clear()
