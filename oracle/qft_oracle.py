@@ -60,6 +60,7 @@ __all__ = [
     "aqft_matrix",
     "aqft_bins",
     "dft_bins",
+    "dft_library",
     "qft_fused_targets",
     "rel_l2",
     "max_err",
@@ -363,6 +364,23 @@ def dft_bins(x, bins, norm: str = "unitary") -> np.ndarray:
     out = np.array([np.sum(x * W[(j * kk) % N]) for kk in bins.tolist()],
                    dtype=np.complex128)
     return out * scale
+
+
+def dft_library(x, norm: str = "unitary", order: str = "natural", workers: int = -1):
+    """The exact DFT through a library FFT (scipy.fft, FP64), for full-size
+    references at large N.  The library routine is the special case that
+    tests/test_oracle.py checks against ``dft_naive``."""
+    import scipy.fft
+    x = np.asarray(x, dtype=np.complex128)
+    N = x.shape[0]
+    n = N.bit_length() - 1
+    y = scipy.fft.fft(x, workers=workers)
+    y *= norm_factor(n, norm) / math.sqrt(N)
+    if order == "bitrev":
+        out = np.empty_like(y)
+        out[bitrev_perm(n)] = y
+        return out
+    return y
 
 
 # ---------------------------------------------------------------------------

@@ -31,6 +31,14 @@ def test_naive_dft_is_numpy_fft(n):
     assert O.rel_l2(O.dft_naive(x, "inv_n"), np.fft.fft(x, norm="forward")) < TOL
 
 
+@pytest.mark.parametrize("n", [0, 1, 5, 10, 12])
+def test_library_fft_is_naive_dft(n):
+    x = I.gaussian(n, 300 + n)
+    for norm in O.NORMS:
+        for order in O.ORDERS:
+            assert O.rel_l2(O.dft_library(x, norm, order), O.dft_naive(x, norm, order)) < TOL
+
+
 @pytest.mark.parametrize("n", list(range(1, 11)))
 @pytest.mark.parametrize("norm", O.NORMS)
 def test_exact_circuit_is_dft(n, norm):
