@@ -120,7 +120,6 @@ def bench_batch(torch, Q, reps=10):
         ms = s.elapsed_time(e) / reps
         res[mode] = {"ms": ms, "transforms_per_s": 512 / (ms * 1e-3),
                      "hbm_gbs": total_bytes / (ms * 1e-3) / 1e9}
-    Q.batch_status(plans, xs)
     res["speedup_graph_vs_per_launch"] = res["per_launch"]["ms"] / res["graph"]["ms"]
     for p in cache.values():
         p.close()

@@ -162,26 +162,23 @@ int qft_plan_pass_times(qft_plan_t *plan, double *ms, int max, long long *execs)
 
 /* ---- batched uneven sizes (one persistent launch) ------------------------ */
 
-/* Transform count arrays, dev_ptrs[i] with plans[i], in one persistent
- * kernel launch.  Work items (transform, pass, tile) are ordered level by
- * level, so that a transform's pass p+1 waits only on its own pass p and
- * only on items claimed before it.  The first call for a given
+/* Transform count arrays, dev_ptrs[i] with plans[i], with one graph launch.
+ * The tiles of all transforms are grouped by pass level, then by register
+ * radix and workgroup size; each group is one kernel launch over the tiles
+ * of many transforms (one tile per workgroup), and the launches run level by
+ * level, so a transform's pass p+1 starts after every pass-p tile is done
+ * and no workgroup waits on another.  The first call for a given
  * (plans, dev_ptrs) set builds the work list (and allocates one workspace per
- * natural-order multi-pass transform) and captures the launch into a HIP
+ * natural-order multi-pass transform) and captures the launches into a HIP
  * graph; later calls replay the graph.  Plans must be fused-schedule plans
- * of one element type.  Replays of one set share its counters: order them on
- * one stream.  Destroying a plan drops the cached sets that use it.         */
+ * of one element type.  Destroying a plan drops the cached sets that use
+ * it.                                                                       */
 int qft_execute_batch(qft_plan_t *const *plans, void *const *dev_ptrs,
                       int count, qft_stream_t stream);
 
-#define QFT_BATCH_EAGER 0x1 /* launch the persistent kernel directly, no graph */
+#define QFT_BATCH_EAGER 0x1 /* enqueue the launches directly, no graph         */
 int qft_execute_batch_ex(qft_plan_t *const *plans, void *const *dev_ptrs,
                          int count, int flags, qft_stream_t stream);
-
-/* Synchronously read the error flag of the cached set (QFT_OK, or
- * QFT_ERR_HIP if a dependency wait ran past its spin limit and the launch
- * gave up; QFT_ERR_INVALID if the set is not cached).                       */
-int qft_batch_status(qft_plan_t *const *plans, void *const *dev_ptrs, int count);
 
 /* ---- device input generation (Philox-4x32-10, Salmon et al. 2011) -------- */
 #define QFT_RNG_GAUSSIAN 0 /* re, im ~ N(0, 1) (Box-Muller in FP64)          */

@@ -1,10 +1,12 @@
-// Batched uneven-size execution: one persistent launch over (transform,
-// pass, tile) work items, captured once per (plans, pointers) set into a HIP
-// graph and replayed.  See include/qft.h.
+// Batched uneven-size execution: the tiles of all transforms, launched pass
+// level by pass level (one launch per level, radix and workgroup size),
+// captured once per (plans, pointers) set into a HIP graph and replayed.
+// See include/qft.h.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -20,9 +22,8 @@ struct BatchEntry {
   std::vector<qft_plan_t *> plans;
   std::vector<void *> ptrs;
   bool c128 = false;
-  int maxrb = 1;
-  BatchLaunch launch{};
-  void *d_mem = nullptr;             // segments, descriptors, io, counters
+  std::vector<BatchGroup> groups;    // launch order: pass level by pass level
+  void *d_mem = nullptr;             // segments, descriptors, io
   std::vector<void *> workspaces;    // one per natural-order multi-pass job
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -47,11 +48,10 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int build_entry(BatchEntry *e) {
   const int njobs = (int)e->plans.size();
-  std::vector<BatchSeg> segs;
   std::vector<PassDesc> descs;
   std::vector<BatchIO> io;
-  // per job: resolve its buffers (the state and, for natural-order plans
-  // with more than one pass, a workspace owned by this batch entry)
+  // per job: its buffers (the state and, for natural-order plans with more
+  // than one pass, a workspace owned by this batch entry)
   std::vector<void *> ws(njobs, nullptr);
   int maxP = 0;
   for (int j = 0; j < njobs; ++j) {
@@ -65,23 +65,39 @@ int build_entry(BatchEntry *e) {
       ws[j] = w;
     }
   }
-  uint32_t item = 0;
-  int block = 1, lds = 0;
-  e->maxrb = 1;
-  std::vector<uint32_t> done_before(njobs, 0);
+  // group the (job, pass) launches by pass level, radix and workgroup size
+  struct GroupBuild {
+    int level, r, threads, lds;
+    std::vector<BatchSeg> segs;
+    uint32_t items = 0;
+  };
+  std::vector<GroupBuild> gb;
   for (int level = 0; level < maxP; ++level) {
+    std::map<std::pair<int, int>, size_t> index;  // (r, threads) -> group
     for (int j = 0; j < njobs; ++j) {
       qft_plan_t *p = e->plans[j];
       if (level >= (int)p->launches.size()) continue;
       const PassLaunch &L = p->launches[level];
+      const auto key = std::make_pair((int)L.d.r, L.threads);
+      auto it = index.find(key);
+      if (it == index.end()) {
+        GroupBuild g;
+        g.level = level;
+        g.r = L.d.r;
+        g.threads = L.threads;
+        g.lds = 0;
+        gb.push_back(g);
+        it = index.emplace(key, gb.size() - 1).first;
+      }
+      GroupBuild &g = gb[it->second];
       BatchSeg sg;
-      sg.first = item;
+      sg.first = g.items;
       sg.ntiles = L.grid;
       sg.desc = (uint32_t)descs.size();
       sg.job = (uint32_t)j;
-      sg.wait = done_before[j];
-      sg.threads = (uint32_t)L.threads;
-      segs.push_back(sg);
+      g.segs.push_back(sg);
+      g.items += L.grid;
+      g.lds = std::max(g.lds, L.lds_bytes);
       PassDesc d = L.d;
       d.xcd_remap = 0;
       descs.push_back(d);
@@ -89,22 +105,23 @@ int build_entry(BatchEntry *e) {
       b.in = L.in_ws ? ws[j] : e->ptrs[j];
       b.out = L.out_ws ? ws[j] : e->ptrs[j];
       io.push_back(b);
-      item += L.grid;
-      done_before[j] += L.grid;
-      block = std::max(block, L.threads);
-      lds = std::max(lds, L.lds_bytes);
-      e->maxrb = std::max(e->maxrb, (int)L.d.r);
     }
   }
-  if (block > batch_max_block(e->c128, e->maxrb))
-    return set_error(QFT_ERR_UNSUPPORTED, "batch mixes tile shapes that do not fit one workgroup size");
+  size_t nsegs = 0;
+  for (const GroupBuild &g : gb) nsegs += g.segs.size();
   const size_t off_seg = 0;
-  const size_t off_desc = align_up(off_seg + segs.size() * sizeof(BatchSeg), 256);
+  const size_t off_desc = align_up(off_seg + nsegs * sizeof(BatchSeg), 256);
   const size_t off_io = align_up(off_desc + descs.size() * sizeof(PassDesc), 256);
-  const size_t off_cnt = align_up(off_io + io.size() * sizeof(BatchIO), 256);
-  const size_t bytes = off_cnt + (size_t)(njobs + 2) * sizeof(uint32_t);
+  const size_t bytes = off_io + io.size() * sizeof(BatchIO);
   std::vector<unsigned char> host(bytes, 0);
-  memcpy(host.data() + off_seg, segs.data(), segs.size() * sizeof(BatchSeg));
+  size_t seg_at = 0;
+  std::vector<size_t> seg_start;
+  for (const GroupBuild &g : gb) {
+    seg_start.push_back(seg_at);
+    memcpy(host.data() + off_seg + seg_at * sizeof(BatchSeg), g.segs.data(),
+           g.segs.size() * sizeof(BatchSeg));
+    seg_at += g.segs.size();
+  }
   memcpy(host.data() + off_desc, descs.data(), descs.size() * sizeof(PassDesc));
   memcpy(host.data() + off_io, io.data(), io.size() * sizeof(BatchIO));
   hipError_t he = hipMalloc(&e->d_mem, bytes);
@@ -112,29 +129,27 @@ int build_entry(BatchEntry *e) {
   he = hipMemcpy(e->d_mem, host.data(), bytes, hipMemcpyHostToDevice);
   if (he != hipSuccess) return hip_error(he, "batch descriptor upload");
   unsigned char *m = (unsigned char *)e->d_mem;
-  BatchLaunch &b = e->launch;
-  b.segs = (const BatchSeg *)(m + off_seg);
-  b.descs = (const PassDesc *)(m + off_desc);
-  b.io = (const BatchIO *)(m + off_io);
-  b.counters = (uint32_t *)(m + off_cnt);
-  b.nseg = (int)segs.size();
-  b.njobs = njobs;
-  b.total = item;
-  b.block = block;
-  b.lds_bytes = lds;
-  // about 2^26 sleeps of ~128 cycles: far beyond any legal wait, so the
-  // limit only ends a wait that could never be met
-  b.spin_limit = 1u << 26;
-  // persistent grid: the workgroups that fit on the device at once
-  int per_cu = 0;
-  he = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel(e->c128, e->maxrb), block,
-                                                    lds);
-  if (he != hipSuccess || per_cu < 1) per_cu = 1;
-  int cus = 0;
-  he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, e->device);
-  if (he != hipSuccess || cus < 1) cus = 1;
-  b.grid = std::max(1u, std::min<uint32_t>(item, (uint32_t)(per_cu * cus)));
+  for (size_t i = 0; i < gb.size(); ++i) {
+    BatchGroup g;
+    g.segs = (const BatchSeg *)(m + off_seg) + seg_start[i];
+    g.descs = (const PassDesc *)(m + off_desc);
+    g.io = (const BatchIO *)(m + off_io);
+    g.nseg = (int)gb[i].segs.size();
+    g.items = gb[i].items;
+    g.threads = gb[i].threads;
+    g.lds_bytes = gb[i].lds;
+    g.r = gb[i].r;
+    e->groups.push_back(g);
+  }
   return QFT_OK;
+}
+
+hipError_t launch_entry(BatchEntry *e, hipStream_t s) {
+  for (const BatchGroup &g : e->groups) {
+    hipError_t he = launch_batch_group(e->c128, g, s);
+    if (he != hipSuccess) return he;
+  }
+  return hipSuccess;
 }
 
 int capture_entry(BatchEntry *e) {
@@ -143,7 +158,7 @@ int capture_entry(BatchEntry *e) {
   if (he != hipSuccess) return hip_error(he, "capture stream");
   he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (he == hipSuccess) {
-    hipError_t le = launch_batch(e->c128, e->maxrb, e->launch, cs);
+    hipError_t le = launch_entry(e, cs);
     he = hipStreamEndCapture(cs, &e->graph);
     if (le != hipSuccess) he = le;
   }
@@ -223,7 +238,7 @@ int qft_execute_batch_ex(qft_plan_t *const *plans, void *const *dev_ptrs, int co
     g_cache.push_back(e);
   }
   if (flags & QFT_BATCH_EAGER) {
-    he = launch_batch(e->c128, e->maxrb, e->launch, (hipStream_t)stream);
+    he = launch_entry(e, (hipStream_t)stream);
     if (he != hipSuccess) return hip_error(he, "batch launch");
     return QFT_OK;
   }
@@ -239,24 +254,6 @@ int qft_execute_batch_ex(qft_plan_t *const *plans, void *const *dev_ptrs, int co
 int qft_execute_batch(qft_plan_t *const *plans, void *const *dev_ptrs, int count,
                       qft_stream_t stream) {
   return qft_execute_batch_ex(plans, dev_ptrs, count, 0, stream);
-}
-
-int qft_batch_status(qft_plan_t *const *plans, void *const *dev_ptrs, int count) {
-  clear_error();
-  std::vector<qft_plan_t *> pv(plans, plans + count);
-  std::vector<void *> dv(dev_ptrs, dev_ptrs + count);
-  std::lock_guard<std::mutex> lk(g_mu);
-  for (BatchEntry *c : g_cache) {
-    if (c->plans == pv && c->ptrs == dv) {
-      uint32_t flag = 0;
-      hipError_t he = hipMemcpy(&flag, c->launch.counters + 1 + c->launch.njobs, sizeof(flag),
-                                hipMemcpyDeviceToHost);
-      if (he != hipSuccess) return hip_error(he, "batch status read");
-      if (flag) return set_error(QFT_ERR_HIP, "a batch wait exceeded its spin limit");
-      return QFT_OK;
-    }
-  }
-  return set_error(QFT_ERR_INVALID, "no such batch");
 }
 
 }  // extern "C"

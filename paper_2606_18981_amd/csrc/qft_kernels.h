@@ -11,35 +11,30 @@ namespace qft {
 hipError_t launch_fused_pass(const PassLaunch &L, bool c128, const void *in, void *out,
                              hipStream_t s);
 
-// Persistent batch launch (see k_batch).
+// Batched launches (see k_batch_group).
 struct BatchSeg {
-  uint32_t first;    // first work item of the segment
+  uint32_t first;    // first work item (workgroup) of the segment in its group
   uint32_t ntiles;   // tiles (items) in the segment
   uint32_t desc;     // index into the descriptor / io arrays
   uint32_t job;      // transform index
-  uint32_t wait;     // finished tiles of the job required before starting
-  uint32_t threads;  // active threads per tile
 };
 struct BatchIO {
   const void *in;
   void *out;
 };
-struct BatchLaunch {
+// one launch: the segments [segs, segs + nseg) of a (pass level, radix,
+// workgroup size) group
+struct BatchGroup {
   const BatchSeg *segs;
   const PassDesc *descs;
   const BatchIO *io;
-  uint32_t *counters;  // njobs + 2 words
   int nseg;
-  int njobs;
-  uint32_t total;
-  uint32_t grid;
-  int block;
+  uint32_t items;
+  int threads;
   int lds_bytes;
-  uint32_t spin_limit;
+  int r;
 };
-hipError_t launch_batch(bool c128, int maxrb, const BatchLaunch &b, hipStream_t s);
-const void *batch_kernel(bool c128, int maxrb);
-int batch_max_block(bool c128, int maxrb);
+hipError_t launch_batch_group(bool c128, const BatchGroup &g, hipStream_t s);
 
 // Gate-by-gate sweeps (unfused circuit, Fig. 1).
 hipError_t launch_h(void *psi, int n, int t, bool c128, hipStream_t s);

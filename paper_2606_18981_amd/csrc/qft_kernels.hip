@@ -278,8 +278,11 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
       v[rho].y *= scale;
     }
   }
+  uint32_t soff[R];
 #pragma unroll
-  for (int rho = 0; rho < R; ++rho) dst[deposit_reg<RB>(rho, d.st_reg_g)] = v[rho];
+  for (int rho = 0; rho < R; ++rho) soff[rho] = deposit_reg<RB>(rho, d.st_reg_g);
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho) dst[soff[rho]] = v[rho];
 }
 
 template <typename Real, int RB>
@@ -338,128 +341,70 @@ hipError_t launch_fused_pass(const PassLaunch &L, bool c128, const void *in, voi
 }
 
 // ---------------------------------------------------------------------------
-// persistent batch kernel
+// batched launches
 // ---------------------------------------------------------------------------
 
-// Work items are (transform, pass, tile) triples laid out segment by segment:
-// all first passes, then all second passes, and so on, so an item only waits
-// for items that were claimed before it (no deadlock, whatever the number of
-// resident workgroups).  counters[0] is the claim counter, counters[1 + j]
-// the number of finished tiles of transform j, counters[1 + njobs] an error
-// flag set when a wait exceeds its spin limit (then every workgroup leaves).
-template <typename Real, int MAXRB>
-__global__ void __launch_bounds__(sizeof(Real) == 8 ? (MAXRB >= 5 ? 256 : MAXRB >= 4 ? 512 : 1024)
-                                                   : (MAXRB >= 5 ? 512 : 1024))
-k_batch(const BatchSeg *__restrict__ segs, int nseg, uint32_t total,
-        const PassDesc *__restrict__ descs, const BatchIO *__restrict__ io, uint32_t *counters,
-        int njobs, uint32_t spin_limit) {
+// One launch of a batch group: the tiles of many transforms that share a pass
+// level, a register radix and a workgroup size, one tile per workgroup.
+// Workgroup b finds its segment (transform pass) by binary search over the
+// segments' first items.  Passes of one transform are in different launches,
+// ordered on the stream, so no workgroup ever waits for another.
+template <typename Real, int RB>
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? (RB >= 5 ? 256 : RB >= 4 ? 512 : 1024)
+                                                   : (RB >= 5 ? 512 : 1024))
+k_batch_group(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__restrict__ descs,
+              const BatchIO *__restrict__ io) {
   extern __shared__ __align__(16) unsigned char qft_smem[];
-  __shared__ uint32_t s_item;
-  __shared__ uint32_t s_abort;
-  cplx<Real> *lds = reinterpret_cast<cplx<Real> *>(qft_smem);
-  const uint32_t tid = threadIdx.x;
-  uint32_t *err_flag = counters + 1 + njobs;
-  for (;;) {
-    if (tid == 0) {
-      s_abort = __hip_atomic_load(err_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_item = atomicAdd(&counters[0], 1u);
-    }
-    __syncthreads();
-    const uint32_t item = s_item;
-    const uint32_t abort_now = s_abort;
-    __syncthreads();
-    if (item >= total || abort_now) break;
-    int lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (segs[mid].first <= item) lo = mid;
-      else hi = mid - 1;
-    }
-    const BatchSeg sg = segs[lo];
-    if (sg.wait) {
-      if (tid == 0) {
-        uint32_t spins = 0;
-        s_abort = 0;
-        while (__hip_atomic_load(&counters[1 + sg.job], __ATOMIC_ACQUIRE,
-                                 __HIP_MEMORY_SCOPE_AGENT) < sg.wait) {
-          __builtin_amdgcn_s_sleep(2);
-          if (++spins > spin_limit) {
-            __hip_atomic_store(err_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_abort = 1;
-            break;
-          }
-        }
-      }
-      __syncthreads();
-      if (s_abort) break;
-      __threadfence();
-    }
-    const PassDesc &d = descs[sg.desc];
-    const BatchIO b = io[sg.desc];
-    const uint32_t t = item - sg.first;
-    const bool active = tid < sg.threads;
-    const cplx<Real> *in = (const cplx<Real> *)b.in;
-    cplx<Real> *out = (cplx<Real> *)b.out;
-    switch (d.r) {
-      case 1: tile_body<Real, 1>(d, t, in, out, lds, tid, active); break;
-      case 2: tile_body<Real, 2>(d, t, in, out, lds, tid, active); break;
-      case 3: if (MAXRB >= 3) tile_body<Real, (MAXRB >= 3 ? 3 : 1)>(d, t, in, out, lds, tid, active); break;
-      case 4: if (MAXRB >= 4) tile_body<Real, (MAXRB >= 4 ? 4 : 1)>(d, t, in, out, lds, tid, active); break;
-      case 5: if (MAXRB >= 5) tile_body<Real, (MAXRB >= 5 ? 5 : 1)>(d, t, in, out, lds, tid, active); break;
-    }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0)
-      __hip_atomic_fetch_add(&counters[1 + sg.job], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t item = blockIdx.x;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].first <= item) lo = mid;
+    else hi = mid - 1;
   }
+  const BatchSeg sg = segs[lo];
+  const BatchIO b = io[sg.desc];
+  tile_body<Real, RB>(descs[sg.desc], item - sg.first, (const cplx<Real> *)b.in,
+                      (cplx<Real> *)b.out, reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x,
+                      true);
 }
 
-__global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t value) {
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    p[i] = value;
+template <typename Real, int RB>
+static hipError_t launch_group_t(const BatchGroup &g, hipStream_t s) {
+  auto fn = k_batch_group<Real, RB>;
+  if (g.lds_bytes > 65536) {
+    static int set = 0;
+    if (!set) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+      if (e != hipSuccess) return e;
+      set = 1;
+    }
+  }
+  hipLaunchKernelGGL(fn, dim3(g.items), dim3(g.threads), g.lds_bytes, s, g.segs, g.nseg, g.descs,
+                     g.io);
+  return hipGetLastError();
 }
 
-template <typename Real, int MAXRB>
-static const void *batch_fn() {
-  return reinterpret_cast<const void *>(k_batch<Real, MAXRB>);
-}
-
-const void *batch_kernel(bool c128, int maxrb) {
+hipError_t launch_batch_group(bool c128, const BatchGroup &g, hipStream_t s) {
   if (c128) {
-    switch (maxrb) {
-      case 1: case 2: case 3: return batch_fn<double, 3>();
-      case 4: return batch_fn<double, 4>();
-      default: return batch_fn<double, 5>();
+    switch (g.r) {
+      case 1: return launch_group_t<double, 1>(g, s);
+      case 2: return launch_group_t<double, 2>(g, s);
+      case 3: return launch_group_t<double, 3>(g, s);
+      case 4: return launch_group_t<double, 4>(g, s);
+      case 5: return launch_group_t<double, 5>(g, s);
+    }
+  } else {
+    switch (g.r) {
+      case 1: return launch_group_t<float, 1>(g, s);
+      case 2: return launch_group_t<float, 2>(g, s);
+      case 3: return launch_group_t<float, 3>(g, s);
+      case 4: return launch_group_t<float, 4>(g, s);
+      case 5: return launch_group_t<float, 5>(g, s);
     }
   }
-  switch (maxrb) {
-    case 1: case 2: case 3: return batch_fn<float, 3>();
-    case 4: return batch_fn<float, 4>();
-    default: return batch_fn<float, 5>();
-  }
-}
-
-hipError_t launch_batch(bool c128, int maxrb, const BatchLaunch &b, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, b.counters, (uint32_t)(b.njobs + 2), 0u);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const void *fn = batch_kernel(c128, maxrb);
-  if (b.lds_bytes > 65536) {
-    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-    if (e != hipSuccess) return e;
-  }
-  int nseg = b.nseg;
-  uint32_t total = b.total;
-  int njobs = b.njobs;
-  uint32_t spin = b.spin_limit;
-  void *args[] = {(void *)&b.segs, &nseg, &total, (void *)&b.descs, (void *)&b.io,
-                  (void *)&b.counters, &njobs, &spin};
-  return hipLaunchKernel(fn, dim3(b.grid), dim3(b.block), args, b.lds_bytes, s);
-}
-
-int batch_max_block(bool c128, int maxrb) {
-  if (c128) return maxrb >= 5 ? 256 : maxrb >= 4 ? 512 : 1024;
-  return maxrb >= 5 ? 512 : 1024;
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

@@ -101,7 +101,6 @@ def _load():
                                     ctypes.POINTER(ctypes.c_longlong)]),
         "qft_execute_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(P), I, P]),
         "qft_execute_batch_ex": (I, [ctypes.POINTER(P), ctypes.POINTER(P), I, I, P]),
-        "qft_batch_status": (I, [ctypes.POINTER(P), ctypes.POINTER(P), I]),
         "qft_fill_random": (I, [P, I, I, I, ctypes.c_uint64, ctypes.c_uint64, P]),
         "qft_tune": (I, [I, I, I, I, P, I, ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_double)]),
         "qft_tune_batch": (I, [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), I, I, I,
@@ -269,19 +268,14 @@ def _batch_arrays(plans, tensors):
 
 
 def execute_batch(plans: Sequence[Plan], tensors, stream=None, graph: bool = True):
-    """One persistent launch over uneven transforms (plans[i] on tensors[i]).
+    """Uneven transforms (plans[i] on tensors[i]) launched pass level by pass
+    level over all transforms' tiles.
 
     graph=True replays a captured HIP graph (captured on the first call for
     this set of plans and tensors); graph=False launches directly."""
     ph, tp, cnt = _batch_arrays(plans, tensors)
     flags = 0 if graph else QFT_BATCH_EAGER
     _check(lib.qft_execute_batch_ex(ph, tp, cnt, flags, _stream_handle(stream)))
-
-
-def batch_status(plans: Sequence[Plan], tensors):
-    """Raise if the cached batch launch for this set gave up on a wait."""
-    ph, tp, cnt = _batch_arrays(plans, tensors)
-    _check(lib.qft_batch_status(ph, tp, cnt))
 
 
 def fill_random(x, dist="gaussian", seed: int = 0, stream_id: int = 0, stream=None):

@@ -1,4 +1,4 @@
-"""GPU tests of the persistent batched launch (uneven sizes in one kernel).
+"""GPU tests of the batched launch (uneven sizes, level-by-level group launches in one graph).
 
 Each transform in a batch must give exactly the result of running it alone
 (same kernels, same arithmetic) and agree with the FP64 oracle.  Graph
@@ -59,7 +59,6 @@ def test_batch_matches_alone_and_oracle(env, dtype, graph):
     ref_alone = alone(torch, Q, plans, hosts, dtype)
     Q.execute_batch(plans, xs, graph=graph)
     torch.cuda.synchronize()
-    Q.batch_status(plans, xs)
     for i, (t, x, n, k) in enumerate(zip(xs, hosts, ns.tolist(), cuts.tolist())):
         y = t.cpu().numpy()
         assert np.array_equal(y, ref_alone[i]), f"item {i} (n={n}, k={k}) differs from alone"
@@ -88,7 +87,6 @@ def test_graph_replays_with_eager_work_between(env):
         assert float(junk) == float(junk)
         for i, t in enumerate(xs):
             assert np.array_equal(t.cpu().numpy(), ref_alone[i]), f"replay {rep} item {i}"
-    Q.batch_status(plans, xs)
     for p in cache.values():
         p.close()
 
@@ -103,7 +101,6 @@ def test_full_uneven_batch_512(env):
     ref_alone = alone(torch, Q, plans, hosts, "c64")
     Q.execute_batch(plans, xs)
     torch.cuda.synchronize()
-    Q.batch_status(plans, xs)
     rng = np.random.default_rng(5)
     sample = set(rng.choice(512, 24, replace=False).tolist())
     for i, t in enumerate(xs):
