@@ -17,6 +17,13 @@
 #pragma once
 #include <stdint.h>
 
+#ifndef __HIPCC__
+#ifndef __host__
+#define __host__
+#define __device__
+#endif
+#endif
+
 namespace qft {
 
 constexpr int kMaxTile = 15;   // max tile bits
@@ -24,43 +31,52 @@ constexpr int kMaxRadix = 5;   // max register bits (32 elements per thread)
 constexpr int kMaxGroups = 15; // register groups per pass
 constexpr int kMaxPasses = 8;
 
+// Bit positions (0..31) are stored four per 32-bit word, so that device code
+// reads them with scalar loads at wave-uniform indices and extracts bytes.
+__host__ __device__ inline uint32_t pos_get(const uint32_t *w, int i) {
+  return (w[i >> 2] >> ((i & 3) * 8)) & 0xffu;
+}
+inline void pos_set(uint32_t *w, int i, uint32_t v) {
+  const int sh = (i & 3) * 8;
+  w[i >> 2] = (w[i >> 2] & ~(0xffu << sh)) | ((v & 0xffu) << sh);
+}
+
 // Register/thread mapping of one group of stages.
 // Element of thread `tid`, register `rho`:
-//   e = deposit(tid, thr_pos) | deposit(rho, reg_pos).
+//   e = deposit(tid, thr) | deposit(rho, reg).
 struct GroupMap {
-  uint8_t reg_pos[kMaxRadix];  // e-position of register bit q
-  uint8_t thr_pos[kMaxTile];   // e-position of thread-id bit b
-  int8_t jbase;                // local pass bit held by register bit 0
-  int8_t nst;                  // stages (targets) applied in this group
+  uint32_t reg_w[2];  // e-position of register bit q (packed)
+  uint32_t thr_w[4];  // e-position of thread-id bit b (packed)
+  int32_t jbase;      // local pass bit held by register bit 0
+  int32_t nst;        // stages (targets) applied in this group
 };
 
 struct PassDesc {
   // geometry
-  uint8_t n;        // qubits of the transform
-  uint8_t T;        // tile bits
-  uint8_t r;        // register bits (R = 2^r)
-  uint8_t m;        // pass bits
-  uint8_t pbase;    // e-position of local pass bit 0
-  uint8_t lo;       // target qubit of local pass bit 0
-  uint8_t ngroups;  // register groups
-  uint8_t reverse;  // 1: output index = rev_n(input index)
-  uint8_t ext_tw;   // 1: apply the diagonal of controls below the pass
-  uint8_t aqft;     // 1: cutoff < n - 1
-  int8_t k;         // effective cutoff (max control-target distance kept)
-  uint8_t nfree;    // non-tile index bits
-  uint8_t MI;       // internal twiddle table: w_{2^MI}^y, y < 2^(MI-1)
-  uint8_t L;        // split of the two-level w_N table
-  uint8_t xcd_remap;// 1: XCD-aware tile order
-  uint8_t pad_;
+  int32_t n;        // qubits of the transform
+  int32_t T;        // tile bits
+  int32_t r;        // register bits (R = 2^r)
+  int32_t m;        // pass bits
+  int32_t pbase;    // e-position of local pass bit 0
+  int32_t lo;       // target qubit of local pass bit 0
+  int32_t ngroups;  // register groups
+  int32_t reverse;  // 1: output index = rev_n(input index)
+  int32_t ext_tw;   // 1: apply the diagonal of controls below the pass
+  int32_t aqft;     // 1: cutoff < n - 1
+  int32_t k;        // effective cutoff (max control-target distance kept)
+  int32_t nfree;    // non-tile index bits
+  int32_t MI;       // internal twiddle table: w_{2^MI}^y, y < 2^(MI-1)
+  int32_t L;        // split of the two-level w_N table
+  int32_t xcd_remap;// 1: XCD-aware tile order
   uint32_t ntiles;
-  uint8_t gpos[kMaxTile];     // global index bit of e-position q
-  uint8_t free_pos[32];       // global positions of the non-tile bits, ascending
+  uint32_t gpos_w[4];   // global index bit of e-position q (packed)
+  uint32_t free_w[8];   // global positions of the non-tile bits, ascending
   // global (input / output) bit positions for the load group (group 0) and
   // the store group (last group)
-  uint8_t ld_thr_g[kMaxTile];
-  uint8_t ld_reg_g[kMaxRadix];
-  uint8_t st_thr_g[kMaxTile];
-  uint8_t st_reg_g[kMaxRadix];
+  uint32_t ld_thr_w[4];
+  uint32_t ld_reg_w[2];
+  uint32_t st_thr_w[4];
+  uint32_t st_reg_w[2];
   GroupMap grp[kMaxGroups];
   double scale;               // folded butterfly normalisation / output norm
   const void *tw_int;         // w_{2^MI}^y, y < 2^(MI-1)

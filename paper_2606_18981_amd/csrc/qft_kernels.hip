@@ -55,18 +55,18 @@ __host__ __device__ __forceinline__ uint32_t lds_swizzle(uint32_t e) {
   return e ^ (h & ((1u << SW) - 1u));
 }
 
-__device__ __forceinline__ uint32_t deposit_tid(uint32_t tid, const uint8_t *pos, int nb) {
+__device__ __forceinline__ uint32_t deposit_tid(uint32_t tid, const uint32_t *pos, int nb) {
   uint32_t e = 0;
-  for (int b = 0; b < nb; ++b) e |= ((tid >> b) & 1u) << pos[b];
+  for (int b = 0; b < nb; ++b) e |= ((tid >> b) & 1u) << pos_get(pos, b);
   return e;
 }
 
 template <int RB>
-__device__ __forceinline__ uint32_t deposit_reg(int rho, const uint8_t *pos) {
+__device__ __forceinline__ uint32_t deposit_reg(int rho, const uint32_t *pos) {
   uint32_t o = 0;
 #pragma unroll
   for (int q = 0; q < RB; ++q)
-    if ((rho >> q) & 1) o |= 1u << pos[q];
+    if ((rho >> q) & 1) o |= 1u << pos_get(pos, q);
   return o;
 }
 
@@ -179,13 +179,13 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
   constexpr int R = 1 << RB;
   const int TR = d.T - RB;
   uint32_t base = 0;
-  for (int b = 0; b < d.nfree; ++b) base |= ((tile >> b) & 1u) << d.free_pos[b];
+  for (int b = 0; b < d.nfree; ++b) base |= ((tile >> b) & 1u) << pos_get(d.free_w, b);
 
   C v[R];
   if (active) {
-    const C *src = in + (base | deposit_tid(tid, d.ld_thr_g, TR));
+    const C *src = in + (base | deposit_tid(tid, d.ld_thr_w, TR));
 #pragma unroll
-    for (int rho = 0; rho < R; ++rho) v[rho] = src[deposit_reg<RB>(rho, d.ld_reg_g)];
+    for (int rho = 0; rho < R; ++rho) v[rho] = src[deposit_reg<RB>(rho, d.ld_reg_w)];
   } else {
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) v[rho] = C{(Real)0, (Real)0};
@@ -195,21 +195,21 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
   const int MI1 = d.MI - 1;
   for (int gi = 0; gi < d.ngroups; ++gi) {
     const GroupMap &G = d.grp[gi];
-    const uint32_t e_thr = deposit_tid(tid, G.thr_pos, TR);
+    const uint32_t e_thr = deposit_tid(tid, G.thr_w, TR);
     if (gi > 0) {
       const GroupMap &P = d.grp[gi - 1];
       if (active) {
-        const uint32_t sp = lds_swizzle<Real>(deposit_tid(tid, P.thr_pos, TR));
+        const uint32_t sp = lds_swizzle<Real>(deposit_tid(tid, P.thr_w, TR));
 #pragma unroll
         for (int rho = 0; rho < R; ++rho)
-          lds[sp ^ lds_swizzle<Real>(deposit_reg<RB>(rho, P.reg_pos))] = v[rho];
+          lds[sp ^ lds_swizzle<Real>(deposit_reg<RB>(rho, P.reg_w))] = v[rho];
       }
       __syncthreads();
       if (active) {
         const uint32_t sg = lds_swizzle<Real>(e_thr);
 #pragma unroll
         for (int rho = 0; rho < R; ++rho)
-          v[rho] = lds[sg ^ lds_swizzle<Real>(deposit_reg<RB>(rho, G.reg_pos))];
+          v[rho] = lds[sg ^ lds_swizzle<Real>(deposit_reg<RB>(rho, G.reg_w))];
       }
       __syncthreads();
     }
@@ -237,14 +237,14 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
 
   const Real scale = (Real)d.scale;
   const uint32_t obase = d.reverse ? rev_bits(base, d.n) : base;
-  C *dst = out + (obase | deposit_tid(tid, d.st_thr_g, TR));
+  C *dst = out + (obase | deposit_tid(tid, d.st_thr_w, TR));
   if (d.ext_tw) {
     // diagonal of the controlled phases whose controls lie below the pass:
     // w_N^E with E = sum over set pass bits j of trunc_{lo+j-k}(vv) 2^{n-1-lo-j}
     // (vv = index bits below the pass).  All register bits are pass bits here,
     // so E = E_thr + sum over set register bits q of c_q.
     const uint32_t nmask = d.n >= 32 ? 0xffffffffu : ((1u << d.n) - 1u);
-    const uint32_t g = base | deposit_tid(tid, d.st_thr_g, TR);
+    const uint32_t g = base | deposit_tid(tid, d.st_thr_w, TR);
     const uint32_t vv = g & ((1u << d.lo) - 1u);
     const uint32_t pt = (g >> d.lo) & ((1u << d.m) - 1u);
     uint32_t Et = 0;
@@ -262,7 +262,7 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
     C f[RB];
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
-      const int j = d.st_reg_g[q] - d.lo;
+      const int j = (int)pos_get(d.st_reg_w, q) - d.lo;
       const int s = d.lo + j - d.k;
       const uint32_t tv = (!d.aqft || s <= 0) ? vv : (s >= d.lo ? 0u : ((vv >> s) << s));
       f[q] = omega_n<Real>(d, (tv << (d.n - 1 - d.lo - j)) & nmask);
@@ -280,7 +280,7 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
   }
   uint32_t soff[R];
 #pragma unroll
-  for (int rho = 0; rho < R; ++rho) soff[rho] = deposit_reg<RB>(rho, d.st_reg_g);
+  for (int rho = 0; rho < R; ++rho) soff[rho] = deposit_reg<RB>(rho, d.st_reg_w);
 #pragma unroll
   for (int rho = 0; rho < R; ++rho) dst[soff[rho]] = v[rho];
 }

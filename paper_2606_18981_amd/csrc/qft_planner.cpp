@@ -115,10 +115,10 @@ void build_groups(PassLaunch &L, const PassGeom &g, int r, int n) {
     }
     GroupMap gm;
     memset(&gm, 0, sizeof(gm));
-    for (int q = 0; q < r; ++q) gm.reg_pos[q] = (uint8_t)regs[q];
-    for (size_t b = 0; b < thr.size(); ++b) gm.thr_pos[b] = (uint8_t)thr[b];
-    gm.jbase = (int8_t)bot;
-    gm.nst = (int8_t)nst;
+    for (int q = 0; q < r; ++q) pos_set(gm.reg_w, q, regs[q]);
+    for (size_t b = 0; b < thr.size(); ++b) pos_set(gm.thr_w, (int)b, thr[b]);
+    gm.jbase = bot;
+    gm.nst = nst;
     groups.push_back(gm);
     thr_orders.push_back(thr);
   }
@@ -130,24 +130,24 @@ void build_groups(PassLaunch &L, const PassGeom &g, int r, int n) {
     std::stable_sort(by_out.begin(), by_out.end(), [&](int a, int b) { return outpos[a] < outpos[b]; });
     if (by_out != thr) {
       GroupMap gm = groups[0];
-      for (size_t b = 0; b < by_out.size(); ++b) gm.thr_pos[b] = (uint8_t)by_out[b];
+      for (size_t b = 0; b < by_out.size(); ++b) pos_set(gm.thr_w, (int)b, by_out[b]);
       gm.nst = 0;
       gm.jbase = 0;
       groups.push_back(gm);
     }
   }
-  d.ngroups = (uint8_t)groups.size();
+  d.ngroups = (int)groups.size();
   for (size_t i = 0; i < groups.size(); ++i) d.grp[i] = groups[i];
-  for (int q = 0; q < T; ++q) d.gpos[q] = (uint8_t)gpos[q];
+  for (int q = 0; q < T; ++q) pos_set(d.gpos_w, q, gpos[q]);
   const GroupMap &g0 = groups.front();
   const GroupMap &gl = groups.back();
   for (int b = 0; b < T - r; ++b) {
-    d.ld_thr_g[b] = (uint8_t)gpos[g0.thr_pos[b]];
-    d.st_thr_g[b] = (uint8_t)outpos[gl.thr_pos[b]];
+    pos_set(d.ld_thr_w, b, gpos[pos_get(g0.thr_w, b)]);
+    pos_set(d.st_thr_w, b, outpos[pos_get(gl.thr_w, b)]);
   }
   for (int q = 0; q < r; ++q) {
-    d.ld_reg_g[q] = (uint8_t)gpos[g0.reg_pos[q]];
-    d.st_reg_g[q] = (uint8_t)outpos[gl.reg_pos[q]];
+    pos_set(d.ld_reg_w, q, gpos[pos_get(g0.reg_w, q)]);
+    pos_set(d.st_reg_w, q, outpos[pos_get(gl.reg_w, q)]);
   }
 }
 
@@ -283,26 +283,26 @@ int plan_fused(HostPlan &p, std::string &err) {
     const int Te = (int)g.spec_g.size() + g.m;
     int r = std::min(r_cfg, Te);
     if (g.lo > 0) r = std::min(r, g.m);
-    d.n = (uint8_t)n;
-    d.T = (uint8_t)Te;
-    d.r = (uint8_t)r;
-    d.m = (uint8_t)g.m;
-    d.pbase = (uint8_t)g.spec_g.size();
-    d.lo = (uint8_t)g.lo;
+    d.n = n;
+    d.T = Te;
+    d.r = r;
+    d.m = g.m;
+    d.pbase = (int)g.spec_g.size();
+    d.lo = g.lo;
     d.reverse = g.reverse ? 1 : 0;
     d.ext_tw = g.lo > 0 ? 1 : 0;
     d.aqft = p.keff < n - 1 ? 1 : 0;
-    d.k = (int8_t)p.keff;
-    d.MI = (uint8_t)MI;
-    d.L = (uint8_t)p.L;
+    d.k = p.keff;
+    d.MI = MI;
+    d.L = p.L;
     build_groups(L, g, r, n);
     // non-tile bits, ascending
     std::vector<int> in_tile(n, 0);
-    for (int q = 0; q < Te; ++q) in_tile[d.gpos[q]] = 1;
+    for (int q = 0; q < Te; ++q) in_tile[pos_get(d.gpos_w, q)] = 1;
     int nf = 0;
     for (int b = 0; b < n; ++b)
-      if (!in_tile[b]) d.free_pos[nf++] = (uint8_t)b;
-    d.nfree = (uint8_t)nf;
+      if (!in_tile[b]) pos_set(d.free_w, nf++, b);
+    d.nfree = nf;
     d.ntiles = 1u << nf;
     d.xcd_remap = (d.ntiles >= 8) ? 1 : 0;
     d.scale = scales[i];

@@ -15,32 +15,42 @@ import numpy as np
 
 from paper_2606_18981_amd import qft as Q
 
-u8 = ctypes.c_uint8
-i8 = ctypes.c_int8
 
 MAX_TILE = 15
 MAX_RADIX = 5
 MAX_GROUPS = 15
 
 
+u32 = ctypes.c_uint32
+i32 = ctypes.c_int32
+
+
 class GroupMap(ctypes.Structure):
-    _fields_ = [("reg_pos", u8 * MAX_RADIX), ("thr_pos", u8 * MAX_TILE),
-                ("jbase", i8), ("nst", i8)]
+    _fields_ = [("reg_w", u32 * 2), ("thr_w", u32 * 4), ("jbase", i32), ("nst", i32)]
 
 
 class PassDesc(ctypes.Structure):
     _fields_ = [
-        ("n", u8), ("T", u8), ("r", u8), ("m", u8), ("pbase", u8), ("lo", u8),
-        ("ngroups", u8), ("reverse", u8), ("ext_tw", u8), ("aqft", u8), ("k", i8),
-        ("nfree", u8), ("MI", u8), ("L", u8), ("xcd_remap", u8), ("pad_", u8),
-        ("ntiles", ctypes.c_uint32),
-        ("gpos", u8 * MAX_TILE), ("free_pos", u8 * 32),
-        ("ld_thr_g", u8 * MAX_TILE), ("ld_reg_g", u8 * MAX_RADIX),
-        ("st_thr_g", u8 * MAX_TILE), ("st_reg_g", u8 * MAX_RADIX),
+        ("n", i32), ("T", i32), ("r", i32), ("m", i32), ("pbase", i32), ("lo", i32),
+        ("ngroups", i32), ("reverse", i32), ("ext_tw", i32), ("aqft", i32), ("k", i32),
+        ("nfree", i32), ("MI", i32), ("L", i32), ("xcd_remap", i32),
+        ("ntiles", u32),
+        ("gpos_w", u32 * 4), ("free_w", u32 * 8),
+        ("ld_thr_w", u32 * 4), ("ld_reg_w", u32 * 2),
+        ("st_thr_w", u32 * 4), ("st_reg_w", u32 * 2),
         ("grp", GroupMap * MAX_GROUPS),
         ("scale", ctypes.c_double),
         ("tw_int", ctypes.c_void_p), ("tw_lo", ctypes.c_void_p), ("tw_hi", ctypes.c_void_p),
     ]
+
+
+def P(words):
+    """Unpack four 8-bit positions per 32-bit word."""
+    out = []
+    for w in words:
+        for b in range(4):
+            out.append((w >> (8 * b)) & 0xFF)
+    return out
 
 
 def desc_size_matches() -> bool:
@@ -104,7 +114,7 @@ def run_pass(d, launch, src, tables, c128, check=True):
         tile = blocks
     base = np.zeros_like(tile)
     for b in range(d.nfree):
-        base |= ((tile >> b) & 1) << d.free_pos[b]
+        base |= ((tile >> b) & 1) << P(d.free_w)[b]
     tid = np.arange(NT, dtype=np.int64)
 
     def dep_tid(pos):
@@ -120,8 +130,8 @@ def run_pass(d, launch, src, tables, c128, check=True):
                 o |= 1 << pos[q]
         return o
 
-    g = base[:, None] | dep_tid(d.ld_thr_g)[None, :]
-    ld_idx = [g | dep_reg(rho, d.ld_reg_g) for rho in range(R)]
+    g = base[:, None] | dep_tid(P(d.ld_thr_w))[None, :]
+    ld_idx = [g | dep_reg(rho, P(d.ld_reg_w)) for rho in range(R)]
     if check:
         allidx = np.concatenate([a.ravel() for a in ld_idx])
         assert np.unique(allidx).size == allidx.size == (1 << d.n), "loads are not a permutation"
@@ -129,19 +139,19 @@ def run_pass(d, launch, src, tables, c128, check=True):
 
     for gi in range(d.ngroups):
         G = d.grp[gi]
-        e_thr = dep_tid(G.thr_pos)
+        e_thr = dep_tid(P(G.thr_w))
         if gi > 0:
-            P = d.grp[gi - 1]
-            e_prev = dep_tid(P.thr_pos)
+            Gp = d.grp[gi - 1]
+            e_prev = dep_tid(P(Gp.thr_w))
             lds = np.full((d.ntiles, 1 << T), np.nan + 0j)
             seen = np.zeros(1 << T, dtype=np.int64)
             for rho in range(R):
-                a = _swizzle(e_prev | dep_reg(rho, P.reg_pos), c128)
+                a = _swizzle(e_prev | dep_reg(rho, P(Gp.reg_w)), c128)
                 lds[:, a] = v[rho]
                 np.add.at(seen, a, 1)
             if check:
                 assert np.all(seen == 1), "LDS exchange does not cover the tile once"
-            v = [lds[:, _swizzle(e_thr | dep_reg(rho, G.reg_pos), c128)] for rho in range(R)]
+            v = [lds[:, _swizzle(e_thr | dep_reg(rho, P(G.reg_w)), c128)] for rho in range(R)]
         # radix network with the constant twiddles of the register bits
         nst, jbase = G.nst, G.jbase
         for q in range(RB - 1, -1, -1):
@@ -173,7 +183,7 @@ def run_pass(d, launch, src, tables, c128, check=True):
                 v[rho] = v[rho] * F[None, :]
 
     obase = _bitrev(base, d.n) if d.reverse else base
-    g = obase[:, None] | dep_tid(d.st_thr_g)[None, :]
+    g = obase[:, None] | dep_tid(P(d.st_thr_w))[None, :]
     nmask = (1 << d.n) - 1
 
     def omega(E):
@@ -192,7 +202,7 @@ def run_pass(d, launch, src, tables, c128, check=True):
                 Et = (Et + np.where((pt >> j) & 1, tv << (d.n - 1 - d.lo - j), 0)) & nmask
         fq = []
         for q in range(RB):
-            j = d.st_reg_g[q] - d.lo
+            j = P(d.st_reg_w)[q] - d.lo
             assert 0 <= j < d.m, "a register bit of the store map is not a pass bit"
             s = d.lo + j - d.k
             tv = vv if (not d.aqft or s <= 0) else (np.zeros_like(vv) if s >= d.lo else (vv >> s) << s)
@@ -208,7 +218,7 @@ def run_pass(d, launch, src, tables, c128, check=True):
         v = [x * d.scale for x in v]
     out_idx, out_val = [], []
     for rho in range(R):
-        idx = g | dep_reg(rho, d.st_reg_g)
+        idx = g | dep_reg(rho, P(d.st_reg_w))
         out_idx.append(idx.ravel())
         out_val.append(v[rho].ravel())
     out_idx = np.concatenate(out_idx)
