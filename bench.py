@@ -241,7 +241,7 @@ def main():
                         f"cutoff={args.cutoff}",
             "n": n, "cutoff": args.cutoff, "passes": info.num_passes,
             "pass_bits": list(info.pass_bits)[:info.num_passes],
-            "kernel_config": {f: getattr(info.config, f) for f, _ in Q.Config._fields_},
+            "kernel_config": Q._cfg_dict(info.config),
         },
         "hbm_gbs": hbm_gbs,
         "hbm_frac_whole_step": hbm_gbs / HBM_PEAK_GBS,

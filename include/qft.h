@@ -84,12 +84,22 @@ typedef void *qft_stream_t; /* hipStream_t */
  * spec_log2:   contiguous low-order elements kept in each tile of the
  *              high-order passes (coalescing width 2^spec_log2)
  * rev_spec_log2: contiguous output elements per run in the final
- *              bit-reversing pass (natural order only)                       */
+ *              bit-reversing pass (natural order only)
+ * tiles_per_wg: tiles each workgroup of a pass works through, loading the
+ *              next tile while it computes the current one (1 = one tile
+ *              per workgroup)
+ * pass_bits:   qubits of each HBM pass, most significant pass first,
+ *              summing to n (all zero = planner's choice: the fewest passes,
+ *              middle passes as wide as the tile allows, the rest split
+ *              between the first and the last pass, whose rows lie furthest
+ *              apart in memory)                                             */
 typedef struct qft_config {
   int tile_log2;
   int radix_log2;
   int spec_log2;
   int rev_spec_log2;
+  int tiles_per_wg;
+  int pass_bits[QFT_MAX_PASSES];
 } qft_config_t;
 
 /* Description of a plan.  Gate counts are those of the circuit before any

@@ -92,14 +92,15 @@ int build_entry(BatchEntry *e) {
       GroupBuild &g = gb[it->second];
       BatchSeg sg;
       sg.first = g.items;
-      sg.ntiles = L.grid;
+      sg.ntiles = L.d.ntiles;
       sg.desc = (uint32_t)descs.size();
       sg.job = (uint32_t)j;
       g.segs.push_back(sg);
-      g.items += L.grid;
+      g.items += L.d.ntiles;
       g.lds = std::max(g.lds, L.lds_bytes);
       PassDesc d = L.d;
       d.xcd_remap = 0;
+      d.pipe_k = 0;
       descs.push_back(d);
       BatchIO b;
       b.in = L.in_ws ? ws[j] : e->ptrs[j];

@@ -68,6 +68,7 @@ struct PassDesc {
   int32_t MI;       // internal twiddle table: w_{2^MI}^y, y < 2^(MI-1)
   int32_t L;        // split of the two-level w_N table
   int32_t xcd_remap;// 1: XCD-aware tile order
+  int32_t pipe_k;   // > 1: pipelined kernel, tiles per workgroup
   uint32_t ntiles;
   uint32_t gpos_w[4];   // global index bit of e-position q (packed)
   uint32_t free_w[8];   // global positions of the non-tile bits, ascending

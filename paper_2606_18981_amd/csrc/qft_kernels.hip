@@ -163,6 +163,105 @@ __device__ __forceinline__ cplx<Real> omega_n(const PassDesc &d, uint32_t E) {
   return cmul(tlo[E & ((1u << d.L) - 1u)], thi[E >> d.L]);
 }
 
+// Index of the tile's first element: the tile number deposited into the
+// non-tile bit positions.
+__device__ __forceinline__ uint32_t tile_base(const PassDesc &d, uint32_t tile) {
+  uint32_t base = 0;
+  for (int b = 0; b < d.nfree; ++b) base |= ((tile >> b) & 1u) << pos_get(d.free_w, b);
+  return base;
+}
+
+// Controls among this thread's pass bits below jbase: target jl = jbase + q
+// gets w_{2^{jl+1}}^{u} on elements with register bit q set, u = those bits
+// with the ones below jl - k cleared (AQFT).  Depends on the thread only, not
+// on the tile.
+template <typename Real, int RB>
+__device__ __forceinline__ void group_factors(const PassDesc &d, const GroupMap &G, uint32_t e_thr,
+                                              cplx<Real> (&f)[RB]) {
+  const cplx<Real> *__restrict__ W = (const cplx<Real> *)d.tw_int;
+  const int MI1 = d.MI - 1;
+  const int jbase = G.jbase;
+  const uint32_t u_thr = (e_thr >> d.pbase) & ((1u << jbase) - 1u);
+#pragma unroll
+  for (int q = 0; q < RB; ++q) {
+    const int jl = jbase + q;
+    int clear = d.aqft ? jl - d.k : 0;
+    clear = clear < 0 ? 0 : clear;
+    const uint32_t x = clear >= jbase ? 0u : ((u_thr >> clear) << clear);
+    f[q] = q < G.nst ? W[x << (MI1 - jl)] : cplx<Real>{(Real)1, (Real)0};
+  }
+}
+
+// Diagonal of the controlled phases whose controls lie below the pass:
+// w_N^E with E = sum over set pass bits j of trunc_{lo+j-k}(vv) 2^{n-1-lo-j}
+// (vv = index bits below the pass).  All register bits of the store map are
+// pass bits, so E = E_thr + sum over set register bits q of c_q: the factors
+// are f0 = w_N^{E_thr} (times the pass scale) and f[q] = w_N^{c_q}.
+// g = index of the thread's register-0 element.
+template <typename Real, int RB>
+__device__ __forceinline__ void ext_factors(const PassDesc &d, uint32_t g, cplx<Real> (&f)[RB],
+                                            cplx<Real> &f0) {
+  const uint32_t nmask = d.n >= 32 ? 0xffffffffu : ((1u << d.n) - 1u);
+  const uint32_t vv = g & ((1u << d.lo) - 1u);
+  const uint32_t pt = (g >> d.lo) & ((1u << d.m) - 1u);
+  uint32_t Et = 0;
+  if (!d.aqft) {
+    Et = (vv * rev_bits(pt, d.m)) << (d.n - d.lo - d.m);
+  } else {
+    for (int j = 0; j < d.m; ++j) {
+      if ((pt >> j) & 1u) {
+        const int s = d.lo + j - d.k;
+        const uint32_t tv = s <= 0 ? vv : (s >= d.lo ? 0u : ((vv >> s) << s));
+        Et = (Et + (tv << (d.n - 1 - d.lo - j))) & nmask;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RB; ++q) {
+    const int j = (int)pos_get(d.st_reg_w, q) - d.lo;
+    const int s = d.lo + j - d.k;
+    const uint32_t tv = (!d.aqft || s <= 0) ? vv : (s >= d.lo ? 0u : ((vv >> s) << s));
+    f[q] = omega_n<Real>(d, (tv << (d.n - 1 - d.lo - j)) & nmask);
+  }
+  f0 = omega_n<Real>(d, Et);
+  const Real scale = (Real)d.scale;
+  f0.x *= scale;
+  f0.y *= scale;
+}
+
+// Move the registers from group P's map to group G's map through LDS.
+template <typename Real, int RB>
+__device__ __forceinline__ void exchange(cplx<Real> (&v)[1 << RB], cplx<Real> *lds,
+                                         const GroupMap &P, const GroupMap &G, uint32_t tid, int TR,
+                                         bool active) {
+  constexpr int R = 1 << RB;
+  if (active) {
+    const uint32_t sp = lds_swizzle<Real>(deposit_tid(tid, P.thr_w, TR));
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho)
+      lds[sp ^ lds_swizzle<Real>(deposit_reg<RB>(rho, P.reg_w))] = v[rho];
+  }
+  __syncthreads();
+  if (active) {
+    const uint32_t sg = lds_swizzle<Real>(deposit_tid(tid, G.thr_w, TR));
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho)
+      v[rho] = lds[sg ^ lds_swizzle<Real>(deposit_reg<RB>(rho, G.reg_w))];
+  }
+  __syncthreads();
+}
+
+template <typename Real, int RB>
+__device__ __forceinline__ void store_tile(const PassDesc &d, cplx<Real> (&v)[1 << RB],
+                                           cplx<Real> *dst) {
+  constexpr int R = 1 << RB;
+  uint32_t soff[R];
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho) soff[rho] = deposit_reg<RB>(rho, d.st_reg_w);
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho) dst[soff[rho]] = v[rho];
+}
+
 // One tile of one pass.  Per register group: radix network on the group's
 // register bits, then the controlled phases whose controls are this thread's
 // lower pass bits (deferred to the end of the group), then an LDS exchange to
@@ -178,8 +277,7 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
   using C = cplx<Real>;
   constexpr int R = 1 << RB;
   const int TR = d.T - RB;
-  uint32_t base = 0;
-  for (int b = 0; b < d.nfree; ++b) base |= ((tile >> b) & 1u) << pos_get(d.free_w, b);
+  const uint32_t base = tile_base(d, tile);
 
   C v[R];
   if (active) {
@@ -191,98 +289,35 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
     for (int rho = 0; rho < R; ++rho) v[rho] = C{(Real)0, (Real)0};
   }
 
-  const C *__restrict__ W = (const C *)d.tw_int;
-  const int MI1 = d.MI - 1;
   for (int gi = 0; gi < d.ngroups; ++gi) {
     const GroupMap &G = d.grp[gi];
-    const uint32_t e_thr = deposit_tid(tid, G.thr_w, TR);
-    if (gi > 0) {
-      const GroupMap &P = d.grp[gi - 1];
-      if (active) {
-        const uint32_t sp = lds_swizzle<Real>(deposit_tid(tid, P.thr_w, TR));
-#pragma unroll
-        for (int rho = 0; rho < R; ++rho)
-          lds[sp ^ lds_swizzle<Real>(deposit_reg<RB>(rho, P.reg_w))] = v[rho];
-      }
-      __syncthreads();
-      if (active) {
-        const uint32_t sg = lds_swizzle<Real>(e_thr);
-#pragma unroll
-        for (int rho = 0; rho < R; ++rho)
-          v[rho] = lds[sg ^ lds_swizzle<Real>(deposit_reg<RB>(rho, G.reg_w))];
-      }
-      __syncthreads();
-    }
-    const int nst = G.nst;
-    radix_network<Real, RB>(v, nst);
-    const int jbase = G.jbase;
-    if (jbase > 0 && nst > 0 && active) {
-      // controls among this thread's pass bits below jbase: target jl = jbase+q
-      // gets w_{2^{jl+1}}^{u} on elements with register bit q set, u = those
-      // bits with the ones below jl - k cleared (AQFT)
-      const uint32_t u_thr = (e_thr >> d.pbase) & ((1u << jbase) - 1u);
+    if (gi > 0) exchange<Real, RB>(v, lds, d.grp[gi - 1], G, tid, TR, active);
+    radix_network<Real, RB>(v, G.nst);
+    if (G.jbase > 0 && G.nst > 0 && active) {
       C f[RB];
-#pragma unroll
-      for (int q = 0; q < RB; ++q) {
-        const int jl = jbase + q;
-        int clear = d.aqft ? jl - d.k : 0;
-        clear = clear < 0 ? 0 : clear;
-        const uint32_t x = clear >= jbase ? 0u : ((u_thr >> clear) << clear);
-        f[q] = q < nst ? W[x << (MI1 - jl)] : C{(Real)1, (Real)0};
-      }
+      group_factors<Real, RB>(d, G, deposit_tid(tid, G.thr_w, TR), f);
       apply_factors<Real, RB>(v, f, C{(Real)1, (Real)0}, false);
     }
   }
   if (!active) return;
 
-  const Real scale = (Real)d.scale;
   const uint32_t obase = d.reverse ? rev_bits(base, d.n) : base;
-  C *dst = out + (obase | deposit_tid(tid, d.st_thr_w, TR));
+  const uint32_t st_thr = deposit_tid(tid, d.st_thr_w, TR);
   if (d.ext_tw) {
-    // diagonal of the controlled phases whose controls lie below the pass:
-    // w_N^E with E = sum over set pass bits j of trunc_{lo+j-k}(vv) 2^{n-1-lo-j}
-    // (vv = index bits below the pass).  All register bits are pass bits here,
-    // so E = E_thr + sum over set register bits q of c_q.
-    const uint32_t nmask = d.n >= 32 ? 0xffffffffu : ((1u << d.n) - 1u);
-    const uint32_t g = base | deposit_tid(tid, d.st_thr_w, TR);
-    const uint32_t vv = g & ((1u << d.lo) - 1u);
-    const uint32_t pt = (g >> d.lo) & ((1u << d.m) - 1u);
-    uint32_t Et = 0;
-    if (!d.aqft) {
-      Et = (vv * rev_bits(pt, d.m)) << (d.n - d.lo - d.m);
-    } else {
-      for (int j = 0; j < d.m; ++j) {
-        if ((pt >> j) & 1u) {
-          const int s = d.lo + j - d.k;
-          const uint32_t tv = s <= 0 ? vv : (s >= d.lo ? 0u : ((vv >> s) << s));
-          Et = (Et + (tv << (d.n - 1 - d.lo - j))) & nmask;
-        }
+    C f[RB], f0;
+    ext_factors<Real, RB>(d, base | st_thr, f, f0);
+    apply_factors<Real, RB>(v, f, f0, true);
+  } else {
+    const Real scale = (Real)d.scale;
+    if (scale != (Real)1) {
+#pragma unroll
+      for (int rho = 0; rho < R; ++rho) {
+        v[rho].x *= scale;
+        v[rho].y *= scale;
       }
     }
-    C f[RB];
-#pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      const int j = (int)pos_get(d.st_reg_w, q) - d.lo;
-      const int s = d.lo + j - d.k;
-      const uint32_t tv = (!d.aqft || s <= 0) ? vv : (s >= d.lo ? 0u : ((vv >> s) << s));
-      f[q] = omega_n<Real>(d, (tv << (d.n - 1 - d.lo - j)) & nmask);
-    }
-    C f0 = omega_n<Real>(d, Et);
-    f0.x *= scale;
-    f0.y *= scale;
-    apply_factors<Real, RB>(v, f, f0, true);
-  } else if (scale != (Real)1) {
-#pragma unroll
-    for (int rho = 0; rho < R; ++rho) {
-      v[rho].x *= scale;
-      v[rho].y *= scale;
-    }
   }
-  uint32_t soff[R];
-#pragma unroll
-  for (int rho = 0; rho < R; ++rho) soff[rho] = deposit_reg<RB>(rho, d.st_reg_w);
-#pragma unroll
-  for (int rho = 0; rho < R; ++rho) dst[soff[rho]] = v[rho];
+  store_tile<Real, RB>(d, v, out + (obase | st_thr));
 }
 
 template <typename Real, int RB>
@@ -293,23 +328,115 @@ k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
   uint32_t tile = blockIdx.x;
   if (d.xcd_remap) {
     // consecutive tiles on one XCD (workgroups are dealt round-robin to 8 XCDs)
-    const uint32_t per = d.ntiles >> 3;
+    const uint32_t per = gridDim.x >> 3;
     tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
   }
   tile_body<Real, RB>(d, tile, in, out, reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x,
                       true);
 }
 
+// Pipelined pass: workgroup w applies the pass to tiles_per_wg consecutive
+// tiles; the loads of tile i+1 are issued before tile i is computed, so HBM
+// stays busy during the register networks, the LDS exchanges and the stores.
+// The per-group factors do not depend on the tile and are loaded once, and
+// the below-pass factors of tile i are loaded before the prefetch, so no wait
+// for a factor has to wait for the prefetched data.  Requires that groups
+// from the third on carry no per-thread factors (the planner checks).
+// (twice the data registers of k_fused_pass: the launch bounds halve the
+// workgroup size so that the register budget doubles)
+template <typename Real, int RB>
+__global__ void __launch_bounds__(sizeof(Real) == 8
+                                      ? (RB >= 5 ? 128 : RB >= 4 ? 256 : RB >= 3 ? 512 : 1024)
+                                      : (RB >= 5 ? 256 : RB >= 4 ? 512 : 1024))
+k_fused_pass_pipe(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
+  using C = cplx<Real>;
+  constexpr int R = 1 << RB;
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  C *lds = reinterpret_cast<C *>(qft_smem);
+  const uint32_t tid = threadIdx.x;
+  const int TR = d.T - RB;
+  const int K = d.pipe_k;
+  uint32_t wg = blockIdx.x;
+  if (d.xcd_remap) {
+    const uint32_t per = gridDim.x >> 3;
+    wg = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  }
+  const uint32_t tile0 = wg * (uint32_t)K;
+  const uint32_t ld_thr = deposit_tid(tid, d.ld_thr_w, TR);
+  const uint32_t st_thr = deposit_tid(tid, d.st_thr_w, TR);
+  uint32_t ld_off[R];
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho) ld_off[rho] = deposit_reg<RB>(rho, d.ld_reg_w);
+
+  // tile-independent factors of the first two groups
+  C gf0[RB], gf1[RB];
+  const bool has0 = d.ngroups > 0 && d.grp[0].jbase > 0 && d.grp[0].nst > 0;
+  const bool has1 = d.ngroups > 1 && d.grp[1].jbase > 0 && d.grp[1].nst > 0;
+  if (has0) group_factors<Real, RB>(d, d.grp[0], deposit_tid(tid, d.grp[0].thr_w, TR), gf0);
+  if (has1) group_factors<Real, RB>(d, d.grp[1], deposit_tid(tid, d.grp[1].thr_w, TR), gf1);
+
+  C va[R], vb[R];
+  {
+    const C *src = in + (tile_base(d, tile0) | ld_thr);
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) va[rho] = src[ld_off[rho]];
+  }
+  auto step = [&](C (&v)[R], C (&nxt)[R], int i) {
+    const uint32_t base = tile_base(d, tile0 + i);
+    C ef[RB], ef0;
+    if (d.ext_tw) ext_factors<Real, RB>(d, base | st_thr, ef, ef0);
+    if (i + 1 < K) {
+      const C *src = in + (tile_base(d, tile0 + i + 1) | ld_thr);
+#pragma unroll
+      for (int rho = 0; rho < R; ++rho) nxt[rho] = src[ld_off[rho]];
+    }
+    // groups 0 and 1 (peeled: their factor arrays stay in registers)
+    radix_network<Real, RB>(v, d.grp[0].nst);
+    if (has0) apply_factors<Real, RB>(v, gf0, C{(Real)1, (Real)0}, false);
+    if (d.ngroups > 1) {
+      exchange<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR, true);
+      radix_network<Real, RB>(v, d.grp[1].nst);
+      if (has1) apply_factors<Real, RB>(v, gf1, C{(Real)1, (Real)0}, false);
+    }
+    for (int gi = 2; gi < d.ngroups; ++gi) {
+      exchange<Real, RB>(v, lds, d.grp[gi - 1], d.grp[gi], tid, TR, true);
+      radix_network<Real, RB>(v, d.grp[gi].nst);
+    }
+    if (d.ext_tw) {
+      apply_factors<Real, RB>(v, ef, ef0, true);
+    } else {
+      const Real scale = (Real)d.scale;
+      if (scale != (Real)1) {
+#pragma unroll
+        for (int rho = 0; rho < R; ++rho) {
+          v[rho].x *= scale;
+          v[rho].y *= scale;
+        }
+      }
+    }
+    const uint32_t obase = d.reverse ? rev_bits(base, d.n) : base;
+    store_tile<Real, RB>(d, v, out + (obase | st_thr));
+  };
+  for (int i = 0; i < K; i += 2) {
+    step(va, vb, i);
+    if (i + 1 < K) step(vb, va, i + 1);
+  }
+}
+
 template <typename Real, int RB>
 static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, hipStream_t s) {
-  auto fn = k_fused_pass<Real, RB>;
+  // (no pipelined instance for complex128 at radix 32: it does not fit the
+  // register file; the planner never asks for it)
+  auto fn = (L.d.pipe_k > 1 && !(sizeof(Real) == 8 && RB >= 5)) ? k_fused_pass_pipe<Real, RB>
+                                                                 : k_fused_pass<Real, RB>;
   if (L.lds_bytes > 65536) {
-    static int set = 0;
-    if (!set) {
+    static int set[2] = {0, 0};
+    const int which = L.d.pipe_k > 1 ? 1 : 0;
+    if (!set[which]) {
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
       if (e != hipSuccess) return e;
-      set = 1;
+      set[which] = 1;
     }
   }
   hipLaunchKernelGGL(fn, dim3(L.grid), dim3(L.threads), L.lds_bytes, s, L.d,

@@ -58,6 +58,10 @@ int check_config(const qft_config_t &c, std::string &err) {
     err = "tile_log2 must be in [radix_log2, 15]";
     return QFT_ERR_INVALID;
   }
+  if (c.tiles_per_wg < 0 || c.tiles_per_wg > 64 || (c.tiles_per_wg & (c.tiles_per_wg - 1))) {
+    err = "tiles_per_wg must be 0 or a power of two up to 64";
+    return QFT_ERR_INVALID;
+  }
   if (c.spec_log2 < 0 || c.spec_log2 >= c.tile_log2 || c.rev_spec_log2 < 0 ||
       c.rev_spec_log2 >= c.tile_log2) {
     err = "spec_log2 and rev_spec_log2 must be in [0, tile_log2)";
@@ -158,6 +162,13 @@ int max_thread_bits(int r, bool c128) {
   return r >= 5 ? 9 : 10;
 }
 
+// the same for the pipelined kernel, which holds two tiles in registers
+// (-1: no pipelined instance for this radix)
+int pipe_max_thread_bits(int r, bool c128) {
+  if (c128) return r >= 5 ? -1 : r >= 4 ? 8 : r >= 3 ? 9 : 10;
+  return r >= 5 ? 8 : r >= 4 ? 9 : 10;
+}
+
 int plan_fused(HostPlan &p, std::string &err) {
   const int n = p.n;
   const qft_config_t &c = p.cfg;
@@ -173,53 +184,83 @@ int plan_fused(HostPlan &p, std::string &err) {
   const int rspec = std::min(c.rev_spec_log2, T - 1);
 
   // ---- pass partition --------------------------------------------------
-  std::vector<PassGeom> geo;
-  if (n <= T) {
-    PassGeom g;
-    g.lo = 0;
-    g.m = n;
-    g.reverse = !p.bitrev;
-    geo.push_back(g);
+  // widths[0] is the most significant pass; the last one holds qubit 0
+  std::vector<int> widths;
+  int nexplicit = 0, sum = 0;
+  for (int i = 0; i < kMaxPasses; ++i) {
+    if (c.pass_bits[i] < 0) {
+      err = "pass_bits must be >= 0";
+      return QFT_ERR_INVALID;
+    }
+    if (c.pass_bits[i] > 0) {
+      if (nexplicit != i) {
+        err = "pass_bits must be given from the first entry on, without gaps";
+        return QFT_ERR_INVALID;
+      }
+      ++nexplicit;
+      sum += c.pass_bits[i];
+    }
+  }
+  if (nexplicit > 0) {
+    if (sum != n) {
+      err = "pass_bits must sum to n";
+      return QFT_ERR_INVALID;
+    }
+    for (int i = 0; i < nexplicit; ++i) {
+      if (c.pass_bits[i] > T) {
+        err = "a pass cannot apply more qubits than the tile holds";
+        return QFT_ERR_INVALID;
+      }
+      widths.push_back(c.pass_bits[i]);
+    }
+  } else if (n <= T) {
+    widths.push_back(n);
   } else {
     const int b_eff = p.bitrev ? 0 : rspec;
     const int amax = T - b_eff;
     const int hmax = T - spec;
-    int P = 1;
+    int P = 2;
     while (amax + (P - 1) * hmax < n) ++P;
     if (P > kMaxPasses) {
       err = "too many passes for this tile configuration";
       return QFT_ERR_UNSUPPORTED;
     }
-    const int a = std::min(amax, n - (P - 1));
-    const int H = n - a;
-    const int Ph = P - 1;
-    std::vector<int> hs(Ph, H / Ph);
-    for (int i = 0; i < H % Ph; ++i) hs[i]++;
+    // middle passes (rows close together in memory) as wide as the tile
+    // allows; the first pass (rows 2^lo elements apart) and the last pass
+    // (bit-reversed rows) share the rest evenly
+    const int rem = n - (P - 2) * hmax;
+    const int a = std::max(std::min(amax, (rem + 1) / 2), rem - hmax);
+    widths.push_back(rem - a);
+    for (int i = 0; i < P - 2; ++i) widths.push_back(hmax);
+    widths.push_back(a);
+  }
+  std::vector<PassGeom> geo;
+  {
     int top = n;
-    for (int i = 0; i < Ph; ++i) {
+    const int P = (int)widths.size();
+    for (int i = 0; i < P; ++i) {
       PassGeom g;
-      g.m = hs[i];
+      g.m = widths[i];
       g.lo = top - g.m;
-      // a high pass applies the diagonal of lower controls per register
-      // group, which needs every register bit to be a pass bit (r <= m)
-      const int r = std::min(r_cfg, g.m);
-      const int Tp = std::min(T, r + max_thread_bits(r, p.c128));
-      const int nspec = std::min(Tp - g.m, g.lo);
-      for (int q = 0; q < nspec; ++q) g.spec_g.push_back(q);
-      geo.push_back(g);
       top = g.lo;
+      if (i + 1 < P) {
+        // a high pass applies the diagonal of lower controls per register
+        // group, which needs every register bit to be a pass bit (r <= m)
+        const int r = std::min(r_cfg, g.m);
+        const int Tp = std::min(T, r + max_thread_bits(r, p.c128));
+        const int nspec = std::min(Tp - g.m, g.lo);
+        for (int q = 0; q < nspec; ++q) g.spec_g.push_back(q);
+      } else {
+        g.reverse = !p.bitrev;
+        const int nspec = std::min(T - g.m, n - g.m);
+        if (p.bitrev) {
+          for (int q = 0; q < nspec; ++q) g.spec_g.push_back(g.m + q);
+        } else {
+          for (int q = 0; q < nspec; ++q) g.spec_g.push_back(n - nspec + q);
+        }
+      }
+      geo.push_back(g);
     }
-    PassGeom g;
-    g.lo = 0;
-    g.m = a;
-    g.reverse = !p.bitrev;
-    const int nspec = std::min(T - a, n - a);
-    if (p.bitrev) {
-      for (int q = 0; q < nspec; ++q) g.spec_g.push_back(a + q);
-    } else {
-      for (int q = 0; q < nspec; ++q) g.spec_g.push_back(n - nspec + q);
-    }
-    geo.push_back(g);
   }
 
   // ---- tables ------------------------------------------------------------
@@ -304,11 +345,19 @@ int plan_fused(HostPlan &p, std::string &err) {
       if (!in_tile[b]) pos_set(d.free_w, nf++, b);
     d.nfree = nf;
     d.ntiles = 1u << nf;
-    d.xcd_remap = (d.ntiles >= 8) ? 1 : 0;
     d.scale = scales[i];
     L.threads = 1 << (Te - r);
     L.lds_bytes = d.ngroups > 1 ? (int)(((size_t)1 << Te) * es) : 0;
-    L.grid = d.ntiles;
+    // pipelined kernel: K consecutive tiles per workgroup, when every group
+    // from the third on carries no per-thread factors
+    int K = std::max(1, c.tiles_per_wg);
+    bool pipe_ok = K > 1 && d.ntiles % (uint32_t)K == 0 &&
+                   Te - r <= pipe_max_thread_bits(r, p.c128);
+    for (int gi = 2; gi < d.ngroups && pipe_ok; ++gi)
+      if (d.grp[gi].jbase > 0 && d.grp[gi].nst > 0) pipe_ok = false;
+    d.pipe_k = pipe_ok ? K : 0;
+    L.grid = pipe_ok ? d.ntiles / (uint32_t)K : d.ntiles;
+    d.xcd_remap = (L.grid >= 8 && L.grid % 8 == 0) ? 1 : 0;
     if (natural_multi) {
       L.in_ws = i == 0 ? 0 : 1;
       L.out_ws = i + 1 == geo.size() ? 0 : 1;
@@ -341,6 +390,7 @@ void plan_gates(HostPlan &p) {
 
 qft_config_t default_config(bool c128) {
   qft_config_t c;
+  memset(&c, 0, sizeof(c));
   if (c128) {
     c.tile_log2 = 12;
     c.radix_log2 = 3;
@@ -442,6 +492,8 @@ int build_host_plan(int n, int cutoff, int norm, int layout, const qft_config_t 
     if (cfg->rev_spec_log2) c.rev_spec_log2 = cfg->rev_spec_log2 < 0 ? 0 : cfg->rev_spec_log2;
     c.spec_log2 = std::min(c.spec_log2, c.tile_log2 - 1);
     c.rev_spec_log2 = std::min(c.rev_spec_log2, c.tile_log2 - 1);
+    for (int i = 0; i < QFT_MAX_PASSES; ++i) c.pass_bits[i] = cfg->pass_bits[i];
+    if (cfg->tiles_per_wg) c.tiles_per_wg = cfg->tiles_per_wg;
   }
   p.cfg = c;
   if (p.schedule == Schedule::Gates) {

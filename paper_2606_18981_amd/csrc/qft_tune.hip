@@ -50,7 +50,15 @@ std::vector<qft_config_t> candidate_grid() {
   for (int t = 8; t <= 14; ++t)
     for (int r = 3; r <= 5; ++r)
       for (int c = 2; c <= 5; ++c)
-        for (int b = 2; b <= 4; ++b) v.push_back(qft_config_t{t, r, c, b});
+        for (int b = 2; b <= 4; ++b) {
+          qft_config_t q;
+          memset(&q, 0, sizeof(q));
+          q.tile_log2 = t;
+          q.radix_log2 = r;
+          q.spec_log2 = c;
+          q.rev_spec_log2 = b;
+          v.push_back(q);
+        }
   return v;
 }
 
@@ -288,11 +296,16 @@ int qft_tune_save(const char *path) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (const auto &kv : g_table) {
     const Entry &e = kv.second;
+    std::string split;
+    for (int i = 0; i < QFT_MAX_PASSES && e.cfg.pass_bits[i] > 0; ++i)
+      split += (i ? "," : "") + std::to_string(e.cfg.pass_bits[i]);
     fprintf(f,
             "{\"arch\":\"%s\",\"n\":%d,\"cutoff\":%d,\"layout\":%d,\"tile_log2\":%d,"
-            "\"radix_log2\":%d,\"spec_log2\":%d,\"rev_spec_log2\":%d,\"ms\":%.6g}\n",
+            "\"radix_log2\":%d,\"spec_log2\":%d,\"rev_spec_log2\":%d,\"pass_bits\":\"%s\","
+            "\"ms\":%.6g}\n",
             arch.c_str(), std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-            e.cfg.tile_log2, e.cfg.radix_log2, e.cfg.spec_log2, e.cfg.rev_spec_log2, e.ms);
+            e.cfg.tile_log2, e.cfg.radix_log2, e.cfg.spec_log2, e.cfg.rev_spec_log2, split.c_str(),
+            e.ms);
   }
   fclose(f);
   return QFT_OK;
@@ -316,7 +329,22 @@ int qft_tune_load(const char *path) {
         !get_num(line, "rev_spec_log2", &b))
       continue;
     if (!get_num(line, "ms", &ms)) ms = 0.0;
-    qft_config_t cfg{(int)t, (int)r, (int)c, (int)b};
+    qft_config_t cfg;
+    memset(&cfg, 0, sizeof(cfg));
+    cfg.tile_log2 = (int)t;
+    cfg.radix_log2 = (int)r;
+    cfg.spec_log2 = (int)c;
+    cfg.rev_spec_log2 = (int)b;
+    std::string split;
+    if (get_str(line, "pass_bits", &split) && !split.empty()) {
+      const char *q = split.c_str();
+      for (int i = 0; i < QFT_MAX_PASSES && *q; ++i) {
+        char *end = nullptr;
+        cfg.pass_bits[i] = (int)strtol(q, &end, 10);
+        if (end == q) break;
+        q = *end == ',' ? end + 1 : end;
+      }
+    }
     // an entry the planner rejects is skipped
     HostPlan hp;
     std::string err;

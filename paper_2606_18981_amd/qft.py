@@ -49,7 +49,9 @@ class QftError(RuntimeError):
 
 class Config(ctypes.Structure):
     _fields_ = [("tile_log2", ctypes.c_int), ("radix_log2", ctypes.c_int),
-                ("spec_log2", ctypes.c_int), ("rev_spec_log2", ctypes.c_int)]
+                ("spec_log2", ctypes.c_int), ("rev_spec_log2", ctypes.c_int),
+                ("tiles_per_wg", ctypes.c_int),
+                ("pass_bits", ctypes.c_int * QFT_MAX_PASSES)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -162,7 +164,14 @@ def _config(config) -> Optional[Config]:
         return None
     if isinstance(config, Config):
         return config
-    return Config(**{k: int(v) for k, v in dict(config).items()})
+    c = Config()
+    for k, v in dict(config).items():
+        if k == "pass_bits":
+            for i, b in enumerate(list(v)[:QFT_MAX_PASSES]):
+                c.pass_bits[i] = int(b)
+        else:
+            setattr(c, k, int(v))
+    return c
 
 
 def describe(n: int, cutoff: int = -1, norm="unitary", dtype="c64", order="natural",
@@ -299,7 +308,13 @@ def fill_random(x, dist="gaussian", seed: int = 0, stream_id: int = 0, stream=No
 # ---- autotuner ------------------------------------------------------------
 
 def _cfg_dict(c: Config) -> dict:
-    return {f: getattr(c, f) for f, _ in Config._fields_}
+    d = {f: getattr(c, f) for f, _ in Config._fields_ if f not in ("pass_bits", "tiles_per_wg")}
+    if c.tiles_per_wg > 1:
+        d["tiles_per_wg"] = c.tiles_per_wg
+    pb = [int(x) for x in c.pass_bits if int(x) > 0]
+    if pb:
+        d["pass_bits"] = pb
+    return d
 
 
 def tune(n: int, cutoff: int = -1, norm="unitary", dtype="c64", order="natural",

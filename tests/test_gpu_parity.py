@@ -105,13 +105,20 @@ CONFIGS = [
     dict(tile_log2=9, radix_log2=5, spec_log2=4, rev_spec_log2=4),
     dict(tile_log2=12, radix_log2=4, spec_log2=4, rev_spec_log2=4),
     dict(tile_log2=13, radix_log2=5, spec_log2=3, rev_spec_log2=3),
+    dict(tile_log2=13, radix_log2=5, spec_log2=3, rev_spec_log2=3, tiles_per_wg=4),
+    dict(tile_log2=12, radix_log2=4, spec_log2=2, rev_spec_log2=2, tiles_per_wg=2),
+    dict(tile_log2=11, radix_log2=3, spec_log2=2, rev_spec_log2=2, tiles_per_wg=8),
+    dict(tile_log2=12, radix_log2=4, spec_log2=2, rev_spec_log2=3, tiles_per_wg=4,
+         pass_bits=[7, 7, 6]),
 ]
 
 
 @pytest.mark.parametrize("cfg", CONFIGS)
 @pytest.mark.parametrize("n,k,order", [(11, -1, "natural"), (19, 4, "natural"),
-                                       (20, -1, "bitrev")])
+                                       (20, -1, "bitrev"), (20, 6, "natural")])
 def test_kernel_configs(torch_cuda, Q, cfg, n, k, order):
+    if "pass_bits" in cfg and sum(cfg["pass_bits"]) != n:
+        pytest.skip("explicit split is for n = 20")
     for dt in ("c64", "c128"):
         x = I.uniform_pm1(n, 4000 + n)
         y = run_gpu(torch_cuda, Q, x, n, k, "unitary", dt, order, "fused", cfg)

@@ -30,7 +30,7 @@ def test_tune_shape_and_reuse(env, tmp_path):
     assert ms > 0
     assert Q.tune_lookup(n, -1, "c64") == best
     plan = Q.Plan(n, -1, "unitary", "c64", "natural")
-    assert {f: getattr(plan.info.config, f) for f, _ in Q.Config._fields_} == best
+    assert Q._cfg_dict(plan.info.config) == best
     x = I.gaussian(n, 4)
     t = torch.from_numpy(x.astype(np.complex64)).cuda()
     plan.execute(t)

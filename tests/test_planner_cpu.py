@@ -158,6 +158,7 @@ CONFIGS = [
     dict(tile_log2=8, radix_log2=3, spec_log2=-1, rev_spec_log2=-1),
     dict(tile_log2=9, radix_log2=5, spec_log2=4, rev_spec_log2=4),
     dict(tile_log2=10, radix_log2=4, spec_log2=5, rev_spec_log2=3),
+    dict(tile_log2=10, radix_log2=4, spec_log2=3, rev_spec_log2=3, tiles_per_wg=4),
 ]
 for cfg in CONFIGS:
     for n, k in ((11, None), (16, 4), (19, 2), (20, None)):
@@ -173,6 +174,36 @@ def test_emulated_kernel_matches_oracle(n, k, norm, dtype, order, cfg):
     ref = O.qft_fused_targets(x, k, norm, order)
     tol = 1e-12 if dtype == "c128" else 2e-6
     assert O.rel_l2(y, ref) < tol
+
+
+@pytest.mark.parametrize("split", [[7, 7, 6], [5, 8, 7], [10, 10], [4, 4, 4, 4, 4]])
+def test_explicit_pass_splits(split):
+    n = sum(split)
+    cfg = dict(tile_log2=12, radix_log2=4, spec_log2=2, rev_spec_log2=2, pass_bits=split)
+    info = Q.describe(n, -1, "unitary", "c128", "natural", "fused", cfg)
+    assert list(info.pass_bits)[:info.num_passes] == split
+    x = I.gaussian(n, 77)
+    for k in (None, 3):
+        y = E.emulate(x, n, -1 if k is None else k, "unitary", "c128", "natural", cfg)
+        assert O.rel_l2(y, O.qft_fused_targets(x, k)) < 1e-12
+
+
+def test_invalid_pass_splits():
+    for split in ([7, 7, 5], [0, 10, 10], [14, 6]):
+        with pytest.raises(Q.QftError):
+            Q.describe(20, config=dict(tile_log2=12, radix_log2=4, pass_bits=split))
+
+
+def test_pipelined_pass_descriptor():
+    cfg = dict(tile_log2=13, radix_log2=5, spec_log2=3, rev_spec_log2=3, tiles_per_wg=4)
+    layout = Q.layout_flags("c64")
+    for p in range(3):
+        d, L = E.get_pass(28, -1, "unitary", layout, cfg, p)
+        assert d.pipe_k == 4 and L[2] * 4 == d.ntiles
+    # no pipelined instance for complex128 at radix 32
+    cfg = dict(tile_log2=12, radix_log2=5, spec_log2=2, rev_spec_log2=2, tiles_per_wg=4)
+    d, L = E.get_pass(28, -1, "unitary", Q.layout_flags("c128"), cfg, 0)
+    assert d.pipe_k == 0
 
 
 def test_emulated_three_pass_plan():
