@@ -51,6 +51,11 @@ def cpu_baseline(n_sample: int = 24):
     }
 
 
+def profile_name(n, dtype, cutoff):
+    tag = "exact" if cutoff < 0 else f"k{cutoff}"
+    return f"fused_pass_n{n}_{dtype}_{tag}.md"
+
+
 def time_plan(torch, Q, plan, x, steps, warmup):
     """Mean ms per execute (HIP events on the current stream)."""
     for _ in range(warmup):
@@ -216,9 +221,17 @@ def main():
     gflops = flops / (ms_per_step * 1e-3) / 1e9
     state_bytes = info.state_bytes
     per_launch_bytes = 2 * state_bytes  # one read and one write of the state
-    # dominant kernel: every pass launches the same fused-pass kernel; the
+    # dominant kernel: every pass launches the fused-pass kernel (one tile per
+    # workgroup, or the variant that walks several tiles per workgroup); the
     # roofline uses its mean launch time over the timed region
     mean_pass_ms = sum(pass_ms) / len(pass_ms)
+    rb = info.config.radix_log2
+    real = "float" if args.dtype == "c64" else "double"
+    kernels = []
+    for p in range(info.num_passes):
+        kpw = info.pass_tiles_per_wg[p]
+        kernels.append(f"k_fused_pass_pipe<{real}, {rb}> (tiles per workgroup {kpw})"
+                       if kpw > 1 else f"k_fused_pass<{real}, {rb}>")
     achieved = per_launch_bytes / (mean_pass_ms * 1e-3) / 1e9
     hbm_gbs = info.hbm_bytes / (ms_per_step * 1e-3) / 1e9
 
@@ -253,10 +266,17 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "k_fused_pass (mean over the plan's passes)",
+            "kernel": "fused pass kernel, mean over the plan's passes: " + "; ".join(kernels),
             "algorithmic_bytes_per_launch": per_launch_bytes,
         },
     }
+    # HBM traffic from the committed rocprofv3 counter summary of this same
+    # workload and kernel sources (FETCH_SIZE and WRITE_SIZE, each scaled by
+    # what it reads for a plain device copy of known size); null otherwise
+    from paper_2606_18981_amd import profile_summary as PS
+    prof = os.path.join(ROOT, "profiles", profile_name(n, args.dtype, args.cutoff))
+    out["roofline"]["traffic"] = PS.load_traffic(prof, out["config"])
+    out["roofline"]["traffic_source"] = os.path.relpath(prof, ROOT)
     if args.copy_ref:
         y = torch.empty_like(x)
         ms_copy = None

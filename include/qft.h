@@ -114,6 +114,8 @@ typedef struct qft_plan_info {
   int pass_bits[QFT_MAX_PASSES]; /* qubits applied by pass p                 */
   int pass_spec[QFT_MAX_PASSES]; /* spectator (coalescing) bits of pass p    */
   int pass_reverse[QFT_MAX_PASSES]; /* pass p writes bit-reversed addresses  */
+  int pass_tiles_per_wg[QFT_MAX_PASSES]; /* tiles walked by one workgroup of
+                                            pass p (1: one tile each)        */
   qft_config_t config;
   long long gates_h, gates_cr, gates_swap;
   size_t state_bytes;     /* 2^n * element size                              */

@@ -525,6 +525,7 @@ void describe_plan(const HostPlan &p, qft_plan_info_t *o) {
       o->pass_bits[i] = d.m;
       o->pass_spec[i] = d.pbase;
       o->pass_reverse[i] = d.reverse;
+      o->pass_tiles_per_wg[i] = d.pipe_k > 1 ? d.pipe_k : 1;
     }
   } else {
     o->num_passes = (int)p.gates.size() + (p.gate_norm != 1.0 ? 1 : 0);

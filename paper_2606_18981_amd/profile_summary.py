@@ -1,0 +1,212 @@
+"""Summarise rocprofv3 results of a bench run as a short markdown file.
+
+Reads the SQLite result databases that ``rocprofv3 -d DIR -o run`` writes
+(one kernel-trace run and two counter runs, FETCH_SIZE and WRITE_SIZE), and
+prints: the per-kernel duration statistics, the counters per dispatch, the
+scale factors that make the counters read true bytes on a plain device copy
+of known size, and one JSON block that ``bench.py`` reads back to report the
+HBM traffic of the pass kernel.  The JSON block records a digest of the
+kernel and planner sources; the traffic figure is only used while the
+sources still have that digest.
+
+Usage (from the repository root)::
+
+    python -m paper_2606_18981_amd.profile_summary \
+        --trace gpurun_out/prof/trace --fetch gpurun_out/prof/fetch \
+        --write gpurun_out/prof/write --copy-bytes 2147483648 \
+        --cmd-trace "..." --cmd-fetch "..." --cmd-write "..." \
+        --bench-json gpurun_out/prof/trace.log > profiles/<name>.md
+"""
+
+import argparse
+import collections
+import glob
+import hashlib
+import json
+import os
+import sqlite3
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+
+# Sources whose change can change what the pass kernel reads and writes.
+KERNEL_SOURCES = (
+    "csrc/qft_kernels.hip",
+    "csrc/qft_kernels.h",
+    "csrc/qft_internal.h",
+    "csrc/qft_planner.cpp",
+    "csrc/qft_planner.h",
+)
+
+PASS_PREFIX = "void qft::k_fused_pass"
+COPY_NAME = "__amd_rocclr_copyBuffer"
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(PKG, rel), "rb") as f:
+            h.update(rel.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _db(path):
+    if os.path.isdir(path):
+        cands = sorted(glob.glob(os.path.join(path, "**", "*results.db"), recursive=True))
+        if not cands:
+            raise FileNotFoundError(f"no *results.db under {path}")
+        path = cands[0]
+    return sqlite3.connect(path)
+
+
+def kernel_stats(path):
+    cur = _db(path).cursor()
+    rows = cur.execute("select name, total_calls, total_duration, average, min, max "
+                       "from top_kernels").fetchall()
+    return [dict(name=r[0], calls=r[1], total_ns=r[2], avg_ns=r[3], min_ns=r[4], max_ns=r[5])
+            for r in rows]
+
+
+def counter_means(path, counter):
+    """Mean counter value per (kernel, grid) over its dispatches (KiB for *_SIZE)."""
+    cur = _db(path).cursor()
+    rows = cur.execute("select kernel_name, grid_size, value from counters_collection "
+                       "where counter_name = ?", (counter,)).fetchall()
+    agg = collections.defaultdict(list)
+    for k, g, v in rows:
+        agg[(k, g)].append(v)
+    return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
+
+
+def _pooled(means, pred):
+    tot, cnt = 0.0, 0
+    for (k, _g), (m, c) in means.items():
+        if pred(k):
+            tot += m * c
+            cnt += c
+    return (tot / cnt if cnt else None), cnt
+
+
+def summarize(a):
+    trace = kernel_stats(a.trace)
+    fetch = counter_means(a.fetch, "FETCH_SIZE")
+    write = counter_means(a.write, "WRITE_SIZE")
+    is_pass = lambda k: k.startswith(PASS_PREFIX)
+    is_copy = lambda k: k.startswith(COPY_NAME)
+    copy_f, _ = _pooled(fetch, is_copy)
+    copy_w, _ = _pooled(write, is_copy)
+    pass_f, nf = _pooled(fetch, is_pass)
+    pass_w, nw = _pooled(write, is_pass)
+    copy_kib = a.copy_bytes / 1024.0
+    f_factor = copy_kib / copy_f if copy_f else None
+    w_factor = copy_kib / copy_w if copy_w else None
+    traffic = None
+    if None not in (pass_f, pass_w, f_factor, w_factor):
+        traffic = (pass_f * f_factor + pass_w * w_factor) * 1024.0
+    pass_trace = [t for t in trace if is_pass(t["name"])]
+    calls = sum(t["calls"] for t in pass_trace)
+    avg_ns = sum(t["total_ns"] for t in pass_trace) / calls if calls else None
+    bench = None
+    if a.bench_json and os.path.exists(a.bench_json):
+        for line in open(a.bench_json):
+            line = line.strip()
+            if line.startswith("{") and '"metric"' in line:
+                bench = json.loads(line)
+    block = {
+        "source_digest": source_digest(),
+        "workload": bench["config"] if bench else None,
+        "pass_kernel_avg_ns": avg_ns,
+        "pass_fetch_kib": pass_f,
+        "pass_write_kib": pass_w,
+        "copy_bytes_each_way": a.copy_bytes,
+        "copy_fetch_kib": copy_f,
+        "copy_write_kib": copy_w,
+        "fetch_factor": f_factor,
+        "write_factor": w_factor,
+        "pass_traffic_bytes_per_launch": traffic,
+    }
+    out = []
+    out.append(f"# {a.title}\n")
+    out.append("Commands (run from the repository root, after `cd /tmp && export TMPDIR=/tmp`):\n")
+    for label, c in (("kernel trace", a.cmd_trace), ("FETCH_SIZE", a.cmd_fetch),
+                     ("WRITE_SIZE", a.cmd_write)):
+        out.append(f"* {label}: `{c}`")
+    out.append("")
+    out.append("## Kernel trace (`--kernel-trace --stats`)\n")
+    out.append("| kernel | calls | avg µs | min µs | max µs |")
+    out.append("|---|---|---|---|---|")
+    for t in trace:
+        out.append(f"| `{t['name'][:90]}` | {t['calls']} | {t['avg_ns'] / 1e3:.1f} | "
+                   f"{t['min_ns'] / 1e3:.1f} | {t['max_ns'] / 1e3:.1f} |")
+    out.append("")
+    out.append("## HBM counters (KiB per dispatch, mean over dispatches)\n")
+    out.append("| kernel | grid | FETCH_SIZE | WRITE_SIZE | dispatches |")
+    out.append("|---|---|---|---|---|")
+    for key in sorted(set(fetch) | set(write)):
+        fm = fetch.get(key, (float("nan"), 0))
+        wm = write.get(key, (float("nan"), 0))
+        out.append(f"| `{key[0][:90]}` | {key[1]} | {fm[0]:.1f} | {wm[0]:.1f} | {fm[1]}/{wm[1]} |")
+    out.append("")
+    out.append("## Scaling against the plain copy\n")
+    if f_factor and w_factor:
+        out.append(f"The device copy moves {a.copy_bytes} bytes each way "
+                   f"({copy_kib:.0f} KiB). FETCH_SIZE reads {copy_f:.1f} KiB "
+                   f"(factor {f_factor:.4f}); WRITE_SIZE reads {copy_w:.1f} KiB "
+                   f"(factor {w_factor:.4f}).")
+    if traffic:
+        out.append(f"Pass kernel, scaled: {traffic / 2**30:.4f} GiB per launch "
+                   f"({nf} / {nw} dispatches counted).")
+    if bench:
+        r = bench.get("roofline", {})
+        out.append("")
+        out.append(f"Bench line of the traced run: {bench['ms_per_step']:.4f} ms per step, "
+                   f"pass mean from HIP events {1e3 * r.get('algorithmic_bytes_per_launch', 0) / max(r.get('achieved', 1), 1e-9) / 1e9:.4f} ms "
+                   f"per launch; rocprofv3 average {avg_ns / 1e6 if avg_ns else float('nan'):.4f} ms.")
+    out.append("")
+    out.append("## Machine-readable\n")
+    out.append("```json")
+    out.append(json.dumps(block, indent=1))
+    out.append("```")
+    return "\n".join(out) + "\n"
+
+
+def load_traffic(md_path, config):
+    """Scaled HBM bytes per pass launch from a summary, or None when the
+    summary is missing, was taken on other sources, or on another workload."""
+    try:
+        text = open(md_path).read()
+    except OSError:
+        return None
+    start = text.find("```json")
+    if start < 0:
+        return None
+    end = text.find("```", start + 7)
+    try:
+        block = json.loads(text[start + 7:end])
+    except ValueError:
+        return None
+    if block.get("source_digest") != source_digest():
+        return None
+    w = block.get("workload") or {}
+    for key in ("n", "cutoff", "pass_bits", "kernel_config", "workload"):
+        if w.get(key) != config.get(key):
+            return None
+    return block.get("pass_traffic_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--cmd-trace", required=True)
+    ap.add_argument("--cmd-fetch", required=True)
+    ap.add_argument("--cmd-write", required=True)
+    ap.add_argument("--bench-json", default=None)
+    ap.add_argument("--title", default="Fused pass kernel, exact QFT n = 28 complex64")
+    print(summarize(ap.parse_args()), end="")
+
+
+if __name__ == "__main__":
+    main()

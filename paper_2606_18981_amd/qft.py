@@ -62,6 +62,7 @@ class PlanInfo(ctypes.Structure):
         ("pass_bits", ctypes.c_int * QFT_MAX_PASSES),
         ("pass_spec", ctypes.c_int * QFT_MAX_PASSES),
         ("pass_reverse", ctypes.c_int * QFT_MAX_PASSES),
+        ("pass_tiles_per_wg", ctypes.c_int * QFT_MAX_PASSES),
         ("config", Config),
         ("gates_h", ctypes.c_longlong), ("gates_cr", ctypes.c_longlong),
         ("gates_swap", ctypes.c_longlong),
