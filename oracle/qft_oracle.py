@@ -23,6 +23,10 @@ Simulation"):
   Sec. 2 (gate fusion paragraph).  It is the vectorised form used for large n
   and is checked against the gate-by-gate form.
 * metrics: relative L2, max error, fidelity and top-bin leakage (Sec. 4).
+* ``inverse=True`` everywhere: the same circuit with every controlled phase
+  conjugated, R_m -> R_m^* (the e^{+} transform).  The H and swap gates are
+  real, so the circuit's matrix becomes its complex conjugate; the QFT and
+  AQFT matrices are symmetric, so that is also their adjoint (inverse).
 
 Conventions (readings of the paper; each is also listed in the design doc):
   - qubit q_j is bit j of the array index (Sec. 2: a 1-wire gate on q_j is
@@ -126,10 +130,13 @@ def bitrev_perm(n: int) -> np.ndarray:
 # the plain definition: naive DFT
 # ---------------------------------------------------------------------------
 
-def _omega_table(N: int) -> np.ndarray:
-    """w_N^m for m = 0..N-1 with w_N = exp(-2 pi i / N) (Sec. 2)."""
+def _omega_table(N: int, inverse: bool = False) -> np.ndarray:
+    """w_N^m for m = 0..N-1 with w_N = exp(-2 pi i / N) (Sec. 2); its
+    conjugate exp(+2 pi i m / N) for the inverse transform."""
     m = np.arange(N, dtype=np.float64)
     ang = 2.0 * np.pi * m / N
+    if inverse:
+        return np.cos(ang) + 1j * np.sin(ang)
     return np.cos(ang) - 1j * np.sin(ang)
 
 
@@ -139,19 +146,21 @@ def dft_matrix(N: int) -> np.ndarray:
     return _omega_table(N)[np.outer(k, k) % N]
 
 
-def dft_naive(x, norm: str = "unitary", order: str = "natural") -> np.ndarray:
+def dft_naive(x, norm: str = "unitary", order: str = "natural",
+              inverse: bool = False) -> np.ndarray:
     """O(N^2) DFT: y_k = s * sum_j x_j w_N^{jk} (Sec. 2 definition).
 
     The exponent j*k is reduced modulo N in integers before the table lookup,
     so every factor is an FP64 cos/sin of an angle in [0, 2 pi).  s follows
-    Sec. 3 step 4: 1/sqrt(N) (unitary), 1 (none), 1/N (inv_n).
+    Sec. 3 step 4: 1/sqrt(N) (unitary), 1 (none), 1/N (inv_n).  inverse=True
+    uses w_N^{-jk} (the e^{+} sign).
     """
     x = np.asarray(x, dtype=np.complex128)
     N = x.shape[0]
     n = N.bit_length() - 1
     if N != 1 << n:
         raise ValueError("N must be a power of two")
-    W = _omega_table(N)
+    W = _omega_table(N, inverse)
     j = np.arange(N, dtype=np.int64)
     y = np.empty(N, dtype=np.complex128)
     block = max(1, (1 << 22) // N)
@@ -215,11 +224,12 @@ def _apply_h(psi: np.ndarray, n: int, t: int) -> None:
     v[:, 1, :] = (a - b) * s
 
 
-def _apply_cr(psi: np.ndarray, n: int, c: int, t: int, m: int) -> None:
-    """Controlled-R_m: multiply amplitudes whose bits c and t are both 1."""
+def _apply_cr(psi: np.ndarray, n: int, c: int, t: int, m: int, conj: bool = False) -> None:
+    """Controlled-R_m (or R_m^* when conj): multiply amplitudes whose bits c
+    and t are both 1 by exp(-/+ 2 pi i / 2^m)."""
     assert c < t
     v = psi.reshape(1 << (n - 1 - t), 2, 1 << (t - 1 - c), 2, 1 << c)
-    v[:, 1, :, 1, :] *= np.exp(-2j * np.pi / float(1 << m))
+    v[:, 1, :, 1, :] *= np.exp((2j if conj else -2j) * np.pi / float(1 << m))
 
 
 def _apply_swap(psi: np.ndarray, n: int, a: int, b: int) -> np.ndarray:
@@ -230,7 +240,7 @@ def _apply_swap(psi: np.ndarray, n: int, a: int, b: int) -> np.ndarray:
 
 
 def qft_circuit(x, cutoff=None, norm: str = "unitary", order: str = "natural",
-                encode: bool = True) -> np.ndarray:
+                encode: bool = True, inverse: bool = False) -> np.ndarray:
     """Gate-by-gate FP64 simulation of the QFT->FFT method (Sec. 3).
 
     Step 1 (encode): scale_in = ||x||_2, psi = x / scale_in, index i <-> basis
@@ -239,6 +249,7 @@ def qft_circuit(x, cutoff=None, norm: str = "unitary", order: str = "natural",
       "bitrev" leaves the index permutation to the caller).
     Step 3 (evolve): apply the gates in order.
     Step 4 (decode): multiply by scale_in and by the norm factor.
+    inverse=True conjugates every controlled phase (the e^{+} transform).
     """
     x = np.asarray(x, dtype=np.complex128)
     N = x.shape[0]
@@ -255,20 +266,21 @@ def qft_circuit(x, cutoff=None, norm: str = "unitary", order: str = "natural",
         if g[0] == "H":
             _apply_h(psi, n, g[1])
         elif g[0] == "CR":
-            _apply_cr(psi, n, g[1], g[2], g[3])
+            _apply_cr(psi, n, g[1], g[2], g[3], inverse)
         elif order == "natural":
             psi = _apply_swap(psi, n, g[1], g[2])
     return psi * (scale_in * norm_factor(n, norm))
 
 
-def qft_circuit_matrix(n: int, cutoff=None, order: str = "natural") -> np.ndarray:
+def qft_circuit_matrix(n: int, cutoff=None, order: str = "natural",
+                       inverse: bool = False) -> np.ndarray:
     """Unitary of the circuit, column by column (small n only)."""
     N = 1 << n
     U = np.empty((N, N), dtype=np.complex128)
     for j in range(N):
         e = np.zeros(N, dtype=np.complex128)
         e[j] = 1.0
-        U[:, j] = qft_circuit(e, cutoff, "unitary", order, encode=False)
+        U[:, j] = qft_circuit(e, cutoff, "unitary", order, encode=False, inverse=inverse)
     return U
 
 
@@ -276,7 +288,7 @@ def qft_circuit_matrix(n: int, cutoff=None, order: str = "natural") -> np.ndarra
 # closed form of the range-k AQFT
 # ---------------------------------------------------------------------------
 
-def aqft_matrix(n: int, cutoff=None) -> np.ndarray:
+def aqft_matrix(n: int, cutoff=None, inverse: bool = False) -> np.ndarray:
     """Closed-form range-k AQFT matrix (output in natural order).
 
     Derivation from Fig. 1: the H on qubit t pairs input bit x_t with output
@@ -287,6 +299,8 @@ def aqft_matrix(n: int, cutoff=None) -> np.ndarray:
         A_k[y, x] = N^{-1/2} exp(-2 pi i sum_{n-1-k <= a+b <= n-1}
                                            x_a y_b 2^{a+b-n}).
     For k = n-1 this is the DFT (terms with a+b >= n are whole turns).
+    The condition on a+b is symmetric in (a, b), so A_k is symmetric.
+    inverse=True gives the conjugate-phase circuit, conj(A_k).
     """
     k = effective_cutoff(n, cutoff)
     N = 1 << n
@@ -298,7 +312,7 @@ def aqft_matrix(n: int, cutoff=None) -> np.ndarray:
             if n - 1 - k <= a + b <= n - 1:
                 P += np.outer(bits[:, b], bits[:, a]) << (a + b)
     P &= N - 1
-    return _omega_table(N)[P] / math.sqrt(N)
+    return _omega_table(N, inverse)[P] / math.sqrt(N)
 
 
 def _aqft_bin_coeffs(n: int, k: int, y: int) -> list:
@@ -314,11 +328,15 @@ def _aqft_bin_coeffs(n: int, k: int, y: int) -> list:
     return C
 
 
-def aqft_bins(x, bins, cutoff=None, norm: str = "unitary") -> np.ndarray:
+def aqft_bins(x, bins, cutoff=None, norm: str = "unitary", inverse: bool = False) -> np.ndarray:
     """Selected outputs (natural order) of the closed-form AQFT, O(N) per bin.
 
-    Uses the C helper when it is built (large N), else numpy.
+    Uses the C helper when it is built (large N), else numpy.  The inverse
+    (conjugate-phase) outputs are conj(A_k conj(x)), an exact identity since
+    the norm factors are real.
     """
+    if inverse:
+        return np.conj(aqft_bins(np.conj(np.asarray(x, dtype=np.complex128)), bins, cutoff, norm))
     x = np.ascontiguousarray(x, dtype=np.complex128)
     N = x.shape[0]
     n = N.bit_length() - 1
@@ -344,8 +362,11 @@ def aqft_bins(x, bins, cutoff=None, norm: str = "unitary") -> np.ndarray:
     return out * scale
 
 
-def dft_bins(x, bins, norm: str = "unitary") -> np.ndarray:
-    """Selected outputs y_k = s sum_j x_j w_N^{jk mod N} of the exact DFT."""
+def dft_bins(x, bins, norm: str = "unitary", inverse: bool = False) -> np.ndarray:
+    """Selected outputs y_k = s sum_j x_j w_N^{jk mod N} of the exact DFT
+    (w_N^{-jk} when inverse, computed as conj of the forward sums of conj x)."""
+    if inverse:
+        return np.conj(dft_bins(np.conj(np.asarray(x, dtype=np.complex128)), bins, norm))
     x = np.ascontiguousarray(x, dtype=np.complex128)
     N = x.shape[0]
     n = N.bit_length() - 1
@@ -366,15 +387,17 @@ def dft_bins(x, bins, norm: str = "unitary") -> np.ndarray:
     return out * scale
 
 
-def dft_library(x, norm: str = "unitary", order: str = "natural", workers: int = -1):
+def dft_library(x, norm: str = "unitary", order: str = "natural", workers: int = -1,
+                inverse: bool = False):
     """The exact DFT through a library FFT (scipy.fft, FP64), for full-size
     references at large N.  The library routine is the special case that
-    tests/test_oracle.py checks against ``dft_naive``."""
+    tests/test_oracle.py checks against ``dft_naive``.  inverse=True uses the
+    library inverse FFT times N (the unnormalised e^{+} sums)."""
     import scipy.fft
     x = np.asarray(x, dtype=np.complex128)
     N = x.shape[0]
     n = N.bit_length() - 1
-    y = scipy.fft.fft(x, workers=workers)
+    y = scipy.fft.ifft(x, workers=workers) * N if inverse else scipy.fft.fft(x, workers=workers)
     y *= norm_factor(n, norm) / math.sqrt(N)
     if order == "bitrev":
         out = np.empty_like(y)
@@ -388,7 +411,7 @@ def dft_library(x, norm: str = "unitary", order: str = "natural", workers: int =
 # ---------------------------------------------------------------------------
 
 def qft_fused_targets(x, cutoff=None, norm: str = "unitary",
-                      order: str = "natural") -> np.ndarray:
+                      order: str = "natural", inverse: bool = False) -> np.ndarray:
     """The circuit with the controlled phases of each target fused.
 
     Sec. 2 (gate fusion): commuting diagonal factors collapse into one
@@ -400,6 +423,7 @@ def qft_fused_targets(x, cutoff=None, norm: str = "unitary",
     unit-norm butterflies and a truncated twiddle index.
 
     No scale_in normalisation is applied here (the map is linear).
+    inverse=True conjugates every twiddle (the conjugate-phase circuit).
     """
     x = np.asarray(x, dtype=np.complex128)
     N = x.shape[0]
@@ -414,7 +438,7 @@ def qft_fused_targets(x, cutoff=None, norm: str = "unitary",
         u = np.arange(1 << t, dtype=np.int64)
         low = max(0, t - k)
         u = (u >> low) << low
-        tw = np.exp(-2j * np.pi * u.astype(np.float64) / float(1 << (t + 1)))
+        tw = np.exp((2j if inverse else -2j) * np.pi * u.astype(np.float64) / float(1 << (t + 1)))
         v[:, 0, :] = (a + b) * s
         v[:, 1, :] = (a - b) * s * tw[None, :]
     psi *= norm_factor(n, norm)

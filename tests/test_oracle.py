@@ -382,3 +382,74 @@ def test_metrics_definitions():
     assert O.max_err(y, ref) == pytest.approx(0.5 / (5.0 / 2.0))
     assert O.fidelity(ref, ref) == pytest.approx(1.0)
     assert O.top_bin_leakage(y, ref) == pytest.approx(1 - 16.0 / 25.25)
+
+
+# --------------------------------------------------------------------------
+# the inverse (conjugate-phase) transform
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", list(range(0, 10)))
+def test_inverse_naive_dft_is_numpy_ifft(n):
+    x = I.gaussian(n, 700 + n)
+    N = 1 << n
+    assert O.rel_l2(O.dft_naive(x, "unitary", inverse=True), np.fft.ifft(x, norm="ortho")) < TOL
+    assert O.rel_l2(O.dft_naive(x, "none", inverse=True), np.fft.ifft(x) * N) < TOL
+    assert O.rel_l2(O.dft_naive(x, "inv_n", inverse=True), np.fft.ifft(x)) < TOL
+    for norm in O.NORMS:
+        for order in O.ORDERS:
+            assert O.rel_l2(O.dft_library(x, norm, order, inverse=True),
+                            O.dft_naive(x, norm, order, inverse=True)) < TOL
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+@pytest.mark.parametrize("norm", ["unitary", "none", "inv_n"])
+def test_inverse_circuit_is_inverse_dft(n, norm):
+    x = I.gaussian(n, 710 + n)
+    for order in O.ORDERS:
+        ref = O.dft_naive(x, norm, order, inverse=True)
+        assert O.rel_l2(O.qft_circuit(x, None, norm, order, inverse=True), ref) < TOL
+        assert O.rel_l2(O.qft_fused_targets(x, None, norm, order, inverse=True), ref) < TOL
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 6])
+def test_aqft_is_symmetric_so_conjugate_is_inverse(n):
+    # the reading behind the inverse AQFT: the conjugate-phase circuit is the
+    # adjoint because the range-k AQFT matrix equals its transpose
+    for k in range(0, n):
+        A = O.qft_circuit_matrix(n, k)
+        assert np.max(np.abs(A - A.T)) < 1e-13
+        Ai = O.qft_circuit_matrix(n, k, inverse=True)
+        assert np.max(np.abs(Ai - np.conj(A))) < 1e-13
+        assert np.max(np.abs(Ai @ A - np.eye(1 << n))) < 1e-12
+        assert np.max(np.abs(O.aqft_matrix(n, k, inverse=True) - Ai)) < 1e-13
+
+
+@pytest.mark.parametrize("k", [None, 0, 2, 5])
+def test_inverse_undoes_forward(k):
+    n = 9
+    x = I.gaussian(n, 720)
+    y = O.qft_circuit(x, k, "unitary", "natural")
+    assert O.rel_l2(O.qft_circuit(y, k, "unitary", "natural", inverse=True), x) < TOL
+    # forward applied twice is the index reflection, not the identity: an
+    # "inverse" that kept the forward sign fails the check above
+    z = O.qft_circuit(y, None, "unitary", "natural") if k is None else None
+    if z is not None:
+        refl = x[(-np.arange(1 << n)) % (1 << n)]
+        assert O.rel_l2(z, refl) < TOL
+
+
+def test_inverse_tone_and_bins():
+    n = 12
+    N = 1 << n
+    b = 357
+    x = np.exp(-2j * np.pi * b * np.arange(N) / N)  # e^{-} tone: spike at bin b of the inverse
+    y = O.qft_fused_targets(x, None, "unitary", "natural", inverse=True)
+    spike = np.zeros(N, complex)
+    spike[b] = math.sqrt(N)
+    assert np.max(np.abs(y - spike)) < 1e-9
+    xg = I.gaussian(n, 730)
+    bins = np.array([0, 1, 17, 2048, 4095])
+    full = O.qft_fused_targets(xg, None, "unitary", "natural", inverse=True)
+    assert O.rel_l2(O.dft_bins(xg, bins, inverse=True), full[bins]) < TOL
+    full6 = O.qft_fused_targets(xg, 6, "unitary", "natural", inverse=True)
+    assert O.rel_l2(O.aqft_bins(xg, bins, 6, inverse=True), full6[bins]) < TOL
