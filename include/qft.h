@@ -63,6 +63,15 @@ typedef void *qft_stream_t; /* hipStream_t */
 #define QFT_PLAN_NO_WORKSPACE 0x8 /* the plan allocates no workspace: run it
                                   with qft_execute_ws (qft_execute then fails
                                   with QFT_ERR_POINTER if one is needed)      */
+#define QFT_INVERSE 0x10       /* the inverse transform: the same circuit with
+                                  every controlled phase conjugated, R_m ->
+                                  R_m^*, i.e. y_k = s * sum_j x_j
+                                  exp(+2 pi i j k / N) when exact.  H and the
+                                  swaps are real and the (A)QFT matrix is
+                                  symmetric, so this is its adjoint: with
+                                  QFT_NORM_UNITARY it undoes the forward plan
+                                  of the same cutoff; QFT_NORM_INV_N gives
+                                  the usual 1/N inverse FFT scale            */
 
 #define QFT_CUTOFF_EXACT (-1) /* any cutoff < 0 or >= n-1 is exact            */
 #define QFT_MAX_QUBITS 31
@@ -172,7 +181,7 @@ int qft_plan_set_timing(qft_plan_t *plan, int enable);
  * the number of timed executes; the accumulators are then cleared.          */
 int qft_plan_pass_times(qft_plan_t *plan, double *ms, int max, long long *execs);
 
-/* ---- batched uneven sizes (one persistent launch) ------------------------ */
+/* ---- batched uneven sizes (one graph launch) ----------------------------- */
 
 /* Transform count arrays, dev_ptrs[i] with plans[i], with one graph launch.
  * The tiles of all transforms are grouped by pass level, then by register

@@ -33,7 +33,7 @@ typedef struct qft_request {
   int n;            /* qubits (2^n amplitudes)                               */
   int cutoff;       /* AQFT range, or QFT_CUTOFF_EXACT                       */
   int norm;         /* QFT_NORM_*                                            */
-  int layout;       /* dtype | order flags (fused schedule only)             */
+  int layout;       /* dtype | order | QFT_INVERSE flags (fused schedule) */
   int dist;         /* input distribution, QFT_RNG_*                         */
   uint64_t seed;    /* Philox key of the request's input                     */
   double arrival;   /* seconds after the start of the run                    */

@@ -252,9 +252,16 @@ __device__ __forceinline__ void exchange(cplx<Real> (&v)[1 << RB], cplx<Real> *l
 }
 
 template <typename Real, int RB>
+__device__ __forceinline__ void conj_regs(cplx<Real> (&v)[1 << RB]) {
+#pragma unroll
+  for (int rho = 0; rho < (1 << RB); ++rho) v[rho].y = -v[rho].y;
+}
+
+template <typename Real, int RB>
 __device__ __forceinline__ void store_tile(const PassDesc &d, cplx<Real> (&v)[1 << RB],
                                            cplx<Real> *dst) {
   constexpr int R = 1 << RB;
+  if (d.conj_out) conj_regs<Real, RB>(v);
   uint32_t soff[R];
 #pragma unroll
   for (int rho = 0; rho < R; ++rho) soff[rho] = deposit_reg<RB>(rho, d.st_reg_w);
@@ -284,6 +291,7 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
     const C *src = in + (base | deposit_tid(tid, d.ld_thr_w, TR));
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) v[rho] = src[deposit_reg<RB>(rho, d.ld_reg_w)];
+    if (d.conj_in) conj_regs<Real, RB>(v);
   } else {
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) v[rho] = C{(Real)0, (Real)0};
@@ -383,6 +391,7 @@ k_fused_pass_pipe(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
   }
   auto step = [&](C (&v)[R], C (&nxt)[R], int i) {
     const uint32_t base = tile_base(d, tile0 + i);
+    if (d.conj_in) conj_regs<Real, RB>(v);
     C ef[RB], ef0;
     if (d.ext_tw) ext_factors<Real, RB>(d, base | st_thr, ef, ef0);
     if (i + 1 < K) {

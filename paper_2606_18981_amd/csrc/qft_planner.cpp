@@ -331,6 +331,10 @@ int plan_fused(HostPlan &p, std::string &err) {
     d.pbase = (int)g.spec_g.size();
     d.lo = g.lo;
     d.reverse = g.reverse ? 1 : 0;
+    // inverse: conj(F conj(x)) runs the conjugate-phase circuit with the
+    // forward tables; the conjugations ride on the first load and last store
+    d.conj_in = (p.inverse && i == 0) ? 1 : 0;
+    d.conj_out = (p.inverse && i + 1 == geo.size()) ? 1 : 0;
     d.ext_tw = g.lo > 0 ? 1 : 0;
     d.aqft = p.keff < n - 1 ? 1 : 0;
     d.k = p.keff;
@@ -376,6 +380,7 @@ void plan_gates(HostPlan &p) {
       if (d > p.keff) break;
       Gate g{1, t - d, t, d + 1, 0.0, 0.0};
       omega_pow2(d + 1, 1, &g.re, &g.im);  // R_{d+1}: exp(-2 pi i / 2^{d+1})
+      if (p.inverse) g.im = -g.im;         // R_{d+1}^* for the inverse
       p.gates.push_back(g);
     }
   }
@@ -466,7 +471,7 @@ int build_host_plan(int n, int cutoff, int norm, int layout, const qft_config_t 
     err = "norm must be QFT_NORM_UNITARY, QFT_NORM_NONE or QFT_NORM_INV_N";
     return QFT_ERR_INVALID;
   }
-  if (layout & ~0xF) {
+  if (layout & ~0x1F) {
     err = "unknown layout flag bits";
     return QFT_ERR_INVALID;
   }
@@ -477,6 +482,7 @@ int build_host_plan(int n, int cutoff, int norm, int layout, const qft_config_t 
   p.layout = layout;
   p.c128 = (layout & QFT_C128) != 0;
   p.bitrev = (layout & QFT_ORDER_BITREV) != 0;
+  p.inverse = (layout & QFT_INVERSE) != 0;
   p.schedule = (layout & QFT_SCHEDULE_GATES) ? Schedule::Gates : Schedule::Fused;
   p.elem_bytes = p.c128 ? 16 : 8;
   p.state_bytes = p.elem_bytes << n;

@@ -28,6 +28,7 @@ struct HostPlan {
   int layout = 0;
   bool c128 = false;
   bool bitrev = false;
+  bool inverse = false; // conjugate-phase circuit (QFT_INVERSE)
   Schedule schedule = Schedule::Fused;
   qft_config_t cfg{};  // resolved configuration
   size_t elem_bytes = 0;

@@ -24,6 +24,7 @@ QFT_ORDER_BITREV = 0x2
 QFT_SCHEDULE_FUSED = 0x0
 QFT_SCHEDULE_GATES = 0x4
 QFT_PLAN_NO_WORKSPACE = 0x8
+QFT_INVERSE = 0x10
 QFT_CUTOFF_EXACT = -1
 QFT_MAX_PASSES = 8
 QFT_RNG_GAUSSIAN = 0
@@ -139,8 +140,8 @@ def _check(rc: int):
         raise QftError(rc, last_error())
 
 
-def layout_flags(dtype="c64", order="natural", schedule="fused") -> int:
-    f = 0
+def layout_flags(dtype="c64", order="natural", schedule="fused", inverse: bool = False) -> int:
+    f = QFT_INVERSE if inverse else 0
     if dtype in ("c128", "complex128") or str(dtype) == "torch.complex128":
         f |= QFT_C128
     elif not (dtype in ("c64", "complex64") or str(dtype) == "torch.complex64"):
@@ -176,11 +177,12 @@ def _config(config) -> Optional[Config]:
 
 
 def describe(n: int, cutoff: int = -1, norm="unitary", dtype="c64", order="natural",
-             schedule="fused", config=None) -> PlanInfo:
+             schedule="fused", config=None, inverse: bool = False) -> PlanInfo:
     """Host-only planner description (no device use)."""
     info = PlanInfo()
     c = _config(config)
-    _check(lib.qft_plan_describe(n, cutoff, _norm(norm), layout_flags(dtype, order, schedule),
+    _check(lib.qft_plan_describe(n, cutoff, _norm(norm),
+                                 layout_flags(dtype, order, schedule, inverse),
                                  ctypes.byref(c) if c is not None else None, ctypes.byref(info)))
     return info
 
@@ -198,10 +200,11 @@ class Plan:
     """A planned 2^n-point transform (owns device tables and workspace)."""
 
     def __init__(self, n: int, cutoff: int = -1, norm="unitary", dtype="c64",
-                 order="natural", schedule="fused", config=None, workspace: bool = True):
+                 order="natural", schedule="fused", config=None, workspace: bool = True,
+                 inverse: bool = False):
         self.n = n
         self.cutoff = cutoff
-        self.layout = layout_flags(dtype, order, schedule)
+        self.layout = layout_flags(dtype, order, schedule, inverse)
         if not workspace:
             self.layout |= QFT_PLAN_NO_WORKSPACE
         self.c128 = bool(self.layout & QFT_C128)

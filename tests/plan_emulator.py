@@ -34,7 +34,7 @@ class PassDesc(ctypes.Structure):
         ("n", i32), ("T", i32), ("r", i32), ("m", i32), ("pbase", i32), ("lo", i32),
         ("ngroups", i32), ("reverse", i32), ("ext_tw", i32), ("aqft", i32), ("k", i32),
         ("nfree", i32), ("MI", i32), ("L", i32), ("xcd_remap", i32), ("pipe_k", i32),
-        ("ntiles", u32),
+        ("conj_in", i32), ("conj_out", i32), ("ntiles", u32),
         ("gpos_w", u32 * 4), ("free_w", u32 * 8),
         ("ld_thr_w", u32 * 4), ("ld_reg_w", u32 * 2),
         ("st_thr_w", u32 * 4), ("st_reg_w", u32 * 2),
@@ -136,6 +136,8 @@ def run_pass(d, launch, src, tables, c128, check=True):
         allidx = np.concatenate([a.ravel() for a in ld_idx])
         assert np.unique(allidx).size == allidx.size == (1 << d.n), "loads are not a permutation"
     v = [src[i].astype(np.complex128) for i in ld_idx]
+    if d.conj_in:
+        v = [np.conj(a) for a in v]
 
     for gi in range(d.ngroups):
         G = d.grp[gi]
@@ -216,6 +218,8 @@ def run_pass(d, launch, src, tables, c128, check=True):
             v[rho] = v[rho] * F
     else:
         v = [x * d.scale for x in v]
+    if d.conj_out:
+        v = [np.conj(a) for a in v]
     out_idx, out_val = [], []
     for rho in range(R):
         idx = g | dep_reg(rho, P(d.st_reg_w))
@@ -228,10 +232,11 @@ def run_pass(d, launch, src, tables, c128, check=True):
     return out_idx, out_val
 
 
-def emulate(x, n, cutoff=-1, norm="unitary", dtype="c64", order="natural", config=None):
-    layout = Q.layout_flags(dtype, order, "fused")
+def emulate(x, n, cutoff=-1, norm="unitary", dtype="c64", order="natural", config=None,
+            inverse=False):
+    layout = Q.layout_flags(dtype, order, "fused", inverse)
     c128 = bool(layout & Q.QFT_C128)
-    info = Q.describe(n, cutoff, norm, dtype, order, "fused", config)
+    info = Q.describe(n, cutoff, norm, dtype, order, "fused", config, inverse)
     tables = get_tables(n, cutoff, norm, layout, config)
     state = np.asarray(x, dtype=np.complex128).copy()
     ws = np.zeros_like(state)

@@ -112,3 +112,24 @@ def test_full_uneven_batch_512(env):
             assert O.rel_l2(y.astype(np.complex128), ref) <= 1e-5
     for p in cache.values():
         p.close()
+
+
+def test_batch_with_inverse_plans(env):
+    torch, Q = env
+    ns = [10, 14, 17, 12, 19, 9]
+    ks = [-1, -1, 6, 3, -1, -1]
+    inv = [True, False, True, False, True, True]
+    plans, xs, hosts = [], [], []
+    for i, (n, k, v) in enumerate(zip(ns, ks, inv)):
+        plans.append(Q.Plan(n, k, "unitary", "c64", "natural", inverse=v))
+        x = I.uniform_pm1(n, 7000 + i)
+        hosts.append(x)
+        xs.append(torch.from_numpy(x.astype(np.complex64)).cuda())
+    print(f"[gpu] batch with inverse plans n={ns}", flush=True)
+    Q.execute_batch(plans, xs, graph=True)
+    torch.cuda.synchronize()
+    for t, x, n, k, v in zip(xs, hosts, ns, ks, inv):
+        ref = O.qft_fused_targets(x, None if k < 0 else k, inverse=v)
+        assert O.rel_l2(t.cpu().numpy().astype(np.complex128), ref) <= 1e-5
+    for p in plans:
+        p.close()

@@ -31,10 +31,10 @@ def Q():
 
 
 def run_gpu(torch, Q, x, n, cutoff=-1, norm="unitary", dtype="c64", order="natural",
-            schedule="fused", config=None):
+            schedule="fused", config=None, inverse=False):
     print(f"[gpu] n={n} cutoff={cutoff} norm={norm} dtype={dtype} order={order} "
-          f"schedule={schedule} config={config}", flush=True)
-    plan = Q.Plan(n, cutoff, norm, dtype, order, schedule, config)
+          f"schedule={schedule} config={config} inverse={inverse}", flush=True)
+    plan = Q.Plan(n, cutoff, norm, dtype, order, schedule, config, inverse=inverse)
     t = torch.from_numpy(np.asarray(x).astype(NPDT[dtype])).to("cuda")
     plan.execute(t)
     torch.cuda.synchronize()
@@ -43,12 +43,12 @@ def run_gpu(torch, Q, x, n, cutoff=-1, norm="unitary", dtype="c64", order="natur
     return y
 
 
-def oracle_ref(x, cutoff, norm, order):
+def oracle_ref(x, cutoff, norm, order, inverse=False):
     n = int(np.log2(len(x)))
     k = None if cutoff < 0 else cutoff
     if n <= 11:
-        return O.qft_circuit(x, k, norm, order)
-    return O.qft_fused_targets(x, k, norm, order)
+        return O.qft_circuit(x, k, norm, order, inverse=inverse)
+    return O.qft_fused_targets(x, k, norm, order, inverse=inverse)
 
 
 # ---- config 1: plain exact n = 10, complex128, gate by gate ---------------
@@ -165,6 +165,56 @@ def test_n28_sampled_bins(torch_cuda, Q, k):
     assert O.rel_l2(y[bins], ref) <= TOL["c64"]
     # the AQFT is unitary: Parseval at any size
     assert np.linalg.norm(y) == pytest.approx(np.linalg.norm(x), rel=1e-5)
+
+
+# ---- inverse (conjugate-phase) transform ----------------------------------
+
+INV = []
+for n in (1, 5, 10, 13, 14, 20):
+    for dt in ("c64", "c128"):
+        INV.append((n, -1, dt, "natural", "unitary", "fused"))
+INV += [(12, 3, "c64", "bitrev", "none", "fused"), (18, 6, "c128", "natural", "inv_n", "fused"),
+        (9, -1, "c128", "natural", "unitary", "gates"), (11, 4, "c64", "bitrev", "inv_n", "gates")]
+
+
+@pytest.mark.parametrize("n,k,dtype,order,norm,schedule", INV)
+def test_inverse_sweep(torch_cuda, Q, n, k, dtype, order, norm, schedule):
+    x = I.gaussian(n, 6000 + n)
+    y = run_gpu(torch_cuda, Q, x, n, k, norm, dtype, order, schedule, inverse=True)
+    assert O.rel_l2(y, oracle_ref(x, k, norm, order, inverse=True)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("cfg", [CONFIGS[4], CONFIGS[5], CONFIGS[8]])
+def test_inverse_kernel_configs(torch_cuda, Q, cfg):
+    n = 20
+    for dt in ("c64", "c128"):
+        x = I.uniform_pm1(n, 6100)
+        y = run_gpu(torch_cuda, Q, x, n, 5, "unitary", dt, "natural", "fused", cfg, inverse=True)
+        assert O.rel_l2(y, oracle_ref(x, 5, "unitary", "natural", inverse=True)) <= TOL[dt]
+
+
+@pytest.mark.parametrize("k", [-1, 7])
+def test_forward_then_inverse_is_identity(torch_cuda, Q, k):
+    torch = torch_cuda
+    n = 22
+    x = I.gaussian(n, 6200)
+    t = torch.from_numpy(x).cuda()
+    fwd = Q.Plan(n, k, "unitary", "c128", "natural")
+    inv = Q.Plan(n, k, "unitary", "c128", "natural", inverse=True)
+    fwd.execute(t)
+    inv.execute(t)
+    torch.cuda.synchronize()
+    assert O.rel_l2(t.cpu().numpy(), x) <= 1e-12
+    fwd.close()
+    inv.close()
+
+
+def test_n28_inverse_sampled_bins(torch_cuda, Q):
+    n = 28
+    x = I.gaussian(n, 1003)
+    y = run_gpu(torch_cuda, Q, x, n, -1, "unitary", "c64", "natural", inverse=True)
+    bins = np.random.default_rng(29).choice(1 << n, 12, replace=False)
+    assert O.rel_l2(y[bins], O.dft_bins(x, bins, inverse=True)) <= TOL["c64"]
 
 
 # ---- device input generator ------------------------------------------------

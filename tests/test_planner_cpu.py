@@ -52,7 +52,7 @@ def test_descriptor_layout_matches():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(n=0), dict(n=32), dict(n=-3), dict(norm=7), dict(layout=0x10), dict(layout=0x20),
+    dict(n=0), dict(n=32), dict(n=-3), dict(norm=7), dict(layout=0x20), dict(layout=0x40),
 ])
 def test_invalid_arguments(bad):
     args = dict(n=10, cutoff=-1, norm=0, layout=0)
@@ -214,3 +214,36 @@ def test_emulated_three_pass_plan():
     for k in (None, 8):
         y = E.emulate(x, n, -1 if k is None else k, "unitary", "c64", "natural")
         assert O.rel_l2(y, O.qft_fused_targets(x, k)) < 2e-6
+
+
+INV_CASES = [
+    (6, None, "unitary", "c128", "natural", None),
+    (12, 4, "none", "c64", "bitrev", None),
+    (17, None, "inv_n", "c128", "natural", dict(tile_log2=9, radix_log2=3, spec_log2=2,
+                                                 rev_spec_log2=2)),
+    (20, 6, "unitary", "c128", "natural", dict(tile_log2=10, radix_log2=4, spec_log2=3,
+                                                rev_spec_log2=3, tiles_per_wg=4)),
+]
+
+
+@pytest.mark.parametrize("n,k,norm,dtype,order,cfg", INV_CASES)
+def test_emulated_inverse_matches_oracle(n, k, norm, dtype, order, cfg):
+    x = I.gaussian(n, 1500 + n)
+    y = E.emulate(x, n, -1 if k is None else k, norm, dtype, order, cfg, inverse=True)
+    ref = O.qft_fused_targets(x, k, norm, order, inverse=True)
+    assert O.rel_l2(y, ref) < (1e-12 if dtype == "c128" else 2e-6)
+
+
+def test_inverse_descriptor_flags():
+    layout = Q.layout_flags("c64", inverse=True)
+    info = Q.describe(28, inverse=True)
+    assert info.layout & Q.QFT_INVERSE
+    P = info.num_passes
+    for p in range(P):
+        d, _ = E.get_pass(28, -1, "unitary", layout, None, p)
+        assert d.conj_in == (1 if p == 0 else 0) and d.conj_out == (1 if p == P - 1 else 0)
+    d, _ = E.get_pass(28, -1, "unitary", Q.layout_flags("c64"), None, 0)
+    assert d.conj_in == 0 and d.conj_out == 0
+    # one-pass plan: both on the same pass
+    d, _ = E.get_pass(10, -1, "unitary", layout, None, 0)
+    assert d.conj_in == 1 and d.conj_out == 1
