@@ -221,17 +221,11 @@ def main():
     gflops = flops / (ms_per_step * 1e-3) / 1e9
     state_bytes = info.state_bytes
     per_launch_bytes = 2 * state_bytes  # one read and one write of the state
-    # dominant kernel: every pass launches the fused-pass kernel (one tile per
-    # workgroup, or the variant that walks several tiles per workgroup); the
+    # dominant kernel: every pass launches the fused-pass kernel; the
     # roofline uses its mean launch time over the timed region
     mean_pass_ms = sum(pass_ms) / len(pass_ms)
-    rb = info.config.radix_log2
     real = "float" if args.dtype == "c64" else "double"
-    kernels = []
-    for p in range(info.num_passes):
-        kpw = info.pass_tiles_per_wg[p]
-        kernels.append(f"k_fused_pass_pipe<{real}, {rb}> (tiles per workgroup {kpw})"
-                       if kpw > 1 else f"k_fused_pass<{real}, {rb}>")
+    kernel = f"k_fused_pass<{real}, {info.config.radix_log2}>"
     achieved = per_launch_bytes / (mean_pass_ms * 1e-3) / 1e9
     hbm_gbs = info.hbm_bytes / (ms_per_step * 1e-3) / 1e9
 
@@ -266,7 +260,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "fused pass kernel, mean over the plan's passes: " + "; ".join(kernels),
+            "kernel": f"{kernel}, mean over the plan's {info.num_passes} passes",
             "algorithmic_bytes_per_launch": per_launch_bytes,
         },
     }

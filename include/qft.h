@@ -94,9 +94,6 @@ typedef void *qft_stream_t; /* hipStream_t */
  *              high-order passes (coalescing width 2^spec_log2)
  * rev_spec_log2: contiguous output elements per run in the final
  *              bit-reversing pass (natural order only)
- * tiles_per_wg: tiles each workgroup of a pass works through, loading the
- *              next tile while it computes the current one (1 = one tile
- *              per workgroup)
  * pass_bits:   qubits of each HBM pass, most significant pass first,
  *              summing to n (all zero = planner's choice: the fewest passes,
  *              middle passes as wide as the tile allows, the rest split
@@ -107,7 +104,6 @@ typedef struct qft_config {
   int radix_log2;
   int spec_log2;
   int rev_spec_log2;
-  int tiles_per_wg;
   int pass_bits[QFT_MAX_PASSES];
 } qft_config_t;
 
@@ -123,8 +119,6 @@ typedef struct qft_plan_info {
   int pass_bits[QFT_MAX_PASSES]; /* qubits applied by pass p                 */
   int pass_spec[QFT_MAX_PASSES]; /* spectator (coalescing) bits of pass p    */
   int pass_reverse[QFT_MAX_PASSES]; /* pass p writes bit-reversed addresses  */
-  int pass_tiles_per_wg[QFT_MAX_PASSES]; /* tiles walked by one workgroup of
-                                            pass p (1: one tile each)        */
   qft_config_t config;
   long long gates_h, gates_cr, gates_swap;
   size_t state_bytes;     /* 2^n * element size                              */

@@ -100,7 +100,6 @@ int build_entry(BatchEntry *e) {
       g.lds = std::max(g.lds, L.lds_bytes);
       PassDesc d = L.d;
       d.xcd_remap = 0;
-      d.pipe_k = 0;
       descs.push_back(d);
       BatchIO b;
       b.in = L.in_ws ? ws[j] : e->ptrs[j];

@@ -68,7 +68,6 @@ struct PassDesc {
   int32_t MI;       // internal twiddle table: w_{2^MI}^y, y < 2^(MI-1)
   int32_t L;        // split of the two-level w_N table
   int32_t xcd_remap;// 1: XCD-aware tile order
-  int32_t pipe_k;   // > 1: pipelined kernel, tiles per workgroup
   int32_t conj_in;  // 1: conjugate the loaded elements (first pass, inverse)
   int32_t conj_out; // 1: conjugate the stored elements (last pass, inverse)
   uint32_t ntiles;

@@ -156,13 +156,6 @@ __device__ __forceinline__ void apply_factors(cplx<Real> (&v)[1 << RB], const cp
   }
 }
 
-template <typename Real>
-__device__ __forceinline__ cplx<Real> omega_n(const PassDesc &d, uint32_t E) {
-  const cplx<Real> *__restrict__ tlo = (const cplx<Real> *)d.tw_lo;
-  const cplx<Real> *__restrict__ thi = (const cplx<Real> *)d.tw_hi;
-  return cmul(tlo[E & ((1u << d.L) - 1u)], thi[E >> d.L]);
-}
-
 // Index of the tile's first element: the tile number deposited into the
 // non-tile bit positions.
 __device__ __forceinline__ uint32_t tile_base(const PassDesc &d, uint32_t tile) {
@@ -196,12 +189,21 @@ __device__ __forceinline__ void group_factors(const PassDesc &d, const GroupMap 
 // w_N^E with E = sum over set pass bits j of trunc_{lo+j-k}(vv) 2^{n-1-lo-j}
 // (vv = index bits below the pass).  All register bits of the store map are
 // pass bits, so E = E_thr + sum over set register bits q of c_q: the factors
-// are f0 = w_N^{E_thr} (times the pass scale) and f[q] = w_N^{c_q}.
-// g = index of the thread's register-0 element.
+// are f0 = w_N^{E_thr} (times the pass scale) and f[q] = w_N^{c_q}.  Each is
+// the product of a low-table and a high-table entry.  ext_loads issues the
+// table reads (g = index of the thread's register-0 element); ext_finish
+// multiplies them, so that the reads can be in flight with the tile's own.
 template <typename Real, int RB>
-__device__ __forceinline__ void ext_factors(const PassDesc &d, uint32_t g, cplx<Real> (&f)[RB],
-                                            cplx<Real> &f0) {
+struct ExtRaw {
+  cplx<Real> lo[RB + 1], hi[RB + 1];  // [RB] is f0's pair
+};
+
+template <typename Real, int RB>
+__device__ __forceinline__ void ext_loads(const PassDesc &d, uint32_t g, ExtRaw<Real, RB> &raw) {
+  const cplx<Real> *__restrict__ tlo = (const cplx<Real> *)d.tw_lo;
+  const cplx<Real> *__restrict__ thi = (const cplx<Real> *)d.tw_hi;
   const uint32_t nmask = d.n >= 32 ? 0xffffffffu : ((1u << d.n) - 1u);
+  const uint32_t lmask = (1u << d.L) - 1u;
   const uint32_t vv = g & ((1u << d.lo) - 1u);
   const uint32_t pt = (g >> d.lo) & ((1u << d.m) - 1u);
   uint32_t Et = 0;
@@ -216,14 +218,25 @@ __device__ __forceinline__ void ext_factors(const PassDesc &d, uint32_t g, cplx<
       }
     }
   }
+  raw.lo[RB] = tlo[Et & lmask];
+  raw.hi[RB] = thi[Et >> d.L];
 #pragma unroll
   for (int q = 0; q < RB; ++q) {
     const int j = (int)pos_get(d.st_reg_w, q) - d.lo;
     const int s = d.lo + j - d.k;
     const uint32_t tv = (!d.aqft || s <= 0) ? vv : (s >= d.lo ? 0u : ((vv >> s) << s));
-    f[q] = omega_n<Real>(d, (tv << (d.n - 1 - d.lo - j)) & nmask);
+    const uint32_t E = (tv << (d.n - 1 - d.lo - j)) & nmask;
+    raw.lo[q] = tlo[E & lmask];
+    raw.hi[q] = thi[E >> d.L];
   }
-  f0 = omega_n<Real>(d, Et);
+}
+
+template <typename Real, int RB>
+__device__ __forceinline__ void ext_finish(const PassDesc &d, const ExtRaw<Real, RB> &raw,
+                                           cplx<Real> (&f)[RB], cplx<Real> &f0) {
+#pragma unroll
+  for (int q = 0; q < RB; ++q) f[q] = cmul(raw.lo[q], raw.hi[q]);
+  f0 = cmul(raw.lo[RB], raw.hi[RB]);
   const Real scale = (Real)d.scale;
   f0.x *= scale;
   f0.y *= scale;
@@ -274,9 +287,11 @@ __device__ __forceinline__ void store_tile(const PassDesc &d, cplx<Real> (&v)[1 
 // lower pass bits (deferred to the end of the group), then an LDS exchange to
 // the next group's mapping.  At the end: the diagonal of the controls below
 // the pass (high passes), the folded scale, and the store (bit-reversed
-// addresses in the final pass of a natural-order plan).  Threads with
-// active == false (workgroups larger than the tile needs) only take part in
-// the barriers.
+// addresses in the final pass of a natural-order plan).  The twiddle-table
+// reads of the first two groups and of the final diagonal are issued before
+// the tile's loads, so the tile waits for one memory latency, not one per
+// table.  Threads with active == false (workgroups larger than the tile
+// needs) only take part in the barriers.
 template <typename Real, int RB>
 __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, const cplx<Real> *in,
                                           cplx<Real> *out, cplx<Real> *lds, uint32_t tid,
@@ -285,6 +300,17 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
   constexpr int R = 1 << RB;
   const int TR = d.T - RB;
   const uint32_t base = tile_base(d, tile);
+  const uint32_t st_thr = deposit_tid(tid, d.st_thr_w, TR);
+
+  const bool has0 = d.ngroups > 0 && d.grp[0].jbase > 0 && d.grp[0].nst > 0;
+  const bool has1 = d.ngroups > 1 && d.grp[1].jbase > 0 && d.grp[1].nst > 0;
+  C gf0[RB], gf1[RB];
+  ExtRaw<Real, RB> raw;
+  if (active) {
+    if (has0) group_factors<Real, RB>(d, d.grp[0], deposit_tid(tid, d.grp[0].thr_w, TR), gf0);
+    if (has1) group_factors<Real, RB>(d, d.grp[1], deposit_tid(tid, d.grp[1].thr_w, TR), gf1);
+    if (d.ext_tw) ext_loads<Real, RB>(d, base | st_thr, raw);
+  }
 
   C v[R];
   if (active) {
@@ -297,11 +323,15 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
     for (int rho = 0; rho < R; ++rho) v[rho] = C{(Real)0, (Real)0};
   }
 
-  for (int gi = 0; gi < d.ngroups; ++gi) {
+  radix_network<Real, RB>(v, d.grp[0].nst);
+  if (has0 && active) apply_factors<Real, RB>(v, gf0, C{(Real)1, (Real)0}, false);
+  for (int gi = 1; gi < d.ngroups; ++gi) {
     const GroupMap &G = d.grp[gi];
-    if (gi > 0) exchange<Real, RB>(v, lds, d.grp[gi - 1], G, tid, TR, active);
+    exchange<Real, RB>(v, lds, d.grp[gi - 1], G, tid, TR, active);
     radix_network<Real, RB>(v, G.nst);
-    if (G.jbase > 0 && G.nst > 0 && active) {
+    if (gi == 1) {
+      if (has1 && active) apply_factors<Real, RB>(v, gf1, C{(Real)1, (Real)0}, false);
+    } else if (G.jbase > 0 && G.nst > 0 && active) {
       C f[RB];
       group_factors<Real, RB>(d, G, deposit_tid(tid, G.thr_w, TR), f);
       apply_factors<Real, RB>(v, f, C{(Real)1, (Real)0}, false);
@@ -310,10 +340,9 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
   if (!active) return;
 
   const uint32_t obase = d.reverse ? rev_bits(base, d.n) : base;
-  const uint32_t st_thr = deposit_tid(tid, d.st_thr_w, TR);
   if (d.ext_tw) {
     C f[RB], f0;
-    ext_factors<Real, RB>(d, base | st_thr, f, f0);
+    ext_finish<Real, RB>(d, raw, f, f0);
     apply_factors<Real, RB>(v, f, f0, true);
   } else {
     const Real scale = (Real)d.scale;
@@ -329,7 +358,7 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
 }
 
 template <typename Real, int RB>
-__global__ void __launch_bounds__(sizeof(Real) == 8 ? (RB >= 5 ? 256 : RB >= 4 ? 512 : 1024)
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? (RB >= 5 ? 256 : RB >= 3 ? 512 : 1024)
                                                    : (RB >= 5 ? 512 : 1024))
 k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
   extern __shared__ __align__(16) unsigned char qft_smem[];
@@ -343,109 +372,16 @@ k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
                       true);
 }
 
-// Pipelined pass: workgroup w applies the pass to tiles_per_wg consecutive
-// tiles; the loads of tile i+1 are issued before tile i is computed, so HBM
-// stays busy during the register networks, the LDS exchanges and the stores.
-// The per-group factors do not depend on the tile and are loaded once, and
-// the below-pass factors of tile i are loaded before the prefetch, so no wait
-// for a factor has to wait for the prefetched data.  Requires that groups
-// from the third on carry no per-thread factors (the planner checks).
-// (twice the data registers of k_fused_pass: the launch bounds halve the
-// workgroup size so that the register budget doubles)
-template <typename Real, int RB>
-__global__ void __launch_bounds__(sizeof(Real) == 8
-                                      ? (RB >= 5 ? 128 : RB >= 4 ? 256 : RB >= 3 ? 512 : 1024)
-                                      : (RB >= 5 ? 256 : RB >= 4 ? 512 : 1024))
-k_fused_pass_pipe(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
-  using C = cplx<Real>;
-  constexpr int R = 1 << RB;
-  extern __shared__ __align__(16) unsigned char qft_smem[];
-  C *lds = reinterpret_cast<C *>(qft_smem);
-  const uint32_t tid = threadIdx.x;
-  const int TR = d.T - RB;
-  const int K = d.pipe_k;
-  uint32_t wg = blockIdx.x;
-  if (d.xcd_remap) {
-    const uint32_t per = gridDim.x >> 3;
-    wg = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
-  }
-  const uint32_t tile0 = wg * (uint32_t)K;
-  const uint32_t ld_thr = deposit_tid(tid, d.ld_thr_w, TR);
-  const uint32_t st_thr = deposit_tid(tid, d.st_thr_w, TR);
-  uint32_t ld_off[R];
-#pragma unroll
-  for (int rho = 0; rho < R; ++rho) ld_off[rho] = deposit_reg<RB>(rho, d.ld_reg_w);
-
-  // tile-independent factors of the first two groups
-  C gf0[RB], gf1[RB];
-  const bool has0 = d.ngroups > 0 && d.grp[0].jbase > 0 && d.grp[0].nst > 0;
-  const bool has1 = d.ngroups > 1 && d.grp[1].jbase > 0 && d.grp[1].nst > 0;
-  if (has0) group_factors<Real, RB>(d, d.grp[0], deposit_tid(tid, d.grp[0].thr_w, TR), gf0);
-  if (has1) group_factors<Real, RB>(d, d.grp[1], deposit_tid(tid, d.grp[1].thr_w, TR), gf1);
-
-  C va[R], vb[R];
-  {
-    const C *src = in + (tile_base(d, tile0) | ld_thr);
-#pragma unroll
-    for (int rho = 0; rho < R; ++rho) va[rho] = src[ld_off[rho]];
-  }
-  auto step = [&](C (&v)[R], C (&nxt)[R], int i) {
-    const uint32_t base = tile_base(d, tile0 + i);
-    if (d.conj_in) conj_regs<Real, RB>(v);
-    C ef[RB], ef0;
-    if (d.ext_tw) ext_factors<Real, RB>(d, base | st_thr, ef, ef0);
-    if (i + 1 < K) {
-      const C *src = in + (tile_base(d, tile0 + i + 1) | ld_thr);
-#pragma unroll
-      for (int rho = 0; rho < R; ++rho) nxt[rho] = src[ld_off[rho]];
-    }
-    // groups 0 and 1 (peeled: their factor arrays stay in registers)
-    radix_network<Real, RB>(v, d.grp[0].nst);
-    if (has0) apply_factors<Real, RB>(v, gf0, C{(Real)1, (Real)0}, false);
-    if (d.ngroups > 1) {
-      exchange<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR, true);
-      radix_network<Real, RB>(v, d.grp[1].nst);
-      if (has1) apply_factors<Real, RB>(v, gf1, C{(Real)1, (Real)0}, false);
-    }
-    for (int gi = 2; gi < d.ngroups; ++gi) {
-      exchange<Real, RB>(v, lds, d.grp[gi - 1], d.grp[gi], tid, TR, true);
-      radix_network<Real, RB>(v, d.grp[gi].nst);
-    }
-    if (d.ext_tw) {
-      apply_factors<Real, RB>(v, ef, ef0, true);
-    } else {
-      const Real scale = (Real)d.scale;
-      if (scale != (Real)1) {
-#pragma unroll
-        for (int rho = 0; rho < R; ++rho) {
-          v[rho].x *= scale;
-          v[rho].y *= scale;
-        }
-      }
-    }
-    const uint32_t obase = d.reverse ? rev_bits(base, d.n) : base;
-    store_tile<Real, RB>(d, v, out + (obase | st_thr));
-  };
-  for (int i = 0; i < K; i += 2) {
-    step(va, vb, i);
-    if (i + 1 < K) step(vb, va, i + 1);
-  }
-}
-
 template <typename Real, int RB>
 static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, hipStream_t s) {
-  // (no pipelined instance for complex128 at radix 32: it does not fit the
-  // register file; the planner never asks for it)
-  auto fn = (L.d.pipe_k > 1 && !(sizeof(Real) == 8 && RB >= 5)) ? k_fused_pass_pipe<Real, RB>
-                                                                 : k_fused_pass<Real, RB>;
+  auto fn = k_fused_pass<Real, RB>;
   if (L.lds_bytes > 65536) {
-    static int set[2] = {0, 0};
-    const int which = L.d.pipe_k > 1 ? 1 : 0;
-    if (!set[which]) {
+    static int set = 0;
+    if (!set) {
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
       if (e != hipSuccess) return e;
-      set[which] = 1;
+      set = 1;
     }
   }
   hipLaunchKernelGGL(fn, dim3(L.grid), dim3(L.threads), L.lds_bytes, s, L.d,
@@ -486,7 +422,7 @@ hipError_t launch_fused_pass(const PassLaunch &L, bool c128, const void *in, voi
 // segments' first items.  Passes of one transform are in different launches,
 // ordered on the stream, so no workgroup ever waits for another.
 template <typename Real, int RB>
-__global__ void __launch_bounds__(sizeof(Real) == 8 ? (RB >= 5 ? 256 : RB >= 4 ? 512 : 1024)
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? (RB >= 5 ? 256 : RB >= 3 ? 512 : 1024)
                                                    : (RB >= 5 ? 512 : 1024))
 k_batch_group(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__restrict__ descs,
               const BatchIO *__restrict__ io) {

@@ -58,10 +58,6 @@ int check_config(const qft_config_t &c, std::string &err) {
     err = "tile_log2 must be in [radix_log2, 15]";
     return QFT_ERR_INVALID;
   }
-  if (c.tiles_per_wg < 0 || c.tiles_per_wg > 64 || (c.tiles_per_wg & (c.tiles_per_wg - 1))) {
-    err = "tiles_per_wg must be 0 or a power of two up to 64";
-    return QFT_ERR_INVALID;
-  }
   if (c.spec_log2 < 0 || c.spec_log2 >= c.tile_log2 || c.rev_spec_log2 < 0 ||
       c.rev_spec_log2 >= c.tile_log2) {
     err = "spec_log2 and rev_spec_log2 must be in [0, tile_log2)";
@@ -158,15 +154,8 @@ void build_groups(PassLaunch &L, const PassGeom &g, int r, int n) {
 // log2 of the largest workgroup the kernel instance for (r, dtype) allows
 // (its launch bounds keep the register tile of 2^r elements free of spills)
 int max_thread_bits(int r, bool c128) {
-  if (c128) return r >= 5 ? 8 : r >= 4 ? 9 : 10;
+  if (c128) return r >= 5 ? 8 : r >= 3 ? 9 : 10;
   return r >= 5 ? 9 : 10;
-}
-
-// the same for the pipelined kernel, which holds two tiles in registers
-// (-1: no pipelined instance for this radix)
-int pipe_max_thread_bits(int r, bool c128) {
-  if (c128) return r >= 5 ? -1 : r >= 4 ? 8 : r >= 3 ? 9 : 10;
-  return r >= 5 ? 8 : r >= 4 ? 9 : 10;
 }
 
 int plan_fused(HostPlan &p, std::string &err) {
@@ -341,26 +330,26 @@ int plan_fused(HostPlan &p, std::string &err) {
     d.MI = MI;
     d.L = p.L;
     build_groups(L, g, r, n);
-    // non-tile bits, ascending
+    // Non-tile bits, in the order in which the tile number fills them.
+    // Workgroups with consecutive numbers run at the same time, so the low
+    // tile-number bits go to the non-tile bits nearest the bottom of the
+    // address that the pass writes: ascending input bits for a pass that
+    // writes in place, descending for the bit-reversing pass (input bit b is
+    // output bit n-1-b).  Concurrent workgroups then write neighbouring
+    // memory.
     std::vector<int> in_tile(n, 0);
     for (int q = 0; q < Te; ++q) in_tile[pos_get(d.gpos_w, q)] = 1;
     int nf = 0;
-    for (int b = 0; b < n; ++b)
+    for (int j = 0; j < n; ++j) {
+      const int b = g.reverse ? n - 1 - j : j;
       if (!in_tile[b]) pos_set(d.free_w, nf++, b);
+    }
     d.nfree = nf;
     d.ntiles = 1u << nf;
     d.scale = scales[i];
     L.threads = 1 << (Te - r);
     L.lds_bytes = d.ngroups > 1 ? (int)(((size_t)1 << Te) * es) : 0;
-    // pipelined kernel: K consecutive tiles per workgroup, when every group
-    // from the third on carries no per-thread factors
-    int K = std::max(1, c.tiles_per_wg);
-    bool pipe_ok = K > 1 && d.ntiles % (uint32_t)K == 0 &&
-                   Te - r <= pipe_max_thread_bits(r, p.c128);
-    for (int gi = 2; gi < d.ngroups && pipe_ok; ++gi)
-      if (d.grp[gi].jbase > 0 && d.grp[gi].nst > 0) pipe_ok = false;
-    d.pipe_k = pipe_ok ? K : 0;
-    L.grid = pipe_ok ? d.ntiles / (uint32_t)K : d.ntiles;
+    L.grid = d.ntiles;
     d.xcd_remap = (L.grid >= 8 && L.grid % 8 == 0) ? 1 : 0;
     if (natural_multi) {
       L.in_ws = i == 0 ? 0 : 1;
@@ -499,7 +488,6 @@ int build_host_plan(int n, int cutoff, int norm, int layout, const qft_config_t 
     c.spec_log2 = std::min(c.spec_log2, c.tile_log2 - 1);
     c.rev_spec_log2 = std::min(c.rev_spec_log2, c.tile_log2 - 1);
     for (int i = 0; i < QFT_MAX_PASSES; ++i) c.pass_bits[i] = cfg->pass_bits[i];
-    if (cfg->tiles_per_wg) c.tiles_per_wg = cfg->tiles_per_wg;
   }
   p.cfg = c;
   if (p.schedule == Schedule::Gates) {
@@ -531,7 +519,6 @@ void describe_plan(const HostPlan &p, qft_plan_info_t *o) {
       o->pass_bits[i] = d.m;
       o->pass_spec[i] = d.pbase;
       o->pass_reverse[i] = d.reverse;
-      o->pass_tiles_per_wg[i] = d.pipe_k > 1 ? d.pipe_k : 1;
     }
   } else {
     o->num_passes = (int)p.gates.size() + (p.gate_norm != 1.0 ? 1 : 0);

@@ -51,7 +51,6 @@ class QftError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("tile_log2", ctypes.c_int), ("radix_log2", ctypes.c_int),
                 ("spec_log2", ctypes.c_int), ("rev_spec_log2", ctypes.c_int),
-                ("tiles_per_wg", ctypes.c_int),
                 ("pass_bits", ctypes.c_int * QFT_MAX_PASSES)]
 
 
@@ -63,7 +62,6 @@ class PlanInfo(ctypes.Structure):
         ("pass_bits", ctypes.c_int * QFT_MAX_PASSES),
         ("pass_spec", ctypes.c_int * QFT_MAX_PASSES),
         ("pass_reverse", ctypes.c_int * QFT_MAX_PASSES),
-        ("pass_tiles_per_wg", ctypes.c_int * QFT_MAX_PASSES),
         ("config", Config),
         ("gates_h", ctypes.c_longlong), ("gates_cr", ctypes.c_longlong),
         ("gates_swap", ctypes.c_longlong),
@@ -312,9 +310,7 @@ def fill_random(x, dist="gaussian", seed: int = 0, stream_id: int = 0, stream=No
 # ---- autotuner ------------------------------------------------------------
 
 def _cfg_dict(c: Config) -> dict:
-    d = {f: getattr(c, f) for f, _ in Config._fields_ if f not in ("pass_bits", "tiles_per_wg")}
-    if c.tiles_per_wg > 1:
-        d["tiles_per_wg"] = c.tiles_per_wg
+    d = {f: getattr(c, f) for f, _ in Config._fields_ if f != "pass_bits"}
     pb = [int(x) for x in c.pass_bits if int(x) > 0]
     if pb:
         d["pass_bits"] = pb

@@ -105,11 +105,10 @@ CONFIGS = [
     dict(tile_log2=9, radix_log2=5, spec_log2=4, rev_spec_log2=4),
     dict(tile_log2=12, radix_log2=4, spec_log2=4, rev_spec_log2=4),
     dict(tile_log2=13, radix_log2=5, spec_log2=3, rev_spec_log2=3),
-    dict(tile_log2=13, radix_log2=5, spec_log2=3, rev_spec_log2=3, tiles_per_wg=4),
-    dict(tile_log2=12, radix_log2=4, spec_log2=2, rev_spec_log2=2, tiles_per_wg=2),
-    dict(tile_log2=11, radix_log2=3, spec_log2=2, rev_spec_log2=2, tiles_per_wg=8),
-    dict(tile_log2=12, radix_log2=4, spec_log2=2, rev_spec_log2=3, tiles_per_wg=4,
-         pass_bits=[7, 7, 6]),
+    dict(tile_log2=12, radix_log2=5, spec_log2=2, rev_spec_log2=2),
+    dict(tile_log2=11, radix_log2=3, spec_log2=2, rev_spec_log2=2),
+    dict(tile_log2=14, radix_log2=5, spec_log2=4, rev_spec_log2=4),
+    dict(tile_log2=12, radix_log2=4, spec_log2=2, rev_spec_log2=3, pass_bits=[7, 7, 6]),
 ]
 
 

@@ -158,7 +158,7 @@ CONFIGS = [
     dict(tile_log2=8, radix_log2=3, spec_log2=-1, rev_spec_log2=-1),
     dict(tile_log2=9, radix_log2=5, spec_log2=4, rev_spec_log2=4),
     dict(tile_log2=10, radix_log2=4, spec_log2=5, rev_spec_log2=3),
-    dict(tile_log2=10, radix_log2=4, spec_log2=3, rev_spec_log2=3, tiles_per_wg=4),
+    dict(tile_log2=11, radix_log2=5, spec_log2=2, rev_spec_log2=3),
 ]
 for cfg in CONFIGS:
     for n, k in ((11, None), (16, 4), (19, 2), (20, None)):
@@ -194,16 +194,18 @@ def test_invalid_pass_splits():
             Q.describe(20, config=dict(tile_log2=12, radix_log2=4, pass_bits=split))
 
 
-def test_pipelined_pass_descriptor():
-    cfg = dict(tile_log2=13, radix_log2=5, spec_log2=3, rev_spec_log2=3, tiles_per_wg=4)
+def test_tile_number_order():
+    # consecutive tile numbers differ in the non-tile bits nearest the bottom
+    # of the written address: ascending input bits in place, descending input
+    # bits in the bit-reversing pass
     layout = Q.layout_flags("c64")
-    for p in range(3):
-        d, L = E.get_pass(28, -1, "unitary", layout, cfg, p)
-        assert d.pipe_k == 4 and L[2] * 4 == d.ntiles
-    # no pipelined instance for complex128 at radix 32
-    cfg = dict(tile_log2=12, radix_log2=5, spec_log2=2, rev_spec_log2=2, tiles_per_wg=4)
-    d, L = E.get_pass(28, -1, "unitary", Q.layout_flags("c128"), cfg, 0)
-    assert d.pipe_k == 0
+    info = Q.describe(28)
+    for p in range(info.num_passes):
+        d, L = E.get_pass(28, -1, "unitary", layout, None, p)
+        free = [E.P(d.free_w)[b] for b in range(d.nfree)]
+        assert sorted(free) == (free[::-1] if d.reverse else free)
+        assert L[2] == d.ntiles == 1 << d.nfree
+    assert info.pass_reverse[info.num_passes - 1] == 1
 
 
 def test_emulated_three_pass_plan():
@@ -222,7 +224,7 @@ INV_CASES = [
     (17, None, "inv_n", "c128", "natural", dict(tile_log2=9, radix_log2=3, spec_log2=2,
                                                  rev_spec_log2=2)),
     (20, 6, "unitary", "c128", "natural", dict(tile_log2=10, radix_log2=4, spec_log2=3,
-                                                rev_spec_log2=3, tiles_per_wg=4)),
+                                                rev_spec_log2=3)),
 ]
 
 
