@@ -385,14 +385,15 @@ void plan_gates(HostPlan &p) {
 qft_config_t default_config(bool c128) {
   qft_config_t c;
   memset(&c, 0, sizeof(c));
+  // fastest measured at 2^27-2^28 elements (64 KiB tiles, radix 32)
   if (c128) {
     c.tile_log2 = 12;
-    c.radix_log2 = 3;
+    c.radix_log2 = 5;
     c.spec_log2 = 2;
     c.rev_spec_log2 = 2;
   } else {
     c.tile_log2 = 13;
-    c.radix_log2 = 4;
+    c.radix_log2 = 5;
     c.spec_log2 = 3;
     c.rev_spec_log2 = 3;
   }
