@@ -151,6 +151,20 @@ int qft_execute(qft_plan_t *plan, void *dev_ptr, qft_stream_t stream);
 int qft_execute_ws(qft_plan_t *plan, void *dev_ptr, void *workspace,
                    qft_stream_t stream);
 
+/* As qft_execute_ws (workspace NULL = the plan's own), and also write the
+ * input's L2 norm ||x||_2 as one double to norm_dev (device memory, 8-byte
+ * aligned) on the same stream.  This is the paper's scale_in (Sec. 3 step
+ * 1): the transform is linear, so encoding x / scale_in, evolving and
+ * decoding by scale_in gives the same output up to rounding, and the norm is
+ * returned as metadata.  The fused schedule sums |x|^2 in its first pass
+ * (no extra pass over the state); the gate schedule adds one reading sweep.
+ * The first call allocates a small plan-owned buffer of partial sums (8
+ * bytes per 64 threads of the first pass); calls of one plan must be
+ * ordered on one stream.  Errors as qft_execute_ws, and QFT_ERR_POINTER for
+ * a NULL or misaligned norm_dev.                                           */
+int qft_execute_norm(qft_plan_t *plan, void *dev_ptr, void *workspace,
+                     double *norm_dev, qft_stream_t stream);
+
 /* Free the plan and its device memory (NULL-safe).  The caller must ensure
  * no enqueued execute of the plan is still pending.                         */
 void qft_destroy(qft_plan_t *plan);

@@ -4,6 +4,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <string>
@@ -33,20 +34,32 @@ int hip_error(hipError_t e, const char *what) {
 void clear_error() { g_last_error.clear(); }
 
 // Enqueue the kernels of a plan.  `ws` may be NULL when the plan needs none.
-int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s) {
+int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm_out) {
   const HostPlan &hp = p->hp;
   hipError_t e = hipSuccess;
   size_t li = 0;
   auto mark = [&](size_t i) {
     if (p->timing) hipEventRecord(p->timer.slot(i), s);
   };
+  if (norm_out && hp.schedule == Schedule::Gates) {
+    e = launch_norm_sweep(dev, hp.n, hp.c128, p->d_norm, p->norm_parts, s);
+    if (e != hipSuccess) return hip_error(e, "norm sweep launch");
+  }
   if (p->timing) p->timer.begin(p->num_launches());
   if (hp.schedule == Schedule::Fused) {
-    for (const PassLaunch &L : p->launches) {
+    for (size_t i = 0; i < p->launches.size(); ++i) {
+      const PassLaunch &L = p->launches[i];
       mark(li);
       const void *in = L.in_ws ? ws : dev;
       void *out = L.out_ws ? ws : dev;
-      e = launch_fused_pass(L, hp.c128, in, out, s);
+      if (i == 0 && norm_out) {
+        // the first pass also sums |x|^2 of the tiles it loads
+        PassLaunch Ln = L;
+        Ln.d.norm_part = p->d_norm;
+        e = launch_fused_pass(Ln, hp.c128, in, out, s);
+      } else {
+        e = launch_fused_pass(L, hp.c128, in, out, s);
+      }
       if (e != hipSuccess) return hip_error(e, "fused pass launch");
       ++li;
     }
@@ -68,6 +81,10 @@ int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s) {
   }
   mark(li);
   if (p->timing) p->timer.end();
+  if (norm_out) {
+    e = launch_norm_finish(p->d_norm, p->norm_parts, norm_out, s);
+    if (e != hipSuccess) return hip_error(e, "norm launch");
+  }
   return QFT_OK;
 }
 
@@ -156,18 +173,10 @@ static qft_plan_t *make_plan(int n, int cutoff, int norm, int layout, const qft_
   return p;
 }
 
-extern "C" {
+namespace {
 
-qft_plan_t *qft_plan(int n, int cutoff, int norm, int layout) {
-  return make_plan(n, cutoff, norm, layout, nullptr);
-}
-
-qft_plan_t *qft_plan_config(int n, int cutoff, int norm, int layout, const qft_config_t *config) {
-  return make_plan(n, cutoff, norm, layout, config);
-}
-
-int qft_execute_ws(qft_plan_t *plan, void *dev_ptr, void *workspace, qft_stream_t stream) {
-  clear_error();
+// Argument checks shared by the execute entry points (no device work).
+int check_execute(qft_plan_s *plan, void *dev_ptr, void *workspace) {
   if (!plan) return set_error(QFT_ERR_INVALID, "plan is NULL");
   if (!dev_ptr) return set_error(QFT_ERR_POINTER, "data pointer is NULL");
   if ((uintptr_t)dev_ptr % plan->hp.elem_bytes)
@@ -182,7 +191,56 @@ int qft_execute_ws(qft_plan_t *plan, void *dev_ptr, void *workspace, qft_stream_
   if (e != hipSuccess) return hip_error(e, "hipGetDevice");
   if (dev != plan->device)
     return set_error(QFT_ERR_INVALID, "the current device is not the plan's device");
+  return QFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qft_plan_t *qft_plan(int n, int cutoff, int norm, int layout) {
+  return make_plan(n, cutoff, norm, layout, nullptr);
+}
+
+qft_plan_t *qft_plan_config(int n, int cutoff, int norm, int layout, const qft_config_t *config) {
+  return make_plan(n, cutoff, norm, layout, config);
+}
+
+int qft_execute_ws(qft_plan_t *plan, void *dev_ptr, void *workspace, qft_stream_t stream) {
+  clear_error();
+  int rc = check_execute(plan, dev_ptr, workspace);
+  if (rc != QFT_OK) return rc;
   return enqueue_plan(plan, dev_ptr, workspace, (hipStream_t)stream);
+}
+
+int qft_execute_norm(qft_plan_t *plan, void *dev_ptr, void *workspace, double *norm_dev,
+                     qft_stream_t stream) {
+  clear_error();
+  if (plan && !workspace) workspace = plan->d_ws;
+  int rc = check_execute(plan, dev_ptr, workspace);
+  if (rc != QFT_OK) return rc;
+  if (!norm_dev) return set_error(QFT_ERR_POINTER, "norm pointer is NULL");
+  if ((uintptr_t)norm_dev % sizeof(double))
+    return set_error(QFT_ERR_POINTER, "norm pointer is not aligned to 8 bytes");
+  if (!plan->d_norm) {
+    const HostPlan &hp = plan->hp;
+    uint32_t parts;
+    if (hp.schedule == Schedule::Fused) {
+      const PassLaunch &L = plan->launches[0];
+      parts = L.d.ntiles * (uint32_t)norm_parts_per_tile(L.threads);
+    } else {
+      const uint32_t N = 1u << hp.n;
+      parts = std::max(1u, std::min(1024u, N / 4096u));
+    }
+    hipError_t e = hipMalloc(&plan->d_norm, (size_t)parts * sizeof(double));
+    if (e != hipSuccess) {
+      plan->d_norm = nullptr;
+      (void)hipGetLastError();
+      return set_error(QFT_ERR_NOMEM, "cannot allocate the norm partial sums");
+    }
+    plan->norm_parts = parts;
+  }
+  return enqueue_plan(plan, dev_ptr, workspace, (hipStream_t)stream, norm_dev);
 }
 
 int qft_execute(qft_plan_t *plan, void *dev_ptr, qft_stream_t stream) {
@@ -199,6 +257,7 @@ void qft_destroy(qft_plan_t *plan) {
   plan->timer.release();
   if (plan->d_tables) hipFree(plan->d_tables);
   if (plan->d_ws) hipFree(plan->d_ws);
+  if (plan->d_norm) hipFree(plan->d_norm);
   delete plan;
 }
 

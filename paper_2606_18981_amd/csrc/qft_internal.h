@@ -84,7 +84,14 @@ struct PassDesc {
   const void *tw_int;         // w_{2^MI}^y, y < 2^(MI-1)
   const void *tw_lo;          // w_N^x, x < 2^L
   const void *tw_hi;          // w_N^(x 2^L), x < 2^(n-L)
+  double *norm_part;          // non-null: per-wave sums of |x|^2 of the
+                              // loaded tile at [tile * parts_per_tile + w]
 };
+
+// Partial sums of |x|^2 one workgroup of `threads` threads writes when a pass
+// reduces the norm of its input: one per wave of 64, or one per thread when
+// the workgroup is smaller than a wave.
+inline int norm_parts_per_tile(int threads) { return threads >= 64 ? threads / 64 : threads; }
 
 // Host-side description of one launch of the fused schedule.
 struct PassLaunch {

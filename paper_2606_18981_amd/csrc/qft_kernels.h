@@ -43,6 +43,12 @@ hipError_t launch_cphase(void *psi, int n, int c, int t, double re, double im, b
 hipError_t launch_swap(void *psi, int n, int a, int b, bool c128, hipStream_t s);
 hipError_t launch_scale(void *psi, int n, double f, bool c128, hipStream_t s);
 
+// Input norm: partial sums of |x|^2 over `nparts` contiguous blocks, and
+// out[0] = sqrt(sum of `count` partials) in FP64.
+hipError_t launch_norm_sweep(const void *psi, int n, bool c128, double *part, uint32_t nparts,
+                             hipStream_t s);
+hipError_t launch_norm_finish(const double *part, uint32_t count, double *out, hipStream_t s);
+
 // Philox-4x32-10 input generator.
 hipError_t launch_fill_random(void *psi, int n, bool c128, int dist, uint64_t seed,
                               uint64_t stream_id, hipStream_t s);

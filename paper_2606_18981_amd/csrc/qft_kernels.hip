@@ -282,6 +282,25 @@ __device__ __forceinline__ void store_tile(const PassDesc &d, cplx<Real> (&v)[1 
   for (int rho = 0; rho < R; ++rho) dst[soff[rho]] = v[rho];
 }
 
+// Sum of |x|^2 over the tile's loaded elements, one partial per wave (or per
+// thread when the workgroup is smaller than a wave), accumulated in FP64.
+// Every thread of the workgroup calls it (inactive ones hold zeros).
+template <typename Real, int RB>
+__device__ __forceinline__ void norm_partial(const cplx<Real> (&v)[1 << RB], double *part,
+                                             uint32_t tile, uint32_t tid) {
+  double a = 0.0;
+#pragma unroll
+  for (int rho = 0; rho < (1 << RB); ++rho) a += (double)(v[rho].x * v[rho].x + v[rho].y * v[rho].y);
+  const uint32_t threads = blockDim.x;
+  if (threads >= 64) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
+    if ((tid & 63u) == 0) part[(size_t)tile * (threads >> 6) + (tid >> 6)] = a;
+  } else {
+    part[(size_t)tile * threads + tid] = a;
+  }
+}
+
 // One tile of one pass.  Per register group: radix network on the group's
 // register bits, then the controlled phases whose controls are this thread's
 // lower pass bits (deferred to the end of the group), then an LDS exchange to
@@ -322,6 +341,7 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) v[rho] = C{(Real)0, (Real)0};
   }
+  if (d.norm_part) norm_partial<Real, RB>(v, d.norm_part, tile, tid);
 
   radix_network<Real, RB>(v, d.grp[0].nst);
   if (has0 && active) apply_factors<Real, RB>(v, gf0, C{(Real)1, (Real)0}, false);
@@ -581,6 +601,64 @@ hipError_t launch_scale(void *psi, int n, double f, bool c128, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_scale<float>, sweep_grid(work), dim3(256), 0, s, (cplx<float> *)psi,
                        work, (float)f);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// input norm ||x||_2 (the paper's scale_in, Sec. 3 step 1) as metadata
+// ---------------------------------------------------------------------------
+
+// Standalone partial sums of |x|^2 (used by the gate-by-gate schedule; the
+// fused schedule folds them into its first pass): workgroup b sums a
+// contiguous block in FP64 and writes part[b].
+template <typename Real>
+__global__ void __launch_bounds__(256) k_norm_sweep(const cplx<Real> *psi, uint32_t N,
+                                                    double *part) {
+  __shared__ double red[4];
+  const uint32_t per = (N + gridDim.x - 1) / gridDim.x;
+  const uint32_t lo = blockIdx.x * per;
+  const uint32_t hi = lo + per < N ? lo + per : N;
+  double a = 0.0;
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const double x = (double)psi[i].x, y = (double)psi[i].y;
+    a += x * x + y * y;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
+  if ((threadIdx.x & 63u) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out[0] = sqrt(sum of part[0..count)), summed in a fixed order.
+__global__ void __launch_bounds__(256) k_norm_finish(const double *part, uint32_t count,
+                                                     double *out) {
+  __shared__ double red[256];
+  double a = 0.0;
+  for (uint32_t i = threadIdx.x; i < count; i += 256) a += part[i];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(red[0]);
+}
+
+hipError_t launch_norm_sweep(const void *psi, int n, bool c128, double *part, uint32_t nparts,
+                             hipStream_t s) {
+  const uint32_t N = 1u << n;
+  if (c128)
+    hipLaunchKernelGGL(k_norm_sweep<double>, dim3(nparts), dim3(256), 0, s,
+                       (const cplx<double> *)psi, N, part);
+  else
+    hipLaunchKernelGGL(k_norm_sweep<float>, dim3(nparts), dim3(256), 0, s,
+                       (const cplx<float> *)psi, N, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_finish(const double *part, uint32_t count, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(256), 0, s, part, count, out);
   return hipGetLastError();
 }
 

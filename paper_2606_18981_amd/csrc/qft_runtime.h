@@ -34,6 +34,8 @@ struct qft_plan_s {
   int device = 0;
   void *d_tables = nullptr;
   void *d_ws = nullptr;
+  double *d_norm = nullptr;  // partial sums for qft_execute_norm (lazy)
+  uint32_t norm_parts = 0;
   std::vector<qft::PassLaunch> launches;  // table pointers resolved
   bool timing = false;
   qft::LaunchTimer timer;
@@ -44,7 +46,8 @@ struct qft_plan_s {
 };
 
 namespace qft {
-int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s);
+// norm_out: device double receiving ||x||_2 of the input, or nullptr
+int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm_out = nullptr);
 // drop cached batch launches that use this plan
 void batch_forget_plan(qft_plan_s *plan);
 // tuned configuration for a plan shape, if the tuning table has one

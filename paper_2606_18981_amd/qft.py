@@ -94,6 +94,7 @@ def _load():
         "qft_plan_config": (P, [I, I, I, I, ctypes.POINTER(Config)]),
         "qft_execute": (I, [P, P, P]),
         "qft_execute_ws": (I, [P, P, P, P]),
+        "qft_execute_norm": (I, [P, P, P, P, P]),
         "qft_destroy": (None, [P]),
         "qft_last_error": (ctypes.c_char_p, []),
         "qft_plan_info": (I, [P, ctypes.POINTER(PlanInfo)]),
@@ -231,16 +232,26 @@ class Plan:
         if x.numel() != (1 << self.n):
             raise ValueError(f"tensor has {x.numel()} elements, plan needs {1 << self.n}")
 
-    def execute(self, x, stream=None, workspace=None):
-        """In-place transform of the CUDA tensor x (complex64/128, 2^n elements)."""
+    def execute(self, x, stream=None, workspace=None, norm_out=None):
+        """In-place transform of the CUDA tensor x (complex64/128, 2^n elements).
+        With norm_out (a float64 CUDA tensor), ||x||_2 of the input is written
+        to norm_out[0] by the same call (the paper's scale_in)."""
         self._check_tensor(x)
-        if workspace is None:
+        if workspace is not None and \
+                workspace.numel() * workspace.element_size() < self.info.workspace_bytes:
+            raise ValueError("workspace too small")
+        ws = None if workspace is None else ctypes.c_void_p(workspace.data_ptr())
+        if norm_out is not None:
+            import torch
+            if not (norm_out.is_cuda and norm_out.dtype == torch.float64 and norm_out.numel() >= 1):
+                raise ValueError("norm_out must be a float64 CUDA tensor")
+            rc = lib.qft_execute_norm(self._h, ctypes.c_void_p(x.data_ptr()), ws,
+                                      ctypes.c_void_p(norm_out.data_ptr()), _stream_handle(stream))
+        elif ws is None:
             rc = lib.qft_execute(self._h, ctypes.c_void_p(x.data_ptr()), _stream_handle(stream))
         else:
-            if workspace.numel() * workspace.element_size() < self.info.workspace_bytes:
-                raise ValueError("workspace too small")
-            rc = lib.qft_execute_ws(self._h, ctypes.c_void_p(x.data_ptr()),
-                                    ctypes.c_void_p(workspace.data_ptr()), _stream_handle(stream))
+            rc = lib.qft_execute_ws(self._h, ctypes.c_void_p(x.data_ptr()), ws,
+                                    _stream_handle(stream))
         _check(rc)
         return x
 

@@ -41,6 +41,7 @@ class PassDesc(ctypes.Structure):
         ("grp", GroupMap * MAX_GROUPS),
         ("scale", ctypes.c_double),
         ("tw_int", ctypes.c_void_p), ("tw_lo", ctypes.c_void_p), ("tw_hi", ctypes.c_void_p),
+        ("norm_part", ctypes.c_void_p),
     ]
 
 

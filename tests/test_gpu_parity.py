@@ -216,6 +216,34 @@ def test_n28_inverse_sampled_bins(torch_cuda, Q):
     assert O.rel_l2(y[bins], O.dft_bins(x, bins, inverse=True)) <= TOL["c64"]
 
 
+# ---- input norm as metadata (the paper's scale_in) -------------------------
+
+@pytest.mark.parametrize("n,dtype,schedule", [(1, "c64", "fused"), (5, "c128", "fused"),
+                                              (10, "c64", "gates"), (12, "c128", "gates"),
+                                              (13, "c64", "fused"), (20, "c128", "fused"),
+                                              (24, "c64", "fused")])
+def test_execute_norm(torch_cuda, Q, n, dtype, schedule):
+    torch = torch_cuda
+    import ctypes
+    print(f"[gpu] norm n={n} dtype={dtype} schedule={schedule}", flush=True)
+    x = (I.gaussian(n, 6300 + n) * 3.7).astype(NPDT[dtype])
+    plan = Q.Plan(n, -1, "unitary", dtype, "natural", schedule)
+    a = torch.from_numpy(x).cuda()
+    b = a.clone()
+    norm = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+    plan.execute(a)
+    plan.execute(b, norm_out=norm)
+    plan.execute(b.clone(), norm_out=norm)  # a second call reuses the partial sums
+    torch.cuda.synchronize()
+    assert torch.equal(a, b), "the norm must not change the transform"
+    ref = float(np.linalg.norm(x.astype(np.complex128)))
+    got = float(norm.cpu()[0])
+    assert abs(got - ref) <= (1e-13 if dtype == "c128" else 1e-6) * ref
+    rc = Q.lib.qft_execute_norm(plan.handle, ctypes.c_void_p(b.data_ptr()), None, None, None)
+    assert rc == Q.QFT_ERR_POINTER
+    plan.close()
+
+
 # ---- device input generator ------------------------------------------------
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
