@@ -81,7 +81,20 @@ class PlanInfo(ctypes.Structure):
         return d
 
 
+def _init_torch_device():
+    """Let torch bring up the HIP runtime first.  The library links the same
+    libamdhip64 soname, so it shares torch's runtime, device view and
+    streams."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def _load():
+    _init_torch_device()
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -m paper_2606_18981_amd.build` "

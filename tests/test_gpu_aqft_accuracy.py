@@ -19,6 +19,7 @@ pytestmark = pytest.mark.gpu
 
 def test_n28_aqft_error_vs_cutoff():
     import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
     from paper_2606_18981_amd import qft as Q
 
     n = 28
