@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
-def cpu_baseline(n_sample: int = 24):
+def cpu_baseline(n_sample: int = 26):
     """Time the FP64 oracle (per-target fused numpy form) on one transform."""
     import numpy as np
 

@@ -60,11 +60,15 @@ def _db(path):
 
 
 def kernel_stats(path):
+    """Per-kernel dispatch count and duration statistics (ns), from the
+    per-dispatch `kernels` view, ordered by total time."""
     cur = _db(path).cursor()
-    rows = cur.execute("select name, total_calls, total_duration, average, min, max "
-                       "from top_kernels").fetchall()
-    return [dict(name=r[0], calls=r[1], total_ns=r[2], avg_ns=r[3], min_ns=r[4], max_ns=r[5])
-            for r in rows]
+    rows = cur.execute("select name, count(*), sum(duration), avg(duration), min(duration), "
+                       "max(duration), max(vgpr_count), max(accum_vgpr_count), "
+                       "max(scratch_size), max(lds_size) from kernels group by name "
+                       "order by sum(duration) desc").fetchall()
+    return [dict(name=r[0], calls=r[1], total_ns=r[2], avg_ns=r[3], min_ns=r[4], max_ns=r[5],
+                 vgpr=r[6], agpr=r[7], scratch=r[8], lds=r[9]) for r in rows]
 
 
 def counter_means(path, counter):
@@ -133,11 +137,12 @@ def summarize(a):
         out.append(f"* {label}: `{c}`")
     out.append("")
     out.append("## Kernel trace (`--kernel-trace --stats`)\n")
-    out.append("| kernel | calls | avg µs | min µs | max µs |")
-    out.append("|---|---|---|---|---|")
+    out.append("| kernel | calls | avg µs | min µs | max µs | VGPR | AGPR | scratch B | LDS B |")
+    out.append("|---|---|---|---|---|---|---|---|---|")
     for t in trace:
         out.append(f"| `{t['name'][:90]}` | {t['calls']} | {t['avg_ns'] / 1e3:.1f} | "
-                   f"{t['min_ns'] / 1e3:.1f} | {t['max_ns'] / 1e3:.1f} |")
+                   f"{t['min_ns'] / 1e3:.1f} | {t['max_ns'] / 1e3:.1f} | {t['vgpr']} | "
+                   f"{t['agpr']} | {t['scratch']} | {t['lds']} |")
     out.append("")
     out.append("## HBM counters (KiB per dispatch, mean over dispatches)\n")
     out.append("| kernel | grid | FETCH_SIZE | WRITE_SIZE | dispatches |")

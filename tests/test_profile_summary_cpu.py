@@ -17,12 +17,12 @@ GIB = 1 << 30
 
 def _trace_db(path):
     db = sqlite3.connect(path)
-    db.execute("create table top_kernels (name, total_calls, total_duration, average, "
-               "percentage, min, max)")
-    db.execute("insert into top_kernels values (?,?,?,?,?,?,?)",
-               (PASS, 6, 6.6e6, 1.1e6, 70.0, 1.0e6, 1.2e6))
-    db.execute("insert into top_kernels values (?,?,?,?,?,?,?)",
-               (COPY, 4, 3.6e6, 0.9e6, 30.0, 0.88e6, 0.92e6))
+    db.execute("create table kernels (name, duration, vgpr_count, accum_vgpr_count, "
+               "scratch_size, lds_size)")
+    for d in (1.0e6, 1.1e6, 1.2e6, 1.0e6, 1.1e6, 1.2e6):
+        db.execute("insert into kernels values (?,?,?,?,?,?)", (PASS, d, 224, 0, 0, 65536))
+    for d in (0.88e6, 0.9e6, 0.92e6, 0.9e6):
+        db.execute("insert into kernels values (?,?,?,?,?,?)", (COPY, d, 16, 0, 0, 0))
     db.commit()
 
 
@@ -54,6 +54,7 @@ def test_summary_scales_counters_by_the_copy_and_round_trips(tmp_path):
                            bench_json=str(bench), title="x")
     md = PS.summarize(a)
     assert "factor 2.0000" in md and "factor 1.0000" in md
+    assert "| 6 | 1100.0 | 1000.0 | 1200.0 | 224 |" in md
     path = tmp_path / "s.md"
     path.write_text(md)
     traffic = PS.load_traffic(str(path), config)
