@@ -17,6 +17,8 @@
 //   generator with FP64 Box-Muller.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "qft_internal.h"
 #include "qft_kernels.h"
 
@@ -270,6 +272,33 @@ __device__ __forceinline__ void conj_regs(cplx<Real> (&v)[1 << RB]) {
   for (int rho = 0; rho < (1 << RB); ++rho) v[rho].y = -v[rho].y;
 }
 
+// Branch-free conjugation: flip the sign bit of every imaginary part when
+// `on` (no data-dependent control flow, so no register merges).
+template <int RB>
+__device__ __forceinline__ void conj_if(cplx<float> (&v)[1 << RB], bool on) {
+  const uint32_t m = on ? 0x80000000u : 0u;
+#pragma unroll
+  for (int rho = 0; rho < (1 << RB); ++rho) v[rho].y = __uint_as_float(__float_as_uint(v[rho].y) ^ m);
+}
+template <int RB>
+__device__ __forceinline__ void conj_if(cplx<double> (&v)[1 << RB], bool on) {
+  const uint64_t m = on ? 0x8000000000000000ull : 0ull;
+#pragma unroll
+  for (int rho = 0; rho < (1 << RB); ++rho)
+    v[rho].y = __longlong_as_double((long long)((uint64_t)__double_as_longlong(v[rho].y) ^ m));
+}
+
+template <typename Real, int RB>
+__device__ __forceinline__ void store_tile_raw(const PassDesc &d, const cplx<Real> (&v)[1 << RB],
+                                               cplx<Real> *dst) {
+  constexpr int R = 1 << RB;
+  uint32_t soff[R];
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho) soff[rho] = deposit_reg<RB>(rho, d.st_reg_w);
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho) dst[soff[rho]] = v[rho];
+}
+
 template <typename Real, int RB>
 __device__ __forceinline__ void store_tile(const PassDesc &d, cplx<Real> (&v)[1 << RB],
                                            cplx<Real> *dst) {
@@ -392,16 +421,104 @@ k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
                       true);
 }
 
+// The common pass shape with its structure fixed at compile time: two
+// register groups, the first full (RB stages, per-thread factors of the
+// lower pass bits), the last with NSTL stages (it holds pass bit 0, so it
+// has no such factors), and (EXT) the diagonal of the controls below the
+// pass.  With nothing left to decide at run time that changes the data
+// registers, no path merges are needed: the generic kernel spends about a
+// third of its vector instructions on register moves that reconcile its
+// run-time branches.
+template <typename Real, int RB, int NSTL, bool EXT>
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? (RB >= 5 ? 256 : RB >= 3 ? 512 : 1024)
+                                                   : (RB >= 5 ? 512 : 1024))
+k_fused_pass2(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
+  using C = cplx<Real>;
+  constexpr int R = 1 << RB;
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  C *lds = reinterpret_cast<C *>(qft_smem);
+  const uint32_t tid = threadIdx.x;
+  uint32_t tile = blockIdx.x;
+  if (d.xcd_remap) {
+    const uint32_t per = gridDim.x >> 3;
+    tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  }
+  const int TR = d.T - RB;
+  const uint32_t base = tile_base(d, tile);
+  const uint32_t st_thr = deposit_tid(tid, d.st_thr_w, TR);
+
+  // every table read first: they are in flight together with the tile's
+  C gf[RB];
+  group_factors<Real, RB>(d, d.grp[0], deposit_tid(tid, d.grp[0].thr_w, TR), gf);
+  ExtRaw<Real, RB> raw;
+  if (EXT) ext_loads<Real, RB>(d, base | st_thr, raw);
+
+  C v[R];
+  {
+    const C *src = in + (base | deposit_tid(tid, d.ld_thr_w, TR));
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) v[rho] = src[deposit_reg<RB>(rho, d.ld_reg_w)];
+  }
+  conj_if<RB>(v, d.conj_in != 0);
+  if (d.norm_part) norm_partial<Real, RB>(v, d.norm_part, tile, tid);
+
+  radix_network<Real, RB>(v, RB);
+  apply_factors<Real, RB>(v, gf, C{(Real)1, (Real)0}, false);
+  exchange<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR, true);
+  radix_network<Real, RB>(v, NSTL);
+
+  if (EXT) {
+    C f[RB], f0;
+    ext_finish<Real, RB>(d, raw, f, f0);
+    apply_factors<Real, RB>(v, f, f0, true);
+  } else {
+    const Real scale = (Real)d.scale;
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) {
+      v[rho].x *= scale;
+      v[rho].y *= scale;
+    }
+  }
+  conj_if<RB>(v, d.conj_out != 0);
+  const uint32_t obase = d.reverse ? rev_bits(base, d.n) : base;
+  store_tile_raw<Real, RB>(d, v, out + (obase | st_thr));
+}
+
+// True when a launch has the shape k_fused_pass2 is written for.
+inline bool pass2_shape(const PassLaunch &L) {
+  const PassDesc &d = L.d;
+  return d.r == 5 && d.ngroups == 2 && d.grp[0].nst == d.r && d.grp[0].jbase > 0 &&
+         d.grp[1].jbase == 0 && d.grp[1].nst >= 1 && d.grp[1].nst <= d.r &&
+         L.threads == (1 << (d.T - d.r));
+}
+
 template <typename Real, int RB>
 static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, hipStream_t s) {
   auto fn = k_fused_pass<Real, RB>;
+  int inst = 0;  // which kernel instance: bit in `raised` below
+  if constexpr (RB == 5) {
+    if (pass2_shape(L)) {
+      using K = void (*)(const PassDesc, const cplx<Real> *, cplx<Real> *);
+      static const K tab[2][5] = {
+          {k_fused_pass2<Real, 5, 1, false>, k_fused_pass2<Real, 5, 2, false>,
+           k_fused_pass2<Real, 5, 3, false>, k_fused_pass2<Real, 5, 4, false>,
+           k_fused_pass2<Real, 5, 5, false>},
+          {k_fused_pass2<Real, 5, 1, true>, k_fused_pass2<Real, 5, 2, true>,
+           k_fused_pass2<Real, 5, 3, true>, k_fused_pass2<Real, 5, 4, true>,
+           k_fused_pass2<Real, 5, 5, true>}};
+      fn = tab[L.d.ext_tw ? 1 : 0][L.d.grp[1].nst - 1];
+      inst = 1 + (L.d.ext_tw ? 5 : 0) + (L.d.grp[1].nst - 1);
+    }
+  }
   if (L.lds_bytes > 65536) {
-    static int set = 0;
-    if (!set) {
+    // raise the LDS limit once per kernel instance
+    static std::atomic<uint32_t> raised{0};
+    const uint32_t bit = 1u << inst;
+    if (!(raised.load(std::memory_order_acquire) & bit)) {
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
       if (e != hipSuccess) return e;
-      set = 1;
+      raised.fetch_or(bit, std::memory_order_release);
     }
   }
   hipLaunchKernelGGL(fn, dim3(L.grid), dim3(L.threads), L.lds_bytes, s, L.d,
