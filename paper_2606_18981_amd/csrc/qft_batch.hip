@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <vector>
 
@@ -67,24 +68,26 @@ int build_entry(BatchEntry *e) {
   }
   // group the (job, pass) launches by pass level, radix and workgroup size
   struct GroupBuild {
-    int level, r, threads, lds;
+    int level, r, threads, lds, shape;
     std::vector<BatchSeg> segs;
     uint32_t items = 0;
   };
   std::vector<GroupBuild> gb;
   for (int level = 0; level < maxP; ++level) {
-    std::map<std::pair<int, int>, size_t> index;  // (r, threads) -> group
+    std::map<std::tuple<int, int, int>, size_t> index;  // (r, threads, shape) -> group
     for (int j = 0; j < njobs; ++j) {
       qft_plan_t *p = e->plans[j];
       if (level >= (int)p->launches.size()) continue;
       const PassLaunch &L = p->launches[level];
-      const auto key = std::make_pair((int)L.d.r, L.threads);
+      const int shape = fused_pass_shape(L);
+      const auto key = std::make_tuple((int)L.d.r, L.threads, shape);
       auto it = index.find(key);
       if (it == index.end()) {
         GroupBuild g;
         g.level = level;
         g.r = L.d.r;
         g.threads = L.threads;
+        g.shape = shape;
         g.lds = 0;
         gb.push_back(g);
         it = index.emplace(key, gb.size() - 1).first;
@@ -139,6 +142,7 @@ int build_entry(BatchEntry *e) {
     g.threads = gb[i].threads;
     g.lds_bytes = gb[i].lds;
     g.r = gb[i].r;
+    g.shape = gb[i].shape;
     e->groups.push_back(g);
   }
   return QFT_OK;

@@ -33,8 +33,14 @@ struct BatchGroup {
   int threads;
   int lds_bytes;
   int r;
+  int shape;  // fused_pass_shape of every pass in the group
 };
 hipError_t launch_batch_group(bool c128, const BatchGroup &g, hipStream_t s);
+
+// 0 for the generic pass kernel; 1 + 5 * ext + (nst - 1) for a pass with the
+// two-group shape of the compile-time specialised kernel (radix 32, the
+// first group full, the last group holding pass bit 0 with nst stages).
+int fused_pass_shape(const PassLaunch &L);
 
 // Gate-by-gate sweeps (unfused circuit, Fig. 1).
 hipError_t launch_h(void *psi, int n, int t, bool c128, hipStream_t s);

@@ -430,19 +430,10 @@ k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
 // third of its vector instructions on register moves that reconcile its
 // run-time branches.
 template <typename Real, int RB, int NSTL, bool EXT>
-__global__ void __launch_bounds__(sizeof(Real) == 8 ? (RB >= 5 ? 256 : RB >= 3 ? 512 : 1024)
-                                                   : (RB >= 5 ? 512 : 1024))
-k_fused_pass2(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
+__device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, const cplx<Real> *in,
+                                           cplx<Real> *out, cplx<Real> *lds, uint32_t tid) {
   using C = cplx<Real>;
   constexpr int R = 1 << RB;
-  extern __shared__ __align__(16) unsigned char qft_smem[];
-  C *lds = reinterpret_cast<C *>(qft_smem);
-  const uint32_t tid = threadIdx.x;
-  uint32_t tile = blockIdx.x;
-  if (d.xcd_remap) {
-    const uint32_t per = gridDim.x >> 3;
-    tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
-  }
   const int TR = d.T - RB;
   const uint32_t base = tile_base(d, tile);
   const uint32_t st_thr = deposit_tid(tid, d.st_thr_w, TR);
@@ -484,20 +475,34 @@ k_fused_pass2(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
   store_tile_raw<Real, RB>(d, v, out + (obase | st_thr));
 }
 
-// True when a launch has the shape k_fused_pass2 is written for.
-inline bool pass2_shape(const PassLaunch &L) {
+template <typename Real, int RB, int NSTL, bool EXT>
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? (RB >= 5 ? 256 : RB >= 3 ? 512 : 1024)
+                                                   : (RB >= 5 ? 512 : 1024))
+k_fused_pass2(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  uint32_t tile = blockIdx.x;
+  if (d.xcd_remap) {
+    const uint32_t per = gridDim.x >> 3;
+    tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  }
+  pass2_tile<Real, RB, NSTL, EXT>(d, tile, in, out, reinterpret_cast<cplx<Real> *>(qft_smem),
+                                  threadIdx.x);
+}
+
+int fused_pass_shape(const PassLaunch &L) {
   const PassDesc &d = L.d;
-  return d.r == 5 && d.ngroups == 2 && d.grp[0].nst == d.r && d.grp[0].jbase > 0 &&
-         d.grp[1].jbase == 0 && d.grp[1].nst >= 1 && d.grp[1].nst <= d.r &&
-         L.threads == (1 << (d.T - d.r));
+  const bool two = d.r == 5 && d.ngroups == 2 && d.grp[0].nst == d.r && d.grp[0].jbase > 0 &&
+                   d.grp[1].jbase == 0 && d.grp[1].nst >= 1 && d.grp[1].nst <= d.r &&
+                   L.threads == (1 << (d.T - d.r));
+  return two ? 1 + (d.ext_tw ? 5 : 0) + (d.grp[1].nst - 1) : 0;
 }
 
 template <typename Real, int RB>
 static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, hipStream_t s) {
   auto fn = k_fused_pass<Real, RB>;
-  int inst = 0;  // which kernel instance: bit in `raised` below
+  const int inst = fused_pass_shape(L);  // which kernel instance: bit in `raised` below
   if constexpr (RB == 5) {
-    if (pass2_shape(L)) {
+    if (inst) {
       using K = void (*)(const PassDesc, const cplx<Real> *, cplx<Real> *);
       static const K tab[2][5] = {
           {k_fused_pass2<Real, 5, 1, false>, k_fused_pass2<Real, 5, 2, false>,
@@ -507,7 +512,6 @@ static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, 
            k_fused_pass2<Real, 5, 3, true>, k_fused_pass2<Real, 5, 4, true>,
            k_fused_pass2<Real, 5, 5, true>}};
       fn = tab[L.d.ext_tw ? 1 : 0][L.d.grp[1].nst - 1];
-      inst = 1 + (L.d.ext_tw ? 5 : 0) + (L.d.grp[1].nst - 1);
     }
   }
   if (L.lds_bytes > 65536) {
@@ -578,16 +582,52 @@ k_batch_group(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__res
                       true);
 }
 
+// The same for groups whose passes all have the two-group shape (see
+// k_fused_pass2), so that a transform gives bit-identical results alone and
+// in a batch.
+template <typename Real, int NSTL, bool EXT>
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? 256 : 512)
+k_batch_group2(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__restrict__ descs,
+               const BatchIO *__restrict__ io) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  const uint32_t item = blockIdx.x;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].first <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchSeg sg = segs[lo];
+  const BatchIO b = io[sg.desc];
+  pass2_tile<Real, 5, NSTL, EXT>(descs[sg.desc], item - sg.first, (const cplx<Real> *)b.in,
+                                 (cplx<Real> *)b.out, reinterpret_cast<cplx<Real> *>(qft_smem),
+                                 threadIdx.x);
+}
+
 template <typename Real, int RB>
 static hipError_t launch_group_t(const BatchGroup &g, hipStream_t s) {
   auto fn = k_batch_group<Real, RB>;
+  if constexpr (RB == 5) {
+    if (g.shape) {
+      using K = void (*)(const BatchSeg *, int, const PassDesc *, const BatchIO *);
+      static const K tab[10] = {
+          k_batch_group2<Real, 1, false>, k_batch_group2<Real, 2, false>,
+          k_batch_group2<Real, 3, false>, k_batch_group2<Real, 4, false>,
+          k_batch_group2<Real, 5, false>, k_batch_group2<Real, 1, true>,
+          k_batch_group2<Real, 2, true>,  k_batch_group2<Real, 3, true>,
+          k_batch_group2<Real, 4, true>,  k_batch_group2<Real, 5, true>};
+      fn = tab[g.shape - 1];
+    }
+  }
   if (g.lds_bytes > 65536) {
-    static int set = 0;
-    if (!set) {
+    // raise the LDS limit once per kernel instance
+    static std::atomic<uint32_t> raised{0};
+    const uint32_t bit = 1u << g.shape;
+    if (!(raised.load(std::memory_order_acquire) & bit)) {
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
       if (e != hipSuccess) return e;
-      set = 1;
+      raised.fetch_or(bit, std::memory_order_release);
     }
   }
   hipLaunchKernelGGL(fn, dim3(g.items), dim3(g.threads), g.lds_bytes, s, g.segs, g.nseg, g.descs,
