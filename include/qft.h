@@ -94,6 +94,12 @@ typedef void *qft_stream_t; /* hipStream_t */
  *              high-order passes (coalescing width 2^spec_log2)
  * rev_spec_log2: contiguous output elements per run in the final
  *              bit-reversing pass (natural order only)
+ * nontemporal: streaming (non-temporal) loads and stores, which do not
+ *              keep the data in the caches: 0 = planner's choice (on passes
+ *              whose tiles read whole 128-byte lines, when the state is
+ *              larger than 256 MiB and so cannot stay in the 256 MB
+ *              Infinity Cache between passes), 1 = never, 2 = on every pass
+ *              whose tiles read whole 128-byte lines
  * pass_bits:   qubits of each HBM pass, most significant pass first,
  *              summing to n (all zero = planner's choice: the fewest passes,
  *              middle passes as wide as the tile allows, the rest split
@@ -104,6 +110,7 @@ typedef struct qft_config {
   int radix_log2;
   int spec_log2;
   int rev_spec_log2;
+  int nontemporal;
   int pass_bits[QFT_MAX_PASSES];
 } qft_config_t;
 

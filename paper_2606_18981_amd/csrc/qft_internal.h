@@ -70,6 +70,7 @@ struct PassDesc {
   int32_t xcd_remap;// 1: XCD-aware tile order
   int32_t conj_in;  // 1: conjugate the loaded elements (first pass, inverse)
   int32_t conj_out; // 1: conjugate the stored elements (last pass, inverse)
+  int32_t nt;       // 1: non-temporal (streaming) loads and stores
   uint32_t ntiles;
   uint32_t gpos_w[4];   // global index bit of e-position q (packed)
   uint32_t free_w[8];   // global positions of the non-tile bits, ascending

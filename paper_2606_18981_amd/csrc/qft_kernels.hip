@@ -272,6 +272,28 @@ __device__ __forceinline__ void conj_regs(cplx<Real> (&v)[1 << RB]) {
   for (int rho = 0; rho < (1 << RB); ++rho) v[rho].y = -v[rho].y;
 }
 
+// One element load / store; NT selects the non-temporal (streaming) form.
+template <bool NT, typename Real>
+__device__ __forceinline__ cplx<Real> ld_elem(const cplx<Real> *p) {
+  if constexpr (NT) {
+    typedef Real V2 __attribute__((ext_vector_type(2)));
+    const V2 t = __builtin_nontemporal_load(reinterpret_cast<const V2 *>(p));
+    return cplx<Real>{t.x, t.y};
+  } else {
+    return *p;
+  }
+}
+template <bool NT, typename Real>
+__device__ __forceinline__ void st_elem(cplx<Real> *p, cplx<Real> v) {
+  if constexpr (NT) {
+    typedef Real V2 __attribute__((ext_vector_type(2)));
+    const V2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<V2 *>(p));
+  } else {
+    *p = v;
+  }
+}
+
 // Branch-free conjugation: flip the sign bit of every imaginary part when
 // `on` (no data-dependent control flow, so no register merges).
 template <int RB>
@@ -288,7 +310,7 @@ __device__ __forceinline__ void conj_if(cplx<double> (&v)[1 << RB], bool on) {
     v[rho].y = __longlong_as_double((long long)((uint64_t)__double_as_longlong(v[rho].y) ^ m));
 }
 
-template <typename Real, int RB>
+template <typename Real, int RB, bool NT>
 __device__ __forceinline__ void store_tile_raw(const PassDesc &d, const cplx<Real> (&v)[1 << RB],
                                                cplx<Real> *dst) {
   constexpr int R = 1 << RB;
@@ -296,7 +318,7 @@ __device__ __forceinline__ void store_tile_raw(const PassDesc &d, const cplx<Rea
 #pragma unroll
   for (int rho = 0; rho < R; ++rho) soff[rho] = deposit_reg<RB>(rho, d.st_reg_w);
 #pragma unroll
-  for (int rho = 0; rho < R; ++rho) dst[soff[rho]] = v[rho];
+  for (int rho = 0; rho < R; ++rho) st_elem<NT>(dst + soff[rho], v[rho]);
 }
 
 template <typename Real, int RB>
@@ -429,7 +451,7 @@ k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
 // registers, no path merges are needed: the generic kernel spends about a
 // third of its vector instructions on register moves that reconcile its
 // run-time branches.
-template <typename Real, int RB, int NSTL, bool EXT>
+template <typename Real, int RB, int NSTL, bool EXT, bool NT>
 __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, const cplx<Real> *in,
                                            cplx<Real> *out, cplx<Real> *lds, uint32_t tid) {
   using C = cplx<Real>;
@@ -448,7 +470,7 @@ __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, con
   {
     const C *src = in + (base | deposit_tid(tid, d.ld_thr_w, TR));
 #pragma unroll
-    for (int rho = 0; rho < R; ++rho) v[rho] = src[deposit_reg<RB>(rho, d.ld_reg_w)];
+    for (int rho = 0; rho < R; ++rho) v[rho] = ld_elem<NT>(src + deposit_reg<RB>(rho, d.ld_reg_w));
   }
   conj_if<RB>(v, d.conj_in != 0);
   if (d.norm_part) norm_partial<Real, RB>(v, d.norm_part, tile, tid);
@@ -472,10 +494,10 @@ __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, con
   }
   conj_if<RB>(v, d.conj_out != 0);
   const uint32_t obase = d.reverse ? rev_bits(base, d.n) : base;
-  store_tile_raw<Real, RB>(d, v, out + (obase | st_thr));
+  store_tile_raw<Real, RB, NT>(d, v, out + (obase | st_thr));
 }
 
-template <typename Real, int RB, int NSTL, bool EXT>
+template <typename Real, int RB, int NSTL, bool EXT, bool NT>
 __global__ void __launch_bounds__(sizeof(Real) == 8 ? (RB >= 5 ? 256 : RB >= 3 ? 512 : 1024)
                                                    : (RB >= 5 ? 512 : 1024))
 k_fused_pass2(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
@@ -485,8 +507,8 @@ k_fused_pass2(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
     const uint32_t per = gridDim.x >> 3;
     tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
   }
-  pass2_tile<Real, RB, NSTL, EXT>(d, tile, in, out, reinterpret_cast<cplx<Real> *>(qft_smem),
-                                  threadIdx.x);
+  pass2_tile<Real, RB, NSTL, EXT, NT>(d, tile, in, out,
+                                      reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x);
 }
 
 int fused_pass_shape(const PassLaunch &L) {
@@ -500,18 +522,19 @@ int fused_pass_shape(const PassLaunch &L) {
 template <typename Real, int RB>
 static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, hipStream_t s) {
   auto fn = k_fused_pass<Real, RB>;
-  const int inst = fused_pass_shape(L);  // which kernel instance: bit in `raised` below
+  // which kernel instance: bit in `raised` below
+  const int inst = fused_pass_shape(L) + (fused_pass_shape(L) && L.d.nt ? 10 : 0);
   if constexpr (RB == 5) {
     if (inst) {
       using K = void (*)(const PassDesc, const cplx<Real> *, cplx<Real> *);
-      static const K tab[2][5] = {
-          {k_fused_pass2<Real, 5, 1, false>, k_fused_pass2<Real, 5, 2, false>,
-           k_fused_pass2<Real, 5, 3, false>, k_fused_pass2<Real, 5, 4, false>,
-           k_fused_pass2<Real, 5, 5, false>},
-          {k_fused_pass2<Real, 5, 1, true>, k_fused_pass2<Real, 5, 2, true>,
-           k_fused_pass2<Real, 5, 3, true>, k_fused_pass2<Real, 5, 4, true>,
-           k_fused_pass2<Real, 5, 5, true>}};
-      fn = tab[L.d.ext_tw ? 1 : 0][L.d.grp[1].nst - 1];
+#define QFT_P2(E, N)                                                                         \
+  {k_fused_pass2<Real, 5, 1, E, N>, k_fused_pass2<Real, 5, 2, E, N>,                        \
+   k_fused_pass2<Real, 5, 3, E, N>, k_fused_pass2<Real, 5, 4, E, N>,                        \
+   k_fused_pass2<Real, 5, 5, E, N>}
+      static const K tab[2][2][5] = {{QFT_P2(false, false), QFT_P2(true, false)},
+                                     {QFT_P2(false, true), QFT_P2(true, true)}};
+#undef QFT_P2
+      fn = tab[L.d.nt ? 1 : 0][L.d.ext_tw ? 1 : 0][L.d.grp[1].nst - 1];
     }
   }
   if (L.lds_bytes > 65536) {
@@ -599,7 +622,7 @@ k_batch_group2(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__re
   }
   const BatchSeg sg = segs[lo];
   const BatchIO b = io[sg.desc];
-  pass2_tile<Real, 5, NSTL, EXT>(descs[sg.desc], item - sg.first, (const cplx<Real> *)b.in,
+  pass2_tile<Real, 5, NSTL, EXT, false>(descs[sg.desc], item - sg.first, (const cplx<Real> *)b.in,
                                  (cplx<Real> *)b.out, reinterpret_cast<cplx<Real> *>(qft_smem),
                                  threadIdx.x);
 }

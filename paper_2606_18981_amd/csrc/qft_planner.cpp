@@ -350,6 +350,17 @@ int plan_fused(HostPlan &p, std::string &err) {
     L.threads = 1 << (Te - r);
     L.lds_bytes = d.ngroups > 1 ? (int)(((size_t)1 << Te) * es) : 0;
     L.grid = d.ntiles;
+    // Streaming loads and stores pay off where a tile reads whole 128-byte
+    // lines: where it reads half lines, the neighbouring tile (run at the
+    // same time on the same XCD) reads the other half from L2.  They are
+    // used only when the state cannot stay in the 256 MB Infinity Cache.
+    {
+      int run = 0;  // low index bits held by the tile: contiguous run 2^run
+      while (run < n && in_tile[run]) ++run;
+      const bool lines = (es << run) >= 128;
+      const bool big = p.state_bytes > ((size_t)256 << 20);
+      d.nt = (c.nontemporal == 2 && lines) || (c.nontemporal == 0 && lines && big) ? 1 : 0;
+    }
     d.xcd_remap = (L.grid >= 8 && L.grid % 8 == 0) ? 1 : 0;
     if (natural_multi) {
       L.in_ws = i == 0 ? 0 : 1;
@@ -486,6 +497,7 @@ int build_host_plan(int n, int cutoff, int norm, int layout, const qft_config_t 
     if (cfg->radix_log2) c.radix_log2 = cfg->radix_log2;
     if (cfg->spec_log2) c.spec_log2 = cfg->spec_log2 < 0 ? 0 : cfg->spec_log2;
     if (cfg->rev_spec_log2) c.rev_spec_log2 = cfg->rev_spec_log2 < 0 ? 0 : cfg->rev_spec_log2;
+    c.nontemporal = cfg->nontemporal;
     c.spec_log2 = std::min(c.spec_log2, c.tile_log2 - 1);
     c.rev_spec_log2 = std::min(c.rev_spec_log2, c.tile_log2 - 1);
     for (int i = 0; i < QFT_MAX_PASSES; ++i) c.pass_bits[i] = cfg->pass_bits[i];

@@ -301,11 +301,11 @@ int qft_tune_save(const char *path) {
       split += (i ? "," : "") + std::to_string(e.cfg.pass_bits[i]);
     fprintf(f,
             "{\"arch\":\"%s\",\"n\":%d,\"cutoff\":%d,\"layout\":%d,\"tile_log2\":%d,"
-            "\"radix_log2\":%d,\"spec_log2\":%d,\"rev_spec_log2\":%d,\"pass_bits\":\"%s\","
-            "\"ms\":%.6g}\n",
+            "\"radix_log2\":%d,\"spec_log2\":%d,\"rev_spec_log2\":%d,\"nontemporal\":%d,"
+            "\"pass_bits\":\"%s\",\"ms\":%.6g}\n",
             arch.c_str(), std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-            e.cfg.tile_log2, e.cfg.radix_log2, e.cfg.spec_log2, e.cfg.rev_spec_log2, split.c_str(),
-            e.ms);
+            e.cfg.tile_log2, e.cfg.radix_log2, e.cfg.spec_log2, e.cfg.rev_spec_log2,
+            e.cfg.nontemporal, split.c_str(), e.ms);
   }
   fclose(f);
   return QFT_OK;
@@ -335,6 +335,8 @@ int qft_tune_load(const char *path) {
     cfg.radix_log2 = (int)r;
     cfg.spec_log2 = (int)c;
     cfg.rev_spec_log2 = (int)b;
+    double ntv;
+    if (get_num(line, "nontemporal", &ntv)) cfg.nontemporal = (int)ntv;
     std::string split;
     if (get_str(line, "pass_bits", &split) && !split.empty()) {
       const char *q = split.c_str();

@@ -51,6 +51,7 @@ class QftError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("tile_log2", ctypes.c_int), ("radix_log2", ctypes.c_int),
                 ("spec_log2", ctypes.c_int), ("rev_spec_log2", ctypes.c_int),
+                ("nontemporal", ctypes.c_int),
                 ("pass_bits", ctypes.c_int * QFT_MAX_PASSES)]
 
 
@@ -334,7 +335,9 @@ def fill_random(x, dist="gaussian", seed: int = 0, stream_id: int = 0, stream=No
 # ---- autotuner ------------------------------------------------------------
 
 def _cfg_dict(c: Config) -> dict:
-    d = {f: getattr(c, f) for f, _ in Config._fields_ if f != "pass_bits"}
+    d = {f: getattr(c, f) for f, _ in Config._fields_ if f not in ("pass_bits", "nontemporal")}
+    if c.nontemporal:
+        d["nontemporal"] = c.nontemporal
     pb = [int(x) for x in c.pass_bits if int(x) > 0]
     if pb:
         d["pass_bits"] = pb

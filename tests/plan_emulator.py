@@ -34,7 +34,7 @@ class PassDesc(ctypes.Structure):
         ("n", i32), ("T", i32), ("r", i32), ("m", i32), ("pbase", i32), ("lo", i32),
         ("ngroups", i32), ("reverse", i32), ("ext_tw", i32), ("aqft", i32), ("k", i32),
         ("nfree", i32), ("MI", i32), ("L", i32), ("xcd_remap", i32),
-        ("conj_in", i32), ("conj_out", i32), ("ntiles", u32),
+        ("conj_in", i32), ("conj_out", i32), ("nt", i32), ("ntiles", u32),
         ("gpos_w", u32 * 4), ("free_w", u32 * 8),
         ("ld_thr_w", u32 * 4), ("ld_reg_w", u32 * 2),
         ("st_thr_w", u32 * 4), ("st_reg_w", u32 * 2),

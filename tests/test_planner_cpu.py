@@ -249,3 +249,17 @@ def test_inverse_descriptor_flags():
     # one-pass plan: both on the same pass
     d, _ = E.get_pass(10, -1, "unitary", layout, None, 0)
     assert d.conj_in == 1 and d.conj_out == 1
+
+
+def test_nontemporal_rule():
+    # streaming access on passes whose tiles read whole 128-byte lines, and
+    # only when the state is larger than the 256 MB Infinity Cache
+    def nts(n, dtype="c64", cfg=None):
+        lay = Q.layout_flags(dtype)
+        P = Q.describe(n, dtype=dtype, config=cfg).num_passes
+        return [E.get_pass(n, -1, "unitary", lay, cfg, p)[0].nt for p in range(P)]
+    assert nts(28) == [1, 0, 1]        # 128 B rows, 64 B rows, contiguous
+    assert nts(27, "c128") == [1, 0, 1]
+    assert nts(24) == [0, 0, 0]        # 128 MiB state: stays cached
+    assert nts(24, cfg=dict(nontemporal=2)) == [1, 0, 1]
+    assert nts(28, cfg=dict(nontemporal=1)) == [0, 0, 0]
