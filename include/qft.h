@@ -97,7 +97,7 @@ typedef void *qft_stream_t; /* hipStream_t */
  * nontemporal: streaming (non-temporal) loads and stores, which do not
  *              keep the data in the caches: 0 = planner's choice (on passes
  *              whose tiles read whole 128-byte lines, when the state is
- *              larger than 256 MiB and so cannot stay in the 256 MB
+ *              at least 256 MiB and so does not stay in the 256 MB
  *              Infinity Cache between passes), 1 = never, 2 = on every pass
  *              whose tiles read whole 128-byte lines
  * pass_bits:   qubits of each HBM pass, most significant pass first,

@@ -261,5 +261,7 @@ def test_nontemporal_rule():
     assert nts(28) == [1, 0, 1]        # 128 B rows, 64 B rows, contiguous
     assert nts(27, "c128") == [1, 0, 1]
     assert nts(24) == [0, 0, 0]        # 128 MiB state: stays cached
+    assert nts(25) == [1, 0, 1]        # 256 MiB
+    assert nts(24, "c128") == [1, 0, 1]
     assert nts(24, cfg=dict(nontemporal=2)) == [1, 0, 1]
     assert nts(28, cfg=dict(nontemporal=1)) == [0, 0, 0]
