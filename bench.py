@@ -225,7 +225,16 @@ def main():
     # roofline uses its mean launch time over the timed region
     mean_pass_ms = sum(pass_ms) / len(pass_ms)
     real = "float" if args.dtype == "c64" else "double"
-    kernel = f"k_fused_pass<{real}, {info.config.radix_log2}>"
+    names = []
+    for p in range(info.num_passes):
+        sh = info.pass_kernel[p]
+        st = "true" if info.pass_streaming[p] else "false"
+        if sh:
+            ext = "true" if sh > 5 else "false"
+            names.append(f"k_fused_pass2<{real}, 5, {(sh - 1) % 5 + 1}, {ext}, {st}>")
+        else:
+            names.append(f"k_fused_pass<{real}, {info.config.radix_log2}>")
+    kernel = "; ".join(names)
     achieved = per_launch_bytes / (mean_pass_ms * 1e-3) / 1e9
     hbm_gbs = info.hbm_bytes / (ms_per_step * 1e-3) / 1e9
 
@@ -260,7 +269,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": f"{kernel}, mean over the plan's {info.num_passes} passes",
+            "kernel": f"fused pass kernels, mean over the plan's {info.num_passes} passes: {kernel}",
             "algorithmic_bytes_per_launch": per_launch_bytes,
         },
     }

@@ -126,6 +126,11 @@ typedef struct qft_plan_info {
   int pass_bits[QFT_MAX_PASSES]; /* qubits applied by pass p                 */
   int pass_spec[QFT_MAX_PASSES]; /* spectator (coalescing) bits of pass p    */
   int pass_reverse[QFT_MAX_PASSES]; /* pass p writes bit-reversed addresses  */
+  int pass_kernel[QFT_MAX_PASSES];  /* 0: the generic pass kernel; else the
+                                       compile-time two-group kernel, shape
+                                       1 + 5 * (below-pass diagonal) +
+                                       (stages of the last group - 1)        */
+  int pass_streaming[QFT_MAX_PASSES]; /* pass p uses non-temporal access    */
   qft_config_t config;
   long long gates_h, gates_cr, gates_swap;
   size_t state_bytes;     /* 2^n * element size                              */

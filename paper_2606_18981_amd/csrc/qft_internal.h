@@ -104,4 +104,16 @@ struct PassLaunch {
   int out_ws;         // write to the workspace instead of the state
 };
 
+// 0 for the generic pass kernel; 1 + 5 * ext + (nst - 1) for a pass with the
+// two-group shape of the compile-time specialised kernel: radix 32, the
+// first group full and carrying per-thread factors, the last group holding
+// pass bit 0 with nst stages, every thread of the workgroup active.
+inline int pass2_shape(const PassLaunch &L) {
+  const PassDesc &d = L.d;
+  const bool two = d.r == 5 && d.ngroups == 2 && d.grp[0].nst == d.r && d.grp[0].jbase > 0 &&
+                   d.grp[1].jbase == 0 && d.grp[1].nst >= 1 && d.grp[1].nst <= d.r &&
+                   L.threads == (1 << (d.T - d.r));
+  return two ? 1 + (d.ext_tw ? 5 : 0) + (d.grp[1].nst - 1) : 0;
+}
+
 }  // namespace qft

@@ -511,13 +511,7 @@ k_fused_pass2(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
                                       reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x);
 }
 
-int fused_pass_shape(const PassLaunch &L) {
-  const PassDesc &d = L.d;
-  const bool two = d.r == 5 && d.ngroups == 2 && d.grp[0].nst == d.r && d.grp[0].jbase > 0 &&
-                   d.grp[1].jbase == 0 && d.grp[1].nst >= 1 && d.grp[1].nst <= d.r &&
-                   L.threads == (1 << (d.T - d.r));
-  return two ? 1 + (d.ext_tw ? 5 : 0) + (d.grp[1].nst - 1) : 0;
-}
+int fused_pass_shape(const PassLaunch &L) { return pass2_shape(L); }
 
 template <typename Real, int RB>
 static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, hipStream_t s) {

@@ -534,6 +534,8 @@ void describe_plan(const HostPlan &p, qft_plan_info_t *o) {
       o->pass_bits[i] = d.m;
       o->pass_spec[i] = d.pbase;
       o->pass_reverse[i] = d.reverse;
+      o->pass_kernel[i] = pass2_shape(p.passes[i]);
+      o->pass_streaming[i] = d.nt;
     }
   } else {
     o->num_passes = (int)p.gates.size() + (p.gate_norm != 1.0 ? 1 : 0);

@@ -63,6 +63,8 @@ class PlanInfo(ctypes.Structure):
         ("pass_bits", ctypes.c_int * QFT_MAX_PASSES),
         ("pass_spec", ctypes.c_int * QFT_MAX_PASSES),
         ("pass_reverse", ctypes.c_int * QFT_MAX_PASSES),
+        ("pass_kernel", ctypes.c_int * QFT_MAX_PASSES),
+        ("pass_streaming", ctypes.c_int * QFT_MAX_PASSES),
         ("config", Config),
         ("gates_h", ctypes.c_longlong), ("gates_cr", ctypes.c_longlong),
         ("gates_swap", ctypes.c_longlong),
