@@ -164,11 +164,13 @@ static qft_plan_t *make_plan(int n, int cutoff, int norm, int layout, const qft_
     }
   }
   p->launches = hp.passes;
-  for (PassLaunch &L : p->launches) {
+  for (size_t i = 0; i < p->launches.size(); ++i) {
+    PassLaunch &L = p->launches[i];
     unsigned char *t = (unsigned char *)p->d_tables;
     L.d.tw_int = t + hp.off_int;
     L.d.tw_lo = t + hp.off_lo;
     L.d.tw_hi = t + hp.off_hi;
+    L.d.gtab = hp.off_gtab[i] ? t + hp.off_gtab[i] : nullptr;
   }
   return p;
 }

@@ -24,6 +24,8 @@ int qft_debug_pass(int n, int cutoff, int norm, int layout, const qft_config_t *
   if (!out_desc || desc_bytes < sizeof(PassDesc)) return QFT_ERR_INVALID;
   PassLaunch L = hp.passes[pass];
   L.d.tw_int = L.d.tw_lo = L.d.tw_hi = nullptr;
+  // the group-factor table: its byte offset in the table image (0: none)
+  L.d.gtab = reinterpret_cast<const void *>((uintptr_t)hp.off_gtab[pass]);
   memcpy(out_desc, &L.d, sizeof(PassDesc));
   if (launch) {
     launch[0] = L.threads;
@@ -45,7 +47,8 @@ int qft_debug_tables(int n, int cutoff, int norm, int layout, const qft_config_t
     offsets[0] = hp.off_int;
     offsets[1] = hp.off_lo;
     offsets[2] = hp.off_hi;
-    offsets[3] = hp.tables.size();
+    offsets[3] = hp.end_hi;
+    offsets[4] = hp.tables.size();
   }
   if (out) {
     if (out_bytes < hp.tables.size()) return QFT_ERR_INVALID;

@@ -85,6 +85,8 @@ struct PassDesc {
   const void *tw_int;         // w_{2^MI}^y, y < 2^(MI-1)
   const void *tw_lo;          // w_N^x, x < 2^L
   const void *tw_hi;          // w_N^(x 2^L), x < 2^(n-L)
+  const void *gtab;           // per-thread factors of group 0, [q][tid]
+                              // (entries of tw_int), or null
   double *norm_part;          // non-null: per-wave sums of |x|^2 of the
                               // loaded tile at [tile * parts_per_tile + w]
 };

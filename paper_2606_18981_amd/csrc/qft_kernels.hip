@@ -460,9 +460,15 @@ __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, con
   const uint32_t base = tile_base(d, tile);
   const uint32_t st_thr = deposit_tid(tid, d.st_thr_w, TR);
 
-  // every table read first: they are in flight together with the tile's
+  // every table read first: they are in flight together with the tile's.
+  // The first group's factors come from the planner's per-thread table
+  // (the same table entries, 64 consecutive ones per wave).
   C gf[RB];
-  group_factors<Real, RB>(d, d.grp[0], deposit_tid(tid, d.grp[0].thr_w, TR), gf);
+  {
+    const C *__restrict__ gt = (const C *)d.gtab;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) gf[q] = gt[(uint32_t)q * blockDim.x + tid];
+  }
   ExtRaw<Real, RB> raw;
   if (EXT) ext_loads<Real, RB>(d, base | st_thr, raw);
 

@@ -158,6 +158,48 @@ int max_thread_bits(int r, bool c128) {
   return r >= 5 ? 9 : 10;
 }
 
+// Per-thread factors of the first register group of every pass that the
+// compile-time two-group kernel runs: entry [q][tid] is the internal-table
+// entry w_{2^MI}^{x << (MI - 1 - jl)} that the group's factor for register
+// bit q of thread tid reads (jl = jbase + q, x = the thread's lower pass bits
+// with those below jl - k cleared for an AQFT).  Copying the table entry
+// keeps the result bitwise the same as reading the table, while the kernel
+// reads 64 consecutive entries per wave instead of 64 scattered ones.
+void build_group_tables(HostPlan &p) {
+  const size_t es = p.elem_bytes;
+  p.off_gtab.assign(p.passes.size(), 0);
+  for (size_t i = 0; i < p.passes.size(); ++i) {
+    const PassLaunch &L = p.passes[i];
+    if (!pass2_shape(L)) continue;
+    const PassDesc &d = L.d;
+    const GroupMap &G = d.grp[0];
+    const int TR = d.T - d.r;
+    const int threads = L.threads;
+    const size_t off = p.tables.size();
+    p.off_gtab[i] = off;
+    p.tables.resize(align_up(off + (size_t)d.r * threads * es, 256), 0);
+    const int MI1 = d.MI - 1;
+    for (int tid = 0; tid < threads; ++tid) {
+      uint32_t e_thr = 0;
+      for (int b = 0; b < TR; ++b) e_thr |= (uint32_t)((tid >> b) & 1) << pos_get(G.thr_w, b);
+      const uint32_t u = (e_thr >> d.pbase) & ((1u << G.jbase) - 1u);
+      for (int q = 0; q < d.r; ++q) {
+        const size_t dst = off + ((size_t)q * threads + tid) * es;
+        if (q >= G.nst) {
+          put_cplx(p.tables, dst, 0, p.c128, 1.0, 0.0);
+          continue;
+        }
+        const int jl = G.jbase + q;
+        int clear = d.aqft ? jl - d.k : 0;
+        clear = clear < 0 ? 0 : clear;
+        const uint32_t x = clear >= G.jbase ? 0u : ((u >> clear) << clear);
+        const size_t src = p.off_int + ((size_t)x << (MI1 - jl)) * es;
+        memcpy(&p.tables[dst], &p.tables[src], es);
+      }
+    }
+  }
+}
+
 int plan_fused(HostPlan &p, std::string &err) {
   const int n = p.n;
   const qft_config_t &c = p.cfg;
@@ -271,6 +313,7 @@ int plan_fused(HostPlan &p, std::string &err) {
   p.off_lo = align_up(p.off_int + n_int * es, 256);
   p.off_hi = align_up(p.off_lo + n_lo * es, 256);
   p.tables.assign(align_up(p.off_hi + n_hi * es, 256), 0);
+  p.end_hi = p.off_hi + n_hi * es;
   for (size_t y = 0; y < n_int; ++y) {
     double re, im;
     omega_pow2(MI, y, &re, &im);
@@ -370,6 +413,7 @@ int plan_fused(HostPlan &p, std::string &err) {
     }
     p.passes.push_back(L);
   }
+  build_group_tables(p);
   return QFT_OK;
 }
 

@@ -44,6 +44,9 @@ struct HostPlan {
   // table image (in the plan's dtype), byte offsets of each table
   std::vector<unsigned char> tables;
   size_t off_int = 0, off_lo = 0, off_hi = 0;
+  // per pass: byte offset of its per-thread group-0 factor table, or 0 (none)
+  std::vector<size_t> off_gtab;
+  size_t end_hi = 0;  // end of the high table (the group tables follow)
 
   // gate schedule
   std::vector<Gate> gates;

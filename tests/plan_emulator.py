@@ -41,6 +41,7 @@ class PassDesc(ctypes.Structure):
         ("grp", GroupMap * MAX_GROUPS),
         ("scale", ctypes.c_double),
         ("tw_int", ctypes.c_void_p), ("tw_lo", ctypes.c_void_p), ("tw_hi", ctypes.c_void_p),
+        ("gtab", ctypes.c_void_p),
         ("norm_part", ctypes.c_void_p),
     ]
 
@@ -70,12 +71,12 @@ def get_pass(n, cutoff, norm, layout, config, p):
 
 
 def get_tables(n, cutoff, norm, layout, config):
-    off = (ctypes.c_size_t * 4)()
+    off = (ctypes.c_size_t * 5)()
     c = Q._config(config)
     cref = ctypes.byref(c) if c is not None else None
     Q._check(Q.lib.qft_debug_tables(n, cutoff, Q._norm(norm), layout, cref, None, 0, off))
-    buf = (ctypes.c_uint8 * max(1, off[3]))()
-    Q._check(Q.lib.qft_debug_tables(n, cutoff, Q._norm(norm), layout, cref, buf, off[3], off))
+    buf = (ctypes.c_uint8 * max(1, off[4]))()
+    Q._check(Q.lib.qft_debug_tables(n, cutoff, Q._norm(norm), layout, cref, buf, off[4], off))
     dt = np.complex128 if layout & Q.QFT_C128 else np.complex64
     raw = np.frombuffer(bytes(buf), dtype=np.uint8)
     es = np.dtype(dt).itemsize
@@ -84,6 +85,46 @@ def get_tables(n, cutoff, norm, layout, config):
         return raw[a:b].view(dt).astype(np.complex128) if b > a else np.zeros(0, np.complex128)
 
     return tab(off[0], off[1]), tab(off[1], off[2]), tab(off[2], off[3]), es
+
+
+def get_table_image(n, cutoff, norm, layout, config):
+    """The plan's whole table image as raw bytes, and its element dtype."""
+    off = (ctypes.c_size_t * 5)()
+    c = Q._config(config)
+    cref = ctypes.byref(c) if c is not None else None
+    Q._check(Q.lib.qft_debug_tables(n, cutoff, Q._norm(norm), layout, cref, None, 0, off))
+    buf = (ctypes.c_uint8 * max(1, off[4]))()
+    Q._check(Q.lib.qft_debug_tables(n, cutoff, Q._norm(norm), layout, cref, buf, off[4], off))
+    dt = np.complex128 if layout & Q.QFT_C128 else np.complex64
+    return np.frombuffer(bytes(buf), dtype=np.uint8), dt
+
+
+def check_group_table(d, launch, image, dt, W):
+    """The planner's per-thread factor table of group 0 (d.gtab is its byte
+    offset in the image) must hold, bit for bit, the internal-table entries
+    that the group's factors read."""
+    if not d.gtab:
+        return False
+    threads = launch[0]
+    RB, TR = d.r, d.T - d.r
+    G = d.grp[0]
+    es = np.dtype(dt).itemsize
+    got = image[d.gtab:d.gtab + RB * threads * es].view(dt).reshape(RB, threads)
+    tid = np.arange(threads, dtype=np.int64)
+    e = np.zeros_like(tid)
+    for b in range(TR):
+        e |= ((tid >> b) & 1) << P(G.thr_w)[b]
+    u = (e >> d.pbase) & ((1 << G.jbase) - 1)
+    for q in range(RB):
+        if q >= G.nst:
+            assert np.all(got[q] == 1), "unused factor slots hold 1"
+            continue
+        jl = G.jbase + q
+        clear = max(0, jl - d.k) if d.aqft else 0
+        x = np.zeros_like(u) if clear >= G.jbase else (u >> clear) << clear
+        want = W[x << (d.MI - 1 - jl)].astype(dt)
+        assert np.array_equal(got[q], want), f"group table row {q} differs"
+    return True
 
 
 def _swizzle(e, c128):
@@ -239,10 +280,12 @@ def emulate(x, n, cutoff=-1, norm="unitary", dtype="c64", order="natural", confi
     c128 = bool(layout & Q.QFT_C128)
     info = Q.describe(n, cutoff, norm, dtype, order, "fused", config, inverse)
     tables = get_tables(n, cutoff, norm, layout, config)
+    image, dt = get_table_image(n, cutoff, norm, layout, config)
     state = np.asarray(x, dtype=np.complex128).copy()
     ws = np.zeros_like(state)
     for p in range(info.num_passes):
         d, launch = get_pass(n, cutoff, norm, layout, config, p)
+        check_group_table(d, launch, image, dt, tables[0])
         src = ws if launch[3] else state
         dst = ws if launch[4] else state
         idx, val = run_pass(d, launch, src, tables, c128)

@@ -265,3 +265,23 @@ def test_nontemporal_rule():
     assert nts(24, "c128") == [1, 0, 1]
     assert nts(24, cfg=dict(nontemporal=2)) == [1, 0, 1]
     assert nts(28, cfg=dict(nontemporal=1)) == [0, 0, 0]
+
+
+@pytest.mark.parametrize("n,k,dtype", [(28, None, "c64"), (27, None, "c128"), (24, 8, "c64"),
+                                       (21, 6, "c128"), (21, 3, "c128")])
+def test_group_factor_tables(n, k, dtype):
+    # every pass of the specialised two-group shape gets a per-thread table
+    # holding exactly the internal-table entries its first group reads
+    lay = Q.layout_flags(dtype)
+    cut = -1 if k is None else k
+    info = Q.describe(n, cut, dtype=dtype)
+    W = E.get_tables(n, cut, "unitary", lay, None)[0]
+    image, dt = E.get_table_image(n, cut, "unitary", lay, None)
+    checked = 0
+    for p in range(info.num_passes):
+        d, launch = E.get_pass(n, cut, "unitary", lay, None, p)
+        assert bool(d.gtab) == bool(info.pass_kernel[p])
+        checked += E.check_group_table(d, launch, image, dt, W)
+    assert checked == sum(1 for p in range(info.num_passes) if info.pass_kernel[p])
+    # radix 32 needs k >= 4 (a register group spans at most k + 1 qubits)
+    assert (checked > 0) == (k is None or k >= 4)
