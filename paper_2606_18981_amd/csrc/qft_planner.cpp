@@ -404,7 +404,9 @@ int plan_fused(HostPlan &p, std::string &err) {
       while (run < n && in_tile[run]) ++run;
       const bool lines = (es << run) >= 128;
       const bool big = p.state_bytes >= ((size_t)256 << 20);
-      d.nt = (c.nontemporal == 2 && lines) || (c.nontemporal == 0 && lines && big) ? 1 : 0;
+      // (only the compile-time two-group kernel has a streaming form)
+      const bool want = (c.nontemporal == 2 && lines) || (c.nontemporal == 0 && lines && big);
+      d.nt = want && pass2_shape(L) ? 1 : 0;
     }
     d.xcd_remap = (L.grid >= 8 && L.grid % 8 == 0) ? 1 : 0;
     if (natural_multi) {

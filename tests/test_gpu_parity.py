@@ -109,6 +109,9 @@ CONFIGS = [
     dict(tile_log2=11, radix_log2=3, spec_log2=2, rev_spec_log2=2),
     dict(tile_log2=14, radix_log2=5, spec_log2=4, rev_spec_log2=4),
     dict(tile_log2=12, radix_log2=4, spec_log2=2, rev_spec_log2=3, pass_bits=[7, 7, 6]),
+    # streaming (non-temporal) access on every pass that reads whole lines
+    dict(tile_log2=13, radix_log2=5, spec_log2=3, rev_spec_log2=3, nontemporal=2),
+    dict(tile_log2=11, radix_log2=5, spec_log2=4, rev_spec_log2=4, nontemporal=2),
 ]
 
 
