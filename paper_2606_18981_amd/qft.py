@@ -130,6 +130,10 @@ def _load():
         "qft_tune_clear": (I, []),
         "qft_tune_save": (I, [ctypes.c_char_p]),
         "qft_tune_load": (I, [ctypes.c_char_p]),
+        "qft_compare_workspace_bytes": (ctypes.c_size_t, [I]),
+        "qft_compare": (I, [P, P, I, I, P, P, P]),
+        "qft_aqft_expected_error": (ctypes.c_double, [I, I]),
+        "qft_select_cutoff": (I, [I, ctypes.c_double]),
         "qft_debug_pass_desc_size": (ctypes.c_size_t, []),
         "qft_debug_pass": (I, [I, I, I, I, ctypes.POINTER(Config), I, P, ctypes.c_size_t,
                                ctypes.POINTER(ctypes.c_int)]),
@@ -395,3 +399,50 @@ def tune_load(path) -> int:
     if rc < 0:
         raise QftError(rc, last_error())
     return rc
+
+
+# ---- accuracy metrics (include/qft_metrics.h) ------------------------------
+
+METRIC_NAMES = ("rel_l2", "max_err", "fidelity", "leakage", "norm_y", "norm_ref", "argmax")
+
+
+def expected_error(n: int, cutoff: int) -> float:
+    """Expected rel-L2 error of the range-k AQFT for i.i.d. complex Gaussian
+    inputs (closed form, host); negative when too costly to evaluate."""
+    return float(lib.qft_aqft_expected_error(n, cutoff))
+
+
+def select_cutoff(n: int, rel_l2_budget: float) -> int:
+    """Smallest cutoff whose expected error meets the budget (host)."""
+    k = int(lib.qft_select_cutoff(n, float(rel_l2_budget)))
+    if k < 0:
+        raise ValueError("invalid n or budget")
+    return k
+
+
+def compare(y, ref, stream=None, workspace=None, out=None):
+    """Accuracy metrics of y against ref (CUDA tensors of one complex dtype and
+    2^n elements), computed on the device in FP64.  Returns a dict; `out`
+    (a float64 CUDA tensor of 7 elements) receives the raw metrics."""
+    import torch
+    if y.dtype != ref.dtype or y.numel() != ref.numel():
+        raise ValueError("y and ref must have the same dtype and size")
+    if not (y.is_cuda and ref.is_cuda and y.is_contiguous() and ref.is_contiguous()):
+        raise ValueError("y and ref must be contiguous CUDA tensors")
+    N = y.numel()
+    n = N.bit_length() - 1
+    if N != 1 << n:
+        raise ValueError("size must be a power of two")
+    lay = layout_flags(y.dtype)
+    if workspace is None:
+        nb = int(lib.qft_compare_workspace_bytes(n))
+        workspace = torch.empty(max(1, nb // 8), dtype=torch.float64, device=y.device)
+    if out is None:
+        out = torch.empty(len(METRIC_NAMES), dtype=torch.float64, device=y.device)
+    _check(lib.qft_compare(ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ref.data_ptr()), n, lay,
+                           ctypes.c_void_p(workspace.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                           _stream_handle(stream)))
+    vals = out.cpu().tolist()
+    d = dict(zip(METRIC_NAMES, vals))
+    d["argmax"] = int(d["argmax"])
+    return d
