@@ -90,6 +90,35 @@ def bench_aqft(torch, Q, n, dtype, cutoffs, steps):
     return rows
 
 
+def bench_budget(torch, Q, n, budgets, steps):
+    """Cutoff picked by accuracy budget (closed-form expected error), then the
+    measured error against the exact transform of the same input, computed
+    on the device (qft_compare), and the runtime of the picked AQFT."""
+    N = 1 << n
+    x = torch.empty(N, dtype=torch.complex64, device="cuda")
+    Q.fill_random(x, "gaussian", seed=1003)
+    exact = x.clone()
+    plan = Q.Plan(n, -1, "unitary", "c64", "natural")
+    plan.execute(exact)
+    plan.close()
+    rows = []
+    for budget in budgets:
+        k = Q.select_cutoff(n, budget)
+        plan = Q.Plan(n, k, "unitary", "c64", "natural")
+        y = x.clone()
+        plan.execute(y)
+        m = Q.compare(y, exact)
+        ms = time_plan(torch, Q, plan, y, steps, 2)  # (transforms y in place)
+        del y
+        rows.append({"budget": budget, "cutoff": k, "predicted_rel_l2": Q.expected_error(n, k),
+                     "measured_rel_l2": m["rel_l2"], "fidelity": m["fidelity"],
+                     "ms": ms, "gates_cr": plan.info.gates_cr})
+        plan.close()
+    del x, exact
+    torch.cuda.empty_cache()
+    return rows
+
+
 def bench_batch(torch, Q, reps=10):
     """512 uneven transforms: one persistent graph launch vs one launch each."""
     from paper_2606_18981_amd import inputs as I
@@ -303,6 +332,8 @@ def main():
     if not args.no_extras:
         print("[bench] aqft sweep", file=sys.stderr, flush=True)
         out["aqft_n28_c64"] = bench_aqft(torch, Q, 28, "c64", [-1, 6, 10, 14, 18], 10)
+        print("[bench] cutoff by accuracy budget", file=sys.stderr, flush=True)
+        out["aqft_budget_n28_c64"] = bench_budget(torch, Q, 28, [1e-2, 1e-3, 1e-4], 10)
         print("[bench] complex128", file=sys.stderr, flush=True)
         out["exact_n28_c128"] = bench_aqft(torch, Q, 28, "c128", [-1], 10)[0]
         print("[bench] batch", file=sys.stderr, flush=True)
