@@ -229,6 +229,19 @@ int qft_execute_batch_ex(qft_plan_t *const *plans, void *const *dev_ptrs,
 int qft_fill_random(void *dev_ptr, int n, int layout, int dist, uint64_t seed,
                     uint64_t stream_id, qft_stream_t stream);
 
+/* ---- lengths that are not powers of two (Sec. 3 step 1) ----------------- */
+/* The method maps N amplitudes onto n = ceil(log2 N) qubits and allocates
+ * 2^n of them; the transform is then DFT_{2^n} of the input padded with
+ * zeros, not DFT_N.  qft_pad copies `count` elements from src to dst and
+ * zero-fills dst[count, 2^n), in one pass, asynchronously on `stream`.
+ * src and dst are device arrays of the layout's element type (QFT_C64 or
+ * QFT_C128); they must not overlap.  count <= 2^n.  Returns QFT_OK,
+ * QFT_ERR_INVALID or QFT_ERR_POINTER.                                       */
+int qft_pad(const void *src, size_t count, void *dst, int n, int layout, qft_stream_t stream);
+
+/* Smallest n with 2^n >= count (count >= 1), or -1.                         */
+int qft_qubits_for(size_t count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -66,6 +66,7 @@ __all__ = [
     "dft_bins",
     "dft_library",
     "qft_fused_targets",
+    "qft_padded",
     "rel_l2",
     "max_err",
     "fidelity",
@@ -447,6 +448,19 @@ def qft_fused_targets(x, cutoff=None, norm: str = "unitary",
     if order != "bitrev":
         raise ValueError(f"unknown order {order!r}")
     return psi
+
+
+def qft_padded(x, cutoff=None, norm: str = "unitary", order: str = "natural",
+               inverse: bool = False) -> np.ndarray:
+    """Sec. 3 step 1 for a length N that is not a power of two: n = ceil(log2 N)
+    qubits, 2^n amplitudes, the input followed by zeros; the result is the
+    (approximate) DFT of length 2^n of that padded input."""
+    x = np.asarray(x, dtype=np.complex128)
+    N = x.shape[0]
+    n = max(0, (N - 1).bit_length())
+    padded = np.zeros(1 << n, dtype=np.complex128)
+    padded[:N] = x
+    return qft_circuit(padded, cutoff, norm, order, encode=True, inverse=inverse)
 
 
 # ---------------------------------------------------------------------------

@@ -317,6 +317,30 @@ int qft_plan_pass_times(qft_plan_t *plan, double *ms, int max, long long *execs)
   return QFT_OK;
 }
 
+int qft_qubits_for(size_t count) {
+  if (count == 0) return -1;
+  int n = 0;
+  while (n < 63 && ((size_t)1 << n) < count) ++n;
+  return n <= QFT_MAX_QUBITS ? n : -1;
+}
+
+int qft_pad(const void *src, size_t count, void *dst, int n, int layout, qft_stream_t stream) {
+  clear_error();
+  if (n < 0 || n > QFT_MAX_QUBITS) return set_error(QFT_ERR_INVALID, "n out of range");
+  if (count > ((size_t)1 << n)) return set_error(QFT_ERR_INVALID, "count exceeds 2^n");
+  const bool c128 = (layout & QFT_C128) != 0;
+  const size_t es = c128 ? 16 : 8;
+  if (!dst || (count && !src)) return set_error(QFT_ERR_POINTER, "NULL pointer");
+  if ((uintptr_t)dst % es || (uintptr_t)src % es)
+    return set_error(QFT_ERR_POINTER, "pointer is not aligned to the element size");
+  const uintptr_t s0 = (uintptr_t)src, s1 = s0 + count * es;
+  const uintptr_t d0 = (uintptr_t)dst, d1 = d0 + (es << n);
+  if (count && s0 < d1 && d0 < s1) return set_error(QFT_ERR_INVALID, "src and dst overlap");
+  hipError_t e = launch_pad(src, count, dst, n, c128, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_error(e, "pad launch");
+  return QFT_OK;
+}
+
 int qft_fill_random(void *dev_ptr, int n, int layout, int dist, uint64_t seed, uint64_t stream_id,
                     qft_stream_t stream) {
   clear_error();

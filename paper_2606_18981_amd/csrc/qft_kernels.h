@@ -56,6 +56,9 @@ hipError_t launch_norm_sweep(const void *psi, int n, bool c128, double *part, ui
 hipError_t launch_norm_finish(const double *part, uint32_t count, double *out, hipStream_t s);
 
 // Philox-4x32-10 input generator.
+// dst[i] = i < count ? src[i] : 0 for i < 2^n.
+hipError_t launch_pad(const void *src, size_t count, void *dst, int n, bool c128, hipStream_t s);
+
 hipError_t launch_fill_random(void *psi, int n, bool c128, int dist, uint64_t seed,
                               uint64_t stream_id, hipStream_t s);
 

@@ -843,6 +843,31 @@ hipError_t launch_norm_finish(const double *part, uint32_t count, double *out, h
 }
 
 // ---------------------------------------------------------------------------
+// zero padding to a power of two
+// ---------------------------------------------------------------------------
+
+template <typename Real>
+__global__ void __launch_bounds__(256) k_pad(const cplx<Real> *src, uint64_t count,
+                                             cplx<Real> *dst, uint64_t N) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = i < count ? src[i] : cplx<Real>{(Real)0, (Real)0};
+}
+
+hipError_t launch_pad(const void *src, size_t count, void *dst, int n, bool c128, hipStream_t s) {
+  const uint64_t N = 1ull << n;
+  const uint64_t blocks = (N + 255) / 256;
+  const dim3 grid((unsigned)(blocks < 65536 ? blocks : 65536));
+  if (c128)
+    hipLaunchKernelGGL(k_pad<double>, grid, dim3(256), 0, s, (const cplx<double> *)src,
+                       (uint64_t)count, (cplx<double> *)dst, N);
+  else
+    hipLaunchKernelGGL(k_pad<float>, grid, dim3(256), 0, s, (const cplx<float> *)src,
+                       (uint64_t)count, (cplx<float> *)dst, N);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Philox-4x32-10 input generator
 // ---------------------------------------------------------------------------
 

@@ -130,6 +130,8 @@ def _load():
         "qft_tune_clear": (I, []),
         "qft_tune_save": (I, [ctypes.c_char_p]),
         "qft_tune_load": (I, [ctypes.c_char_p]),
+        "qft_pad": (I, [P, ctypes.c_size_t, P, I, I, P]),
+        "qft_qubits_for": (I, [ctypes.c_size_t]),
         "qft_compare_workspace_bytes": (ctypes.c_size_t, [I]),
         "qft_compare": (I, [P, P, I, I, P, P, P]),
         "qft_aqft_expected_error": (ctypes.c_double, [I, I]),
@@ -446,3 +448,22 @@ def compare(y, ref, stream=None, workspace=None, out=None):
     d = dict(zip(METRIC_NAMES, vals))
     d["argmax"] = int(d["argmax"])
     return d
+
+
+# ---- lengths that are not powers of two --------------------------------------
+
+def padded(x, stream=None):
+    """A new CUDA tensor of 2^ceil(log2 len(x)) elements: x followed by zeros
+    (one device pass).  Transforming it gives DFT_{2^n} of the padded input,
+    as the method defines for such lengths, not DFT_len(x)."""
+    import torch
+    if not (x.is_cuda and x.is_contiguous() and x.dim() == 1):
+        raise ValueError("x must be a contiguous 1-D CUDA tensor")
+    n = int(lib.qft_qubits_for(x.numel()))
+    if n < 0:
+        raise ValueError("length out of range")
+    n = max(n, 1)  # plans take at least one qubit
+    out = torch.empty(1 << n, dtype=x.dtype, device=x.device)
+    _check(lib.qft_pad(ctypes.c_void_p(x.data_ptr()), x.numel(), ctypes.c_void_p(out.data_ptr()),
+                       n, layout_flags(x.dtype), _stream_handle(stream)))
+    return out

@@ -247,6 +247,34 @@ def test_execute_norm(torch_cuda, Q, n, dtype, schedule):
     plan.close()
 
 
+# ---- lengths that are not powers of two --------------------------------------
+
+@pytest.mark.parametrize("N,dtype", [(3, "c64"), (1000, "c128"), (70000, "c64"), (1, "c128")])
+def test_padded_transform(torch_cuda, Q, N, dtype):
+    torch = torch_cuda
+    import ctypes
+    print(f"[gpu] padded N={N} {dtype}", flush=True)
+    rng = np.random.default_rng(N)
+    x = (rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(NPDT[dtype])
+    t = Q.padded(torch.from_numpy(x).cuda())
+    M = t.numel()
+    assert M == max(2, 1 << (N - 1).bit_length())
+    host = t.cpu().numpy()
+    assert np.array_equal(host[:N], x) and not np.any(host[N:])
+    n = M.bit_length() - 1
+    plan = Q.Plan(n, -1, "unitary", dtype, "natural")
+    plan.execute(t)
+    torch.cuda.synchronize()
+    ref = O.qft_padded(x.astype(np.complex128)) if N > 1 else O.qft_circuit(
+        np.array([x[0], 0], dtype=np.complex128))
+    assert O.rel_l2(t.cpu().numpy().astype(np.complex128), ref) <= TOL[dtype]
+    plan.close()
+    # overlapping buffers are refused
+    rc = Q.lib.qft_pad(ctypes.c_void_p(t.data_ptr()), 1, ctypes.c_void_p(t.data_ptr()), n,
+                       Q.layout_flags(dtype), None)
+    assert rc == Q.QFT_ERR_INVALID
+
+
 # ---- device input generator ------------------------------------------------
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])

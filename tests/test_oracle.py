@@ -453,3 +453,21 @@ def test_inverse_tone_and_bins():
     assert O.rel_l2(O.dft_bins(xg, bins, inverse=True), full[bins]) < TOL
     full6 = O.qft_fused_targets(xg, 6, "unitary", "natural", inverse=True)
     assert O.rel_l2(O.aqft_bins(xg, bins, 6, inverse=True), full6[bins]) < TOL
+
+
+
+# --------------------------------------------------------------------------
+# lengths that are not powers of two (Sec. 3 step 1)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 100, 1000])
+def test_padded_is_library_fft_of_zero_padded_input(N):
+    rng = np.random.default_rng(900 + N)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    M = 1 << max(0, (N - 1).bit_length())
+    y = O.qft_padded(x)
+    assert y.shape == (M,)
+    # numpy's fft with n = M zero-pads the input to length M
+    assert O.rel_l2(y, np.fft.fft(x, n=M) / math.sqrt(M)) < TOL
+    if N == M:
+        assert O.rel_l2(y, O.qft_circuit(x)) < TOL
