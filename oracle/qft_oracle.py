@@ -67,6 +67,8 @@ __all__ = [
     "dft_library",
     "qft_fused_targets",
     "qft_padded",
+    "apply_gates",
+    "qft_as_gates",
     "rel_l2",
     "max_err",
     "fidelity",
@@ -461,6 +463,63 @@ def qft_padded(x, cutoff=None, norm: str = "unitary", order: str = "natural",
     padded = np.zeros(1 << n, dtype=np.complex128)
     padded[:N] = x
     return qft_circuit(padded, cutoff, norm, order, encode=True, inverse=inverse)
+
+
+def apply_gates(x, gates) -> np.ndarray:
+    """Gate-by-gate FP64 simulation of a general gate list on n qubits, with
+    the Sec. 2 conventions (qubit q_j = bit j of the index; a one-wire gate U
+    on q_j is I_{2^{n-1-j}} (x) U (x) I_{2^j}).  Gates:
+      ("U", q, M)      2x2 matrix M on qubit q;
+      ("CU", c, t, M)  M on qubit t where qubit c is 1;
+      ("SWAP", a, b)   exchange qubits a and b.
+    """
+    psi = np.array(x, dtype=np.complex128)
+    N = psi.shape[0]
+    n = N.bit_length() - 1
+    for g in gates:
+        if g[0] == "U":
+            q, M = g[1], np.asarray(g[2], dtype=np.complex128)
+            v = psi.reshape(1 << (n - 1 - q), 2, 1 << q)
+            a = v[:, 0, :].copy()
+            b = v[:, 1, :].copy()
+            v[:, 0, :] = M[0, 0] * a + M[0, 1] * b
+            v[:, 1, :] = M[1, 0] * a + M[1, 1] * b
+        elif g[0] == "CU":
+            c, t, M = g[1], g[2], np.asarray(g[3], dtype=np.complex128)
+            v = psi.reshape((2,) * n)  # axis n-1-j holds bit j
+            sel = [slice(None)] * n
+            sel[n - 1 - c] = 1
+            sub = v[tuple(sel)]  # control bit fixed to 1: n-1 axes
+            ax = (n - 1 - t) - (1 if (n - 1 - c) < (n - 1 - t) else 0)
+            s0 = [slice(None)] * (n - 1)
+            s1 = [slice(None)] * (n - 1)
+            s0[ax] = 0
+            s1[ax] = 1
+            a = sub[tuple(s0)].copy()
+            b = sub[tuple(s1)].copy()
+            sub[tuple(s0)] = M[0, 0] * a + M[0, 1] * b
+            sub[tuple(s1)] = M[1, 0] * a + M[1, 1] * b
+        elif g[0] == "SWAP":
+            psi = _apply_swap(psi, n, g[1], g[2])
+        else:
+            raise ValueError(f"unknown gate {g[0]!r}")
+    return psi
+
+
+def qft_as_gates(n: int, cutoff=None, order: str = "natural"):
+    """The QFT circuit of ``qft_gate_list`` written as general gates: H as the
+    matrix [[1, 1], [1, -1]] / sqrt(2), controlled-R_m as controlled
+    diag(1, exp(-2 pi i / 2^m)), and the swaps (natural order only)."""
+    h = np.array([[1.0, 1.0], [1.0, -1.0]]) / math.sqrt(2.0)
+    out = []
+    for g in qft_gate_list(n, cutoff):
+        if g[0] == "H":
+            out.append(("U", g[1], h))
+        elif g[0] == "CR":
+            out.append(("CU", g[1], g[2], np.diag([1.0, np.exp(-2j * np.pi / float(1 << g[3]))])))
+        elif order == "natural":
+            out.append(("SWAP", g[1], g[2]))
+    return out
 
 
 # ---------------------------------------------------------------------------

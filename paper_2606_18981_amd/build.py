@@ -17,7 +17,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HIP_SOURCES = ["qft_kernels.hip", "qft_api.hip", "qft_batch.hip", "qft_server.hip", "qft_tune.hip",
-               "qft_metrics.hip"]
+               "qft_metrics.hip", "qft_circuit.hip"]
 CXX_SOURCES = ["qft_planner.cpp", "qft_debug.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

@@ -131,6 +131,16 @@ def _load():
         "qft_tune_save": (I, [ctypes.c_char_p]),
         "qft_tune_load": (I, [ctypes.c_char_p]),
         "qft_pad": (I, [P, ctypes.c_size_t, P, I, I, P]),
+        "qft_circuit_create": (P, [I, I]),
+        "qft_circuit_destroy": (None, [P]),
+        "qft_circuit_add_1q": (I, [P, I, ctypes.POINTER(ctypes.c_double)]),
+        "qft_circuit_add_controlled": (I, [P, I, I, ctypes.POINTER(ctypes.c_double)]),
+        "qft_circuit_add_swap": (I, [P, I, I]),
+        "qft_circuit_compile": (I, [P, I]),
+        "qft_circuit_info": (I, [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+        "qft_circuit_describe": (I, [P, I, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_int), I]),
+        "qft_circuit_execute": (I, [P, P, P]),
         "qft_qubits_for": (I, [ctypes.c_size_t]),
         "qft_compare_workspace_bytes": (ctypes.c_size_t, [I]),
         "qft_compare": (I, [P, P, I, I, P, P, P]),
@@ -467,3 +477,79 @@ def padded(x, stream=None):
     _check(lib.qft_pad(ctypes.c_void_p(x.data_ptr()), x.numel(), ctypes.c_void_p(out.data_ptr()),
                        n, layout_flags(x.dtype), _stream_handle(stream)))
     return out
+
+
+# ---- general fused circuits (include/qft_circuit.h) ---------------------------
+
+def _mat8(u):
+    import numpy as np
+    m = np.asarray(u, dtype=np.complex128).reshape(2, 2)
+    flat = np.empty(8, dtype=np.float64)
+    flat[0::2] = m.real.ravel()
+    flat[1::2] = m.imag.ravel()
+    return (ctypes.c_double * 8)(*flat.tolist())
+
+
+class Circuit:
+    """A list of one- and two-qubit gates on n qubits, run in fused passes
+    (runs of consecutive gates whose qubits fit in one tile share one HBM
+    pass)."""
+
+    def __init__(self, n: int, dtype="c64"):
+        self.n = n
+        self.c128 = bool(layout_flags(dtype) & QFT_C128)
+        h = lib.qft_circuit_create(n, layout_flags(dtype))
+        if not h:
+            raise QftError(QFT_ERR_INVALID, last_error())
+        self._h = ctypes.c_void_p(h)
+
+    def add_1q(self, q, u):
+        _check(lib.qft_circuit_add_1q(self._h, q, _mat8(u)))
+        return self
+
+    def add_controlled(self, control, target, u):
+        _check(lib.qft_circuit_add_controlled(self._h, control, target, _mat8(u)))
+        return self
+
+    def add_swap(self, a, b):
+        _check(lib.qft_circuit_add_swap(self._h, a, b))
+        return self
+
+    def compile(self, tile_qubits: int = 0):
+        _check(lib.qft_circuit_compile(self._h, tile_qubits))
+        return self
+
+    def describe(self, tile_qubits: int = 0, max_passes: int = 4096):
+        """Host-only grouping: (first gate of each pass, tile bits of each pass)."""
+        gb = (ctypes.c_int * max_passes)()
+        tb = (ctypes.c_int * max_passes)()
+        rc = lib.qft_circuit_describe(self._h, tile_qubits, gb, tb, max_passes)
+        _check(min(rc, 0))
+        k = min(rc, max_passes)
+        return list(gb)[:k], list(tb)[:k]
+
+    def info(self):
+        g, p = ctypes.c_int(0), ctypes.c_int(0)
+        _check(lib.qft_circuit_info(self._h, ctypes.byref(g), ctypes.byref(p)))
+        return {"gates": g.value, "passes": p.value}
+
+    def execute(self, x, stream=None):
+        import torch
+        want = torch.complex128 if self.c128 else torch.complex64
+        if not (x.is_cuda and x.dtype == want and x.is_contiguous() and x.numel() == 1 << self.n):
+            raise ValueError("x must be a contiguous CUDA tensor of 2^n elements of the "
+                             "circuit's dtype")
+        _check(lib.qft_circuit_execute(self._h, ctypes.c_void_p(x.data_ptr()),
+                                       _stream_handle(stream)))
+        return x
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.qft_circuit_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

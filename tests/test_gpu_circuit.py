@@ -1,0 +1,82 @@
+"""General fused circuits on the GPU against the oracle's gate-by-gate
+simulation: random gate lists and the QFT written as general gates."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_18981_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": 1e-5, "c128": 1e-12}
+NPDT = {"c64": np.complex64, "c128": np.complex128}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2606_18981_amd import qft as Q
+    return torch, Q
+
+
+def unitary(rng):
+    q, _ = np.linalg.qr(rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2)))
+    return q
+
+
+def random_gates(n, count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        kind = rng.integers(0, 3) if n > 1 else 0
+        if kind == 0:
+            out.append(("U", int(rng.integers(0, n)), unitary(rng)))
+        else:
+            a, b = rng.choice(n, 2, replace=False)
+            out.append(("CU", int(a), int(b), unitary(rng)) if kind == 1
+                       else ("SWAP", int(a), int(b)))
+    return out
+
+
+def run(torch, Q, n, gates, x, dtype, B=0):
+    c = Q.Circuit(n, dtype)
+    for g in gates:
+        if g[0] == "U":
+            c.add_1q(g[1], g[2])
+        elif g[0] == "CU":
+            c.add_controlled(g[1], g[2], g[3])
+        else:
+            c.add_swap(g[1], g[2])
+    c.compile(B)
+    t = torch.from_numpy(x.astype(NPDT[dtype])).cuda()
+    c.execute(t)
+    torch.cuda.synchronize()
+    info = c.info()
+    c.close()
+    return t.cpu().numpy().astype(np.complex128), info
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,count,B", [(1, 5, 0), (5, 40, 0), (12, 150, 6), (16, 300, 0),
+                                       (20, 200, 10), (13, 100, 2)])
+def test_random_circuits(env, dtype, n, count, B):
+    torch, Q = env
+    print(f"[gpu] circuit n={n} gates={count} B={B} {dtype}", flush=True)
+    gates = random_gates(n, count, 9000 + n)
+    x = I.gaussian(n, 9100 + n)
+    y, info = run(torch, Q, n, gates, x, dtype, B)
+    assert info["gates"] == len(gates) and info["passes"] >= 1
+    assert O.rel_l2(y, O.apply_gates(x, gates)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,k", [(10, None), (18, 6)])
+def test_qft_as_general_circuit(env, dtype, n, k):
+    torch, Q = env
+    print(f"[gpu] qft as circuit n={n} k={k} {dtype}", flush=True)
+    x = I.gaussian(n, 9200 + n)
+    y, info = run(torch, Q, n, O.qft_as_gates(n, k), x, dtype)
+    ref = O.qft_fused_targets(x, k)
+    assert O.rel_l2(y, ref) <= TOL[dtype]

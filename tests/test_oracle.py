@@ -471,3 +471,69 @@ def test_padded_is_library_fft_of_zero_padded_input(N):
     assert O.rel_l2(y, np.fft.fft(x, n=M) / math.sqrt(M)) < TOL
     if N == M:
         assert O.rel_l2(y, O.qft_circuit(x)) < TOL
+
+
+
+# --------------------------------------------------------------------------
+# general gate lists
+# --------------------------------------------------------------------------
+
+def _kron_gate(n, g):
+    """Full matrix of one gate from Kronecker products (Sec. 2 convention)."""
+    I2 = np.eye(2)
+    P0 = np.diag([1.0, 0.0])
+    P1 = np.diag([0.0, 1.0])
+
+    def chain(ops):  # ops[j] acts on qubit j; the leftmost factor is qubit n-1
+        out = np.eye(1)
+        for j in range(n - 1, -1, -1):
+            out = np.kron(out, ops.get(j, I2))
+        return out
+    if g[0] == "U":
+        return chain({g[1]: g[2]})
+    if g[0] == "CU":
+        return chain({g[1]: P0}) + chain({g[1]: P1, g[2]: g[3]})
+    a, b = g[1], g[2]
+    N = 1 << n
+    P = np.zeros((N, N))
+    for i in range(N):
+        ba, bb = (i >> a) & 1, (i >> b) & 1
+        j = i & ~((1 << a) | (1 << b)) | (bb << a) | (ba << b)
+        P[j, i] = 1.0
+    return P
+
+
+def _random_gates(n, count, seed):
+    rng = np.random.default_rng(seed)
+    gates = []
+    for _ in range(count):
+        M = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+        kind = rng.integers(0, 3)
+        if kind == 0:
+            gates.append(("U", int(rng.integers(0, n)), M))
+        elif kind == 1 and n > 1:
+            c, t = rng.choice(n, 2, replace=False)
+            gates.append(("CU", int(c), int(t), M))
+        elif n > 1:
+            a, b = rng.choice(n, 2, replace=False)
+            gates.append(("SWAP", int(a), int(b)))
+    return gates
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_apply_gates_matches_kronecker_matrices(n):
+    gates = _random_gates(n, 12, 40 + n)
+    x = I.gaussian(n, 50 + n)
+    y = x.astype(np.complex128)
+    for g in gates:
+        y = _kron_gate(n, g) @ y
+    assert O.rel_l2(O.apply_gates(x, gates), y) < TOL
+
+
+@pytest.mark.parametrize("n", [3, 6, 9])
+@pytest.mark.parametrize("k", [None, 2])
+def test_qft_as_general_gates_is_the_circuit(n, k):
+    x = I.gaussian(n, 60 + n)
+    for order in O.ORDERS:
+        y = O.apply_gates(x, O.qft_as_gates(n, k, order))
+        assert O.rel_l2(y, O.qft_circuit(x, k, "unitary", order, encode=False)) < TOL
