@@ -119,6 +119,45 @@ def bench_budget(torch, Q, n, budgets, steps):
     return rows
 
 
+def bench_circuit(torch, Q, n=24, steps=5):
+    """The QFT written as general gates (H, controlled phases, swaps) and run
+    through the general fused-circuit path, against the QFT plan."""
+    import numpy as np
+    N = 1 << n
+    x = torch.empty(N, dtype=torch.complex64, device="cuda")
+    Q.fill_random(x, "gaussian", seed=1003)
+    c = Q.Circuit(n, "c64")
+    h = np.array([[1.0, 1.0], [1.0, -1.0]]) / np.sqrt(2.0)
+    for t in range(n - 1, -1, -1):
+        c.add_1q(t, h)
+        for d in range(1, t + 1):
+            c.add_controlled(t - d, t, np.diag([1.0, np.exp(-2j * np.pi / 2.0 ** (d + 1))]))
+    for a in range(n // 2):
+        c.add_swap(a, n - 1 - a)
+    c.compile(10)
+    info = c.info()
+    for _ in range(2):
+        c.execute(x)
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(steps):
+        c.execute(x)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / steps
+    c.close()
+    plan = Q.Plan(n, -1, "unitary", "c64", "natural")
+    ms_plan = time_plan(torch, Q, plan, x, 10, 2)
+    plan.close()
+    del x
+    torch.cuda.empty_cache()
+    return {"n": n, "gates": info["gates"], "passes": info["passes"], "ms": ms,
+            "gbs": info["passes"] * 2 * N * 8 / (ms * 1e-3) / 1e9,
+            "qft_plan_ms": ms_plan, "qft_plan_passes": 3}
+
+
 def bench_batch(torch, Q, reps=10):
     """512 uneven transforms: one persistent graph launch vs one launch each."""
     from paper_2606_18981_amd import inputs as I
@@ -336,6 +375,8 @@ def main():
         out["aqft_budget_n28_c64"] = bench_budget(torch, Q, 28, [1e-2, 1e-3, 1e-4], 10)
         print("[bench] complex128", file=sys.stderr, flush=True)
         out["exact_n28_c128"] = bench_aqft(torch, Q, 28, "c128", [-1], 10)[0]
+        print("[bench] general circuit", file=sys.stderr, flush=True)
+        out["general_circuit_qft_n24_c64"] = bench_circuit(torch, Q)
         print("[bench] batch", file=sys.stderr, flush=True)
         out["batch_512"] = bench_batch(torch, Q)
         print("[bench] serve", file=sys.stderr, flush=True)
