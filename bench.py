@@ -159,7 +159,8 @@ def bench_circuit(torch, Q, n=24, steps=5):
 
 
 def bench_batch(torch, Q, reps=10):
-    """512 uneven transforms: one persistent graph launch vs one launch each."""
+    """512 uneven transforms: the batched launches in one HIP graph, the same
+    launches enqueued directly, and one plan execute per transform."""
     from paper_2606_18981_amd import inputs as I
     ns, cuts = I.batch_sizes(1004, count=512, lo=8, hi=20, aqft_frac=0.25, aqft_k=8)
     plans, xs, cache = [], [], {}
