@@ -266,6 +266,36 @@ __device__ __forceinline__ void exchange(cplx<Real> (&v)[1 << RB], cplx<Real> *l
   __syncthreads();
 }
 
+// The same exchange in two halves: real parts, then imaginary parts, through
+// an LDS area of 2^T scalars (half the tile).  Four barriers instead of two,
+// but half the LDS per workgroup, so three 2^13-element complex64 workgroups
+// fit a CU's 160 KiB instead of two.
+template <typename Real, int RB>
+__device__ __forceinline__ void exchange_split(cplx<Real> (&v)[1 << RB], cplx<Real> *lds_c,
+                                               const GroupMap &P, const GroupMap &G,
+                                               uint32_t tid, int TR) {
+  constexpr int R = 1 << RB;
+  Real *lds = reinterpret_cast<Real *>(lds_c);
+  const uint32_t sp = lds_swizzle<Real>(deposit_tid(tid, P.thr_w, TR));
+  const uint32_t sg = lds_swizzle<Real>(deposit_tid(tid, G.thr_w, TR));
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho)
+    lds[sp ^ lds_swizzle<Real>(deposit_reg<RB>(rho, P.reg_w))] = v[rho].x;
+  __syncthreads();
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho)
+    v[rho].x = lds[sg ^ lds_swizzle<Real>(deposit_reg<RB>(rho, G.reg_w))];
+  __syncthreads();
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho)
+    lds[sp ^ lds_swizzle<Real>(deposit_reg<RB>(rho, P.reg_w))] = v[rho].y;
+  __syncthreads();
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho)
+    v[rho].y = lds[sg ^ lds_swizzle<Real>(deposit_reg<RB>(rho, G.reg_w))];
+  __syncthreads();
+}
+
 template <typename Real, int RB>
 __device__ __forceinline__ void conj_regs(cplx<Real> (&v)[1 << RB]) {
 #pragma unroll
@@ -483,7 +513,11 @@ __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, con
 
   radix_network<Real, RB>(v, RB);
   apply_factors<Real, RB>(v, gf, C{(Real)1, (Real)0}, false);
-  exchange<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR, true);
+  if constexpr (sizeof(Real) == 4) {
+    exchange_split<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR);  // half-tile LDS
+  } else {
+    exchange<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR, true);
+  }
   radix_network<Real, RB>(v, NSTL);
 
   if (EXT) {

@@ -392,6 +392,9 @@ int plan_fused(HostPlan &p, std::string &err) {
     d.scale = scales[i];
     L.threads = 1 << (Te - r);
     L.lds_bytes = d.ngroups > 1 ? (int)(((size_t)1 << Te) * es) : 0;
+    // the complex64 two-group kernel exchanges real and imaginary parts in
+    // turn through half the tile's LDS (three workgroups per CU at 2^13)
+    if (!p.c128 && pass2_shape(L)) L.lds_bytes /= 2;
     L.grid = d.ntiles;
     // Streaming loads and stores pay off where a tile reads whole 128-byte
     // lines: where it reads half lines, the neighbouring tile (run at the

@@ -285,3 +285,16 @@ def test_group_factor_tables(n, k, dtype):
     assert checked == sum(1 for p in range(info.num_passes) if info.pass_kernel[p])
     # radix 32 needs k >= 4 (a register group spans at most k + 1 qubits)
     assert (checked > 0) == (k is None or k >= 4)
+
+
+def test_split_exchange_lds():
+    # complex64 two-group passes exchange real and imaginary parts in turn
+    # through half the tile; complex128 ones use the whole tile
+    for dtype, es, half in (("c64", 8, True), ("c128", 16, False)):
+        lay = Q.layout_flags(dtype)
+        info = Q.describe(27, dtype=dtype)
+        for p in range(info.num_passes):
+            d, launch = E.get_pass(27, -1, "unitary", lay, None, p)
+            assert info.pass_kernel[p]
+            full = (1 << d.T) * es
+            assert launch[1] == (full // 2 if half else full)
