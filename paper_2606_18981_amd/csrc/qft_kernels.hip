@@ -269,30 +269,32 @@ __device__ __forceinline__ void exchange(cplx<Real> (&v)[1 << RB], cplx<Real> *l
 // The same exchange in two halves: real parts, then imaginary parts, through
 // an LDS area of 2^T scalars (half the tile).  Four barriers instead of two,
 // but half the LDS per workgroup, so three 2^13-element complex64 workgroups
-// fit a CU's 160 KiB instead of two.
+// fit a CU's 160 KiB instead of two.  Slots are the tile positions
+// themselves: with 4-byte slots the XOR fold measured slower (2.64-2.67 ms
+// against 2.61 ms at 2^28).
 template <typename Real, int RB>
 __device__ __forceinline__ void exchange_split(cplx<Real> (&v)[1 << RB], cplx<Real> *lds_c,
                                                const GroupMap &P, const GroupMap &G,
                                                uint32_t tid, int TR) {
   constexpr int R = 1 << RB;
   Real *lds = reinterpret_cast<Real *>(lds_c);
-  const uint32_t sp = lds_swizzle<Real>(deposit_tid(tid, P.thr_w, TR));
-  const uint32_t sg = lds_swizzle<Real>(deposit_tid(tid, G.thr_w, TR));
+  const uint32_t sp = deposit_tid(tid, P.thr_w, TR);
+  const uint32_t sg = deposit_tid(tid, G.thr_w, TR);
 #pragma unroll
   for (int rho = 0; rho < R; ++rho)
-    lds[sp ^ lds_swizzle<Real>(deposit_reg<RB>(rho, P.reg_w))] = v[rho].x;
+    lds[sp | deposit_reg<RB>(rho, P.reg_w)] = v[rho].x;
   __syncthreads();
 #pragma unroll
   for (int rho = 0; rho < R; ++rho)
-    v[rho].x = lds[sg ^ lds_swizzle<Real>(deposit_reg<RB>(rho, G.reg_w))];
+    v[rho].x = lds[sg | deposit_reg<RB>(rho, G.reg_w)];
   __syncthreads();
 #pragma unroll
   for (int rho = 0; rho < R; ++rho)
-    lds[sp ^ lds_swizzle<Real>(deposit_reg<RB>(rho, P.reg_w))] = v[rho].y;
+    lds[sp | deposit_reg<RB>(rho, P.reg_w)] = v[rho].y;
   __syncthreads();
 #pragma unroll
   for (int rho = 0; rho < R; ++rho)
-    v[rho].y = lds[sg ^ lds_swizzle<Real>(deposit_reg<RB>(rho, G.reg_w))];
+    v[rho].y = lds[sg | deposit_reg<RB>(rho, G.reg_w)];
   __syncthreads();
 }
 
