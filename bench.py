@@ -372,6 +372,7 @@ def main():
     if not args.no_extras:
         print("[bench] aqft sweep", file=sys.stderr, flush=True)
         out["aqft_n28_c64"] = bench_aqft(torch, Q, 28, "c64", [-1, 6, 10, 14, 18], 10)
+        out["aqft_n30_c64"] = bench_aqft(torch, Q, 30, "c64", [-1, 6, 10, 14, 18], 10)
         print("[bench] cutoff by accuracy budget", file=sys.stderr, flush=True)
         out["aqft_budget_n28_c64"] = bench_budget(torch, Q, 28, [1e-2, 1e-3, 1e-4], 10)
         print("[bench] complex128", file=sys.stderr, flush=True)
