@@ -11,6 +11,13 @@
  * LDS): a pass loads a tile of the state into LDS, applies its gates there
  * in circuit order, and stores the tile.
  *
+ * A pass needs in its tile only the qubits whose amplitudes its gates mix:
+ * targets of non-diagonal gates and both qubits of a SWAP.  Controls and
+ * diagonal gates (one- or two-qubit, u01 = u10 = 0) only select or scale
+ * amplitudes; the value of any qubit is known for every element of a tile
+ * from its global index, so they need no tile qubit.  Runs of consecutive
+ * diagonal gates (which commute) are applied as one scaling per element.
+ *
  * Gates (all matrices in FP64, row-major, complex as (re, im) pairs):
  *  - one-qubit U on q: |0>,|1> components of every pair (i, i + 2^q) with
  *    bit q of i clear are mapped by U;
@@ -45,10 +52,12 @@ int qft_circuit_add_swap(qft_circuit_t *c, int a, int b);
 
 /* Group the gates into passes and upload their matrices (device memory of
  * the current device, owned by the circuit).  tile_qubits: the number of
- * qubits a pass may touch (its tile holds 2^tile_log2 amplitudes, the rest
- * of the tile bits being the lowest untouched qubits, for coalescing);
- * 0 = default (10).  The grouping is greedy over the gate list: a pass takes
- * gates in order until the next gate would bring in one qubit too many.     */
+ * qubits a pass may mix (see above), at most the tile size T = min(n, 13)
+ * for complex64 and min(n, 12) for complex128; the other tile bits are the
+ * lowest qubits the pass does not mix, so that rows of the tile are
+ * contiguous.  0 = default: T - 4 (complex64) or T - 3 (complex128), rows of
+ * 128 bytes.  The grouping is greedy over the gate list: a pass takes gates
+ * in order until the next gate would bring in one qubit too many.           */
 int qft_circuit_compile(qft_circuit_t *c, int tile_qubits);
 
 /* Host only (no device use): the grouping qft_circuit_compile would make.

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <new>
 #include <string>
 #include <vector>
@@ -24,7 +25,12 @@ using namespace qft;
 namespace {
 
 constexpr int kCircThreads = 256;
-constexpr int kMaxCircTile = 12;  // 2^12 complex64 / 2^11 complex128 = 32 KiB of LDS
+constexpr int kMaxTileC64 = 13;   // 2^13 complex64 = 64 KiB of LDS
+constexpr int kMaxTileC128 = 12;  // 2^12 complex128 = 64 KiB of LDS
+constexpr int kLowBits = 6;       // tile positions [0, 6) index the low tables
+constexpr int kMaxHighBits = kMaxTileC64 - kLowBits;
+constexpr int32_t kNoControl = 0x7fffffff;
+constexpr int kChunk = 8;  // elements a thread scales per read of a diagonal record
 
 template <typename Real>
 struct alignas(2 * sizeof(Real)) c2 {
@@ -39,20 +45,42 @@ struct GateRec {
   double u[8];     // row-major 2x2, (re, im) pairs
 };
 
-// A gate as a pass applies it: tile-bit positions, matrix in the dtype.
+// What a pass does, in order.  A qubit operand is encoded as its tile
+// position p >= 0, or as -1 - g for a global bit g outside the tile (whose
+// value is the same for every element of a tile).
+enum OpKind : int32_t { kOpPair = 0, kOpSwap = 1, kOpDiag = 2 };
+
 template <typename Real>
-struct DevGate {
-  int32_t kind, la, lb, pad;
-  c2<Real> u[4];
+struct DevOp {
+  int32_t kind;
+  int32_t a;       // pair: target tile position; swap: tile position; diag: first record
+  int32_t b;       // pair: encoded control or kNoControl; swap: tile position;
+                   // diag: records of the low table
+  int32_t c;       // diag: records of the high table
+  int32_t d;       // diag: records evaluated per element
+  int32_t hx;      // diag: high tile position that extends the low table, or -1
+  int32_t pad[2];
+  c2<Real> u[4];   // pair: row-major 2x2
+};
+
+// A diagonal gate on qubits (q1, q0): the amplitude is scaled by
+// D[2 bit(q1) + bit(q0)] (q1 == q0 for a one-qubit diagonal).
+template <typename Real>
+struct DevDiag {
+  int32_t q1, q0;
+  int32_t pad[2];
+  c2<Real> D[4];
 };
 
 struct CircPass {
-  int32_t n, T, nfree, ngates;
+  int32_t n, T, TL, nfree;
+  int32_t nops, pad;
   uint32_t gpos_w[4];   // global bit of tile position q (packed 4 per word)
   uint32_t free_w[8];   // global bits of the non-tile positions, ascending
   uint32_t ntiles;
   int32_t xcd_remap;
-  const void *gates;    // DevGate<Real>[ngates]
+  const void *ops;      // DevOp<Real>[nops]
+  const void *recs;     // DevDiag<Real>[] of this pass
 };
 
 __device__ __forceinline__ uint32_t insert_zero(uint32_t x, int pos) {
@@ -70,13 +98,65 @@ __device__ __forceinline__ c2<Real> cadd2(c2<Real> a, c2<Real> b) {
   return {a.x + b.x, a.y + b.y};
 }
 
-// One pass: load the tile into LDS (tile element e = sum of bit q of e at
-// global bit gpos[q]), apply the pass's gates in order, store the tile.
+__device__ __forceinline__ uint32_t qbit(int32_t q, uint32_t e, uint64_t base) {
+  return q >= 0 ? (e >> q) & 1u : (uint32_t)(base >> (-1 - q)) & 1u;
+}
+
+template <typename Real>
+__device__ __forceinline__ c2<Real> diag_factor(const DevDiag<Real> &r, uint32_t e,
+                                                uint64_t base) {
+  const uint32_t b1 = qbit(r.q1, e, base), b0 = qbit(r.q0, e, base);
+  const c2<Real> lo = b0 ? r.D[1] : r.D[0];
+  const c2<Real> hi = b0 ? r.D[3] : r.D[2];
+  return b1 ? hi : lo;
+}
+
+// 2x2 matrix u on the pairs (e0, e0 + 2^t) of the tile; with a control in
+// the tile (cq >= 0) only the pairs whose control bit is set.
+template <typename Real>
+__device__ __forceinline__ void apply_pair(c2<Real> *lds, uint32_t TE, int t, int cq,
+                                           c2<Real> u0, c2<Real> u1, c2<Real> u2, c2<Real> u3,
+                                           uint32_t tid) {
+  using C = c2<Real>;
+  if (cq < 0) {
+    for (uint32_t p = tid; p < (TE >> 1); p += kCircThreads) {
+      const uint32_t e0 = insert_zero(p, t), e1 = e0 | (1u << t);
+      const C a = lds[e0], b = lds[e1];
+      lds[e0] = cadd2(cmul2(u0, a), cmul2(u1, b));
+      lds[e1] = cadd2(cmul2(u2, a), cmul2(u3, b));
+    }
+  } else {
+    const int lo = cq < t ? cq : t, hi = cq < t ? t : cq;
+    for (uint32_t p = tid; p < (TE >> 2); p += kCircThreads) {
+      const uint32_t e0 = insert_zero(insert_zero(p, lo), hi) | (1u << cq);
+      const uint32_t e1 = e0 | (1u << t);
+      const C a = lds[e0], b = lds[e1];
+      lds[e0] = cadd2(cmul2(u0, a), cmul2(u1, b));
+      lds[e1] = cadd2(cmul2(u2, a), cmul2(u3, b));
+    }
+  }
+}
+
+// One pass: load the tile into LDS (element e = sum over tile positions q of
+// bit q of e at global bit gpos[q], plus the tile's free bits), apply the
+// pass's operations in order, store the tile.
+//  - pair: a 2x2 matrix on a tile qubit, optionally controlled by a tile
+//    qubit or by a global bit (then the whole tile takes it or skips it);
+//  - swap of two tile qubits;
+//  - a run of diagonal gates (they commute): the factors that depend only on
+//    global bits and on the low tile positions (plus at most one chosen high
+//    position hx) are multiplied into a low table, those that depend only on
+//    global bits and high positions into a high table, once per tile; each
+//    element takes one entry of each table times its remaining gates, which
+//    straddle both halves.
 template <typename Real>
 __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d, c2<Real> *psi) {
   using C = c2<Real>;
   extern __shared__ __align__(16) unsigned char circ_smem[];
   C *lds = reinterpret_cast<C *>(circ_smem);
+  __shared__ C flo[2 << kLowBits], fhi[1 << kMaxHighBits];
+  __shared__ uint64_t alo[1 << kLowBits], ahi[1 << kMaxHighBits];
+  const uint32_t tid = threadIdx.x;
   uint32_t tile = blockIdx.x;
   if (d.xcd_remap) {
     const uint32_t per = gridDim.x >> 3;
@@ -84,46 +164,95 @@ __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d,
   }
   uint64_t base = 0;
   for (int b = 0; b < d.nfree; ++b) base |= (uint64_t)((tile >> b) & 1u) << pos_get(d.free_w, b);
-  const uint32_t TE = 1u << d.T;
-  auto addr = [&](uint32_t e) {
+  const int TL = d.TL, TH = d.T - d.TL;
+  const uint32_t mlo = (1u << TL) - 1u;
+  // element e of the tile is psi[alo[e & mlo] | ahi[e >> TL]]
+  if (tid < 64u) {
+    if (tid <= mlo) {
+      uint64_t g = 0;
+      for (int q = 0; q < TL; ++q) g |= (uint64_t)((tid >> q) & 1u) << pos_get(d.gpos_w, q);
+      alo[tid] = g;
+    }
+  } else if (tid - 64u < (1u << TH)) {
+    const uint32_t j = tid - 64u;
     uint64_t g = base;
-    for (int q = 0; q < d.T; ++q) g |= (uint64_t)((e >> q) & 1u) << pos_get(d.gpos_w, q);
-    return g;
-  };
-  for (uint32_t e = threadIdx.x; e < TE; e += kCircThreads) lds[e] = psi[addr(e)];
+    for (int q = 0; q < TH; ++q) g |= (uint64_t)((j >> q) & 1u) << pos_get(d.gpos_w, TL + q);
+    ahi[j] = g;
+  }
   __syncthreads();
-  const DevGate<Real> *G = (const DevGate<Real> *)d.gates;
-  for (int gi = 0; gi < d.ngates; ++gi) {
-    const DevGate<Real> g = G[gi];
-    if (g.kind == kOne) {
-      for (uint32_t p = threadIdx.x; p < (TE >> 1); p += kCircThreads) {
-        const uint32_t e0 = insert_zero(p, g.la), e1 = e0 | (1u << g.la);
-        const C a = lds[e0], b = lds[e1];
-        lds[e0] = cadd2(cmul2(g.u[0], a), cmul2(g.u[1], b));
-        lds[e1] = cadd2(cmul2(g.u[2], a), cmul2(g.u[3], b));
-      }
-    } else if (g.kind == kControlled) {
-      const int lo = g.la < g.lb ? g.la : g.lb, hi = g.la < g.lb ? g.lb : g.la;
-      for (uint32_t p = threadIdx.x; p < (TE >> 2); p += kCircThreads) {
-        const uint32_t e0 = insert_zero(insert_zero(p, lo), hi) | (1u << g.la);
-        const uint32_t e1 = e0 | (1u << g.lb);
-        const C a = lds[e0], b = lds[e1];
-        lds[e0] = cadd2(cmul2(g.u[0], a), cmul2(g.u[1], b));
-        lds[e1] = cadd2(cmul2(g.u[2], a), cmul2(g.u[3], b));
+  const uint32_t TE = 1u << d.T;
+  for (uint32_t e = tid; e < TE; e += kCircThreads) lds[e] = psi[alo[e & mlo] | ahi[e >> TL]];
+  __syncthreads();
+  const DevOp<Real> *ops = (const DevOp<Real> *)d.ops;
+  const DevDiag<Real> *recs = (const DevDiag<Real> *)d.recs;
+  for (int oi = 0; oi < d.nops; ++oi) {
+    const DevOp<Real> &op = ops[oi];
+    const int kind = op.kind;
+    if (kind == kOpPair) {
+      const C u0 = op.u[0], u1 = op.u[1], u2 = op.u[2], u3 = op.u[3];
+      const int cq = op.b;
+      // a global control is the same for the whole tile: take or skip
+      const bool take = cq == kNoControl || cq >= 0 || ((base >> (-1 - cq)) & 1u);
+      if (take) apply_pair<Real>(lds, TE, op.a, cq == kNoControl ? -1 : cq, u0, u1, u2, u3, tid);
+    } else if (kind == kOpSwap) {
+      const int a = op.a, b = op.b;
+      const int lo = a < b ? a : b, hi = a < b ? b : a;
+      for (uint32_t p = tid; p < (TE >> 2); p += kCircThreads) {
+        const uint32_t z = insert_zero(insert_zero(p, lo), hi);
+        const uint32_t e0 = z | (1u << a), e1 = z | (1u << b);
+        const C t = lds[e0];
+        lds[e0] = lds[e1];
+        lds[e1] = t;
       }
     } else {
-      const int lo = g.la < g.lb ? g.la : g.lb, hi = g.la < g.lb ? g.lb : g.la;
-      for (uint32_t p = threadIdx.x; p < (TE >> 2); p += kCircThreads) {
-        const uint32_t z = insert_zero(insert_zero(p, lo), hi);
-        const uint32_t e0 = z | (1u << g.la), e1 = z | (1u << g.lb);
-        const C a = lds[e0];
-        lds[e0] = lds[e1];
-        lds[e1] = a;
+      const int r0 = op.a, r1 = r0 + op.b, r2 = r1 + op.c, r3 = r2 + op.d;
+      // low table: index bits [0, TL) are the low tile positions, bit TL
+      // (when hx >= 0) is tile position hx
+      const int hx = op.hx;
+      if (tid < 128u) {
+        if (tid <= mlo || (hx >= 0 && tid <= 2u * mlo + 1u)) {
+          const uint32_t e = (tid & mlo) | (hx >= 0 ? ((tid >> TL) & 1u) << hx : 0u);
+          C f{(Real)1, (Real)0};
+#pragma unroll 4
+          for (int r = r0; r < r1; ++r) f = cmul2(f, diag_factor(recs[r], e, base));
+          flo[tid] = f;
+        }
+      } else if (tid - 128u < (1u << TH)) {
+        const uint32_t j = tid - 128u;
+        C f{(Real)1, (Real)0};
+#pragma unroll 4
+        for (int r = r1; r < r2; ++r) f = cmul2(f, diag_factor(recs[r], j << TL, base));
+        fhi[j] = f;
+      }
+      __syncthreads();
+      const int hsh = hx >= 0 ? hx : 0;
+      const uint32_t hmask = hx >= 0 ? 1u : 0u;
+      // each thread scales its elements e = tid + 256 i, kChunk at a time:
+      // a record is read once per chunk and applied to all of its elements
+      for (uint32_t e0 = tid; e0 < TE; e0 += kChunk * kCircThreads) {
+        C f[kChunk];
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) {
+          const uint32_t e = e0 + i * kCircThreads;
+          const uint32_t il = (e & mlo) | (((e >> hsh) & hmask) << TL);
+          f[i] = e < TE ? cmul2(flo[il], fhi[e >> TL]) : C{(Real)1, (Real)0};
+        }
+        for (int r = r2; r < r3; ++r) {
+          const DevDiag<Real> rec = recs[r];
+#pragma unroll
+          for (int i = 0; i < kChunk; ++i)
+            f[i] = cmul2(f[i], diag_factor(rec, e0 + i * kCircThreads, base));
+        }
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) {
+          const uint32_t e = e0 + i * kCircThreads;
+          if (e < TE) lds[e] = cmul2(f[i], lds[e]);
+        }
       }
     }
     __syncthreads();
   }
-  for (uint32_t e = threadIdx.x; e < TE; e += kCircThreads) psi[addr(e)] = lds[e];
+  for (uint32_t e = tid; e < TE; e += kCircThreads) psi[alo[e & mlo] | ahi[e >> TL]] = lds[e];
 }
 
 }  // namespace
@@ -163,42 +292,177 @@ int add_gate(qft_circuit_s *c, const GateRec &g) {
   return QFT_OK;
 }
 
-std::vector<int> gate_qubits(const GateRec &g) {
-  if (g.kind == kOne) return {g.a};
-  return {g.a, g.b};
+bool is_diagonal(const GateRec &g) {
+  return g.kind != kSwap && g.u[2] == 0.0 && g.u[3] == 0.0 && g.u[4] == 0.0 && g.u[5] == 0.0;
+}
+
+// The qubits a gate needs among the tile bits of its pass: the amplitudes it
+// mixes.  A control, or any qubit of a diagonal gate, only selects or scales
+// amplitudes, and its bit is known for every element from its global index.
+std::vector<int> tile_needs(const GateRec &g) {
+  if (g.kind == kSwap) return {g.a, g.b};
+  if (is_diagonal(g)) return {};
+  return {g.kind == kOne ? g.a : g.b};
+}
+
+int default_tile_bits(const qft_circuit_s *c) {
+  return std::min(c->n, c->c128 ? kMaxTileC128 : kMaxTileC64);
+}
+
+// Device operations and diagonal records of one pass (host image).
+template <typename Real>
+struct PassImage {
+  std::vector<DevOp<Real>> ops;
+  std::vector<DevDiag<Real>> recs;
+};
+
+template <typename Real>
+c2<Real> cval(const double *u, int i) {
+  return c2<Real>{(Real)u[2 * i], (Real)u[2 * i + 1]};
 }
 
 template <typename Real>
-void pack_gate(const GateRec &g, const std::vector<int> &tpos, DevGate<Real> &o) {
-  o.kind = g.kind;
-  o.la = tpos[g.a];
-  o.lb = g.kind == kOne ? 0 : tpos[g.b];
-  o.pad = 0;
-  for (int i = 0; i < 4; ++i) o.u[i] = c2<Real>{(Real)g.u[2 * i], (Real)g.u[2 * i + 1]};
+void build_pass_image(const qft_circuit_s *c, int g0, int g1, const std::vector<int> &tpos,
+                      int TL, PassImage<Real> &img) {
+  auto enc = [&](int q) { return tpos[q] >= 0 ? tpos[q] : -1 - q; };
+  std::vector<DevDiag<Real>> run;
+  // Split a run of diagonal records over the low table (low positions,
+  // global bits and the high position hx), the high table (high positions
+  // and global bits) and the per-element list.  hx is the high position that
+  // the most records pairing a low with a high position share (for the QFT,
+  // the target of the run).
+  auto flush = [&]() {
+    if (run.empty()) return;
+    auto is_low = [&](int32_t q) { return q >= 0 && q < TL; };
+    auto is_high = [&](int32_t q) { return q >= TL; };
+    std::vector<int> votes(64, 0);
+    for (const DevDiag<Real> &r : run) {
+      if (is_low(r.q1) && is_high(r.q0)) ++votes[r.q0];
+      if (is_low(r.q0) && is_high(r.q1)) ++votes[r.q1];
+    }
+    int hx = -1;
+    for (int q = 0; q < 64; ++q)
+      if (votes[q] > 0 && (hx < 0 || votes[q] > votes[hx])) hx = q;
+    std::vector<DevDiag<Real>> lo, hi, cross;
+    for (const DevDiag<Real> &r : run) {
+      const bool any_low = is_low(r.q1) || is_low(r.q0);
+      const bool other_high = (is_high(r.q1) && r.q1 != hx) || (is_high(r.q0) && r.q0 != hx);
+      if (!any_low) hi.push_back(r);
+      else if (!other_high) lo.push_back(r);
+      else cross.push_back(r);
+    }
+    DevOp<Real> op;
+    memset(&op, 0, sizeof(op));
+    op.kind = kOpDiag;
+    op.a = (int32_t)img.recs.size();
+    op.b = (int32_t)lo.size();
+    op.c = (int32_t)hi.size();
+    op.d = (int32_t)cross.size();
+    op.hx = hx;
+    img.recs.insert(img.recs.end(), lo.begin(), lo.end());
+    img.recs.insert(img.recs.end(), hi.begin(), hi.end());
+    img.recs.insert(img.recs.end(), cross.begin(), cross.end());
+    img.ops.push_back(op);
+    run.clear();
+  };
+  const c2<Real> one{(Real)1, (Real)0};
+  for (int i = g0; i < g1; ++i) {
+    const GateRec &g = c->gates[i];
+    if (is_diagonal(g)) {
+      DevDiag<Real> r;
+      memset(&r, 0, sizeof(r));
+      if (g.kind == kOne) {
+        r.q1 = r.q0 = enc(g.a);
+        r.D[0] = cval<Real>(g.u, 0);
+        r.D[1] = r.D[2] = one;  // unreachable: both bits are the same qubit
+        r.D[3] = cval<Real>(g.u, 3);
+      } else {
+        r.q1 = enc(g.a);  // control
+        r.q0 = enc(g.b);  // target
+        r.D[0] = r.D[1] = one;
+        r.D[2] = cval<Real>(g.u, 0);
+        r.D[3] = cval<Real>(g.u, 3);
+      }
+      run.push_back(r);
+      continue;
+    }
+    flush();
+    DevOp<Real> op;
+    memset(&op, 0, sizeof(op));
+    if (g.kind == kSwap) {
+      op.kind = kOpSwap;
+      op.a = tpos[g.a];
+      op.b = tpos[g.b];
+    } else {
+      op.kind = kOpPair;
+      op.a = tpos[g.kind == kOne ? g.a : g.b];
+      op.b = g.kind == kOne ? kNoControl : enc(g.a);
+      for (int j = 0; j < 4; ++j) op.u[j] = cval<Real>(g.u, j);
+    }
+    img.ops.push_back(op);
+  }
+  flush();
+}
+
+template <typename Real>
+int upload_passes(qft_circuit_s *c, std::vector<PassImage<Real>> &imgs) {
+  size_t bytes = 0;
+  std::vector<size_t> off_ops(imgs.size()), off_recs(imgs.size());
+  for (size_t r = 0; r < imgs.size(); ++r) {
+    off_ops[r] = bytes;
+    bytes += imgs[r].ops.size() * sizeof(DevOp<Real>);
+    off_recs[r] = bytes;
+    bytes += imgs[r].recs.size() * sizeof(DevDiag<Real>);
+  }
+  std::vector<unsigned char> host(bytes);
+  for (size_t r = 0; r < imgs.size(); ++r) {
+    if (!imgs[r].ops.empty())
+      memcpy(host.data() + off_ops[r], imgs[r].ops.data(),
+             imgs[r].ops.size() * sizeof(DevOp<Real>));
+    if (!imgs[r].recs.empty())
+      memcpy(host.data() + off_recs[r], imgs[r].recs.data(),
+             imgs[r].recs.size() * sizeof(DevDiag<Real>));
+  }
+  if (bytes) {
+    hipError_t e = hipMalloc(&c->d_gates, bytes);
+    if (e != hipSuccess) {
+      c->d_gates = nullptr;
+      return hip_error(e, "circuit gate upload");
+    }
+    e = hipMemcpy(c->d_gates, host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, "circuit gate upload");
+  }
+  for (size_t r = 0; r < imgs.size(); ++r) {
+    c->passes[r].ops = (unsigned char *)c->d_gates + off_ops[r];
+    c->passes[r].recs = (unsigned char *)c->d_gates + off_recs[r];
+  }
+  return QFT_OK;
 }
 
 int compile(qft_circuit_s *c, int tile_qubits, bool upload) {
   drop_compiled(c);
   const int n = c->n;
-  const int T = std::min(n, c->c128 ? kMaxCircTile - 1 : kMaxCircTile);
-  int B = tile_qubits > 0 ? tile_qubits : 10;
+  const int T = default_tile_bits(c);
+  // leave about 128 bytes of contiguous elements per tile row by default
+  int B = tile_qubits > 0 ? tile_qubits : T - (c->c128 ? 3 : 4);
   B = std::max(2, std::min(B, T));
-  c->tile_qubits = B;
-  // greedy runs of gates whose qubits fit in B
+  c->tile_qubits = tile_qubits;
+  // greedy runs of gates whose tile needs fit in B qubits
   std::vector<std::pair<int, int>> runs;
   std::vector<std::vector<int>> sets;
   {
     std::vector<int> S;
     int start = 0;
     for (int i = 0; i < (int)c->gates.size(); ++i) {
+      const std::vector<int> need = tile_needs(c->gates[i]);
       std::vector<int> U = S;
-      for (int q : gate_qubits(c->gates[i]))
+      for (int q : need)
         if (std::find(U.begin(), U.end(), q) == U.end()) U.push_back(q);
       if ((int)U.size() > B) {
         runs.push_back({start, i});
         sets.push_back(S);
         start = i;
-        U = gate_qubits(c->gates[i]);
+        U = need;
         std::sort(U.begin(), U.end());
         U.erase(std::unique(U.begin(), U.end()), U.end());
       }
@@ -209,13 +473,12 @@ int compile(qft_circuit_s *c, int tile_qubits, bool upload) {
       sets.push_back(S);
     }
   }
-  const size_t gsz = c->c128 ? sizeof(DevGate<double>) : sizeof(DevGate<float>);
-  std::vector<unsigned char> host(c->gates.size() * gsz);
+  std::vector<PassImage<float>> img32;
+  std::vector<PassImage<double>> img64;
   for (size_t r = 0; r < runs.size(); ++r) {
-    std::vector<int> S = sets[r];
-    // tile: the run's qubits plus the lowest other qubits, up to T bits,
-    // ordered by global bit so that low tile bits give contiguous runs
-    std::vector<int> tile = S;
+    // tile: the run's needed qubits plus the lowest other qubits, up to T
+    // bits, ordered by global bit so that low tile bits give contiguous rows
+    std::vector<int> tile = sets[r];
     for (int q = 0; q < n && (int)tile.size() < T; ++q)
       if (std::find(tile.begin(), tile.end(), q) == tile.end()) tile.push_back(q);
     std::sort(tile.begin(), tile.end());
@@ -224,6 +487,7 @@ int compile(qft_circuit_s *c, int tile_qubits, bool upload) {
     memset(&p, 0, sizeof(p));
     p.n = n;
     p.T = (int)tile.size();
+    p.TL = std::min(p.T, kLowBits);
     for (int q = 0; q < p.T; ++q) {
       pos_set(p.gpos_w, q, (uint32_t)tile[q]);
       tpos[tile[q]] = q;
@@ -234,29 +498,38 @@ int compile(qft_circuit_s *c, int tile_qubits, bool upload) {
     p.nfree = nf;
     p.ntiles = 1u << nf;
     p.xcd_remap = (p.ntiles >= 8 && p.ntiles % 8 == 0) ? 1 : 0;
-    p.ngates = runs[r].second - runs[r].first;
-    for (int i = runs[r].first; i < runs[r].second; ++i) {
-      unsigned char *dst = host.data() + (size_t)i * gsz;
-      if (c->c128) pack_gate<double>(c->gates[i], tpos, *(DevGate<double> *)dst);
-      else pack_gate<float>(c->gates[i], tpos, *(DevGate<float> *)dst);
+    if (c->c128) {
+      img64.emplace_back();
+      build_pass_image<double>(c, runs[r].first, runs[r].second, tpos, p.TL, img64.back());
+      p.nops = (int)img64.back().ops.size();
+    } else {
+      img32.emplace_back();
+      build_pass_image<float>(c, runs[r].first, runs[r].second, tpos, p.TL, img32.back());
+      p.nops = (int)img32.back().ops.size();
     }
     c->passes.push_back(p);
     c->gate_begin.push_back(runs[r].first);
   }
   if (!upload) return QFT_OK;  // host grouping only (describe)
-  if (!host.empty()) {
-    hipError_t e = hipMalloc(&c->d_gates, host.size());
-    if (e != hipSuccess) {
-      c->d_gates = nullptr;
-      return hip_error(e, "circuit gate upload");
-    }
-    e = hipMemcpy(c->d_gates, host.data(), host.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_error(e, "circuit gate upload");
-  }
-  for (size_t r = 0; r < c->passes.size(); ++r)
-    c->passes[r].gates = (unsigned char *)c->d_gates + (size_t)c->gate_begin[r] * gsz;
+  const int rc = c->c128 ? upload_passes<double>(c, img64) : upload_passes<float>(c, img32);
+  if (rc != QFT_OK) return rc;
   c->compiled = true;
   return QFT_OK;
+}
+
+template <typename Real>
+hipError_t launch_circuit_pass(const CircPass &p, void *dev_ptr, hipStream_t s) {
+  static std::atomic<int> raised{0};
+  if (!raised.load(std::memory_order_acquire)) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_circuit_pass<Real>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    if (e != hipSuccess) return e;
+    raised.store(1, std::memory_order_release);
+  }
+  const size_t lds = ((size_t)1 << p.T) * sizeof(c2<Real>);
+  hipLaunchKernelGGL(k_circuit_pass<Real>, dim3(p.ntiles), dim3(kCircThreads), lds, s, p,
+                     (c2<Real> *)dev_ptr);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -336,7 +609,9 @@ int qft_circuit_describe(qft_circuit_t *c, int tile_qubits, int *gate_begin, int
   clear_error();
   if (!c) return set_error(QFT_ERR_INVALID, "NULL circuit");
   if (tile_qubits < 0) return set_error(QFT_ERR_INVALID, "tile_qubits < 0");
+  const int keep = c->tile_qubits;
   int rc = compile(c, tile_qubits, false);
+  c->tile_qubits = keep;
   if (rc != QFT_OK) return rc;
   const int np = (int)c->passes.size();
   for (int i = 0; i < np && i < max_passes; ++i) {
@@ -370,14 +645,8 @@ int qft_circuit_execute(qft_circuit_t *c, void *dev_ptr, qft_stream_t stream) {
   }
   hipStream_t s = (hipStream_t)stream;
   for (const CircPass &p : c->passes) {
-    const size_t lds = ((size_t)1 << p.T) * (c->c128 ? 16 : 8);
-    if (c->c128)
-      hipLaunchKernelGGL(k_circuit_pass<double>, dim3(p.ntiles), dim3(kCircThreads), lds, s, p,
-                         (c2<double> *)dev_ptr);
-    else
-      hipLaunchKernelGGL(k_circuit_pass<float>, dim3(p.ntiles), dim3(kCircThreads), lds, s, p,
-                         (c2<float> *)dev_ptr);
-    hipError_t e = hipGetLastError();
+    hipError_t e = c->c128 ? launch_circuit_pass<double>(p, dev_ptr, s)
+                           : launch_circuit_pass<float>(p, dev_ptr, s);
     if (e != hipSuccess) return hip_error(e, "circuit pass launch");
   }
   return QFT_OK;

@@ -71,6 +71,64 @@ def test_random_circuits(env, dtype, n, count, B):
     assert O.rel_l2(y, O.apply_gates(x, gates)) <= TOL[dtype]
 
 
+def diagonal(rng):
+    """A diagonal 2x2 with entries of modulus near 1 (not unitary)."""
+    return np.diag(rng.uniform(0.9, 1.1, 2) * np.exp(1j * rng.uniform(0, 2 * np.pi, 2)))
+
+
+def mixed_gates(n, count, seed):
+    """Non-diagonal and diagonal one-qubit gates, controlled gates of both
+    kinds and swaps, on qubits anywhere in the register."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        kind = rng.integers(0, 5) if n > 1 else rng.integers(0, 2)
+        if kind == 0:
+            out.append(("U", int(rng.integers(0, n)), unitary(rng)))
+        elif kind == 1:
+            out.append(("U", int(rng.integers(0, n)), diagonal(rng)))
+        else:
+            a, b = rng.choice(n, 2, replace=False)
+            if kind == 2:
+                out.append(("CU", int(a), int(b), unitary(rng)))
+            elif kind == 3:
+                out.append(("CU", int(a), int(b), diagonal(rng)))
+            else:
+                out.append(("SWAP", int(a), int(b)))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("n,count,B", [(1, 6, 0), (4, 60, 0), (7, 80, 3), (13, 200, 0),
+                                       (14, 200, 4), (17, 300, 0), (21, 250, 9)])
+def test_mixed_diagonal_circuits(env, dtype, n, count, B):
+    """Diagonal runs split over the low and high factor tables and the
+    per-element list, controls inside and outside the tile."""
+    torch, Q = env
+    print(f"[gpu] mixed circuit n={n} gates={count} B={B} {dtype}", flush=True)
+    gates = mixed_gates(n, count, 9300 + n)
+    x = I.gaussian(n, 9400 + n)
+    y, info = run(torch, Q, n, gates, x, dtype, B)
+    assert info["gates"] == len(gates)
+    assert O.rel_l2(y, O.apply_gates(x, gates)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_diagonal_only_circuit_is_one_pass(env, dtype):
+    torch, Q = env
+    n = 20
+    rng = np.random.default_rng(9500)
+    gates = []
+    for q in range(n):
+        gates.append(("U", q, diagonal(rng)))
+        gates.append(("CU", q, (q + 1 + int(rng.integers(0, n - 1))) % n, diagonal(rng)))
+    gates = [g for g in gates if g[0] == "U" or g[1] != g[2]]
+    x = I.gaussian(n, 9501)
+    y, info = run(torch, Q, n, gates, x, dtype)
+    assert info["passes"] == 1
+    assert O.rel_l2(y, O.apply_gates(x, gates)) <= TOL[dtype]
+
+
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("n,k", [(10, None), (18, 6)])
 def test_qft_as_general_circuit(env, dtype, n, k):
