@@ -134,7 +134,7 @@ def bench_circuit(torch, Q, n=24, steps=5):
             c.add_controlled(t - d, t, np.diag([1.0, np.exp(-2j * np.pi / 2.0 ** (d + 1))]))
     for a in range(n // 2):
         c.add_swap(a, n - 1 - a)
-    c.compile(10)
+    c.compile()
     info = c.info()
     for _ in range(2):
         c.execute(x)

@@ -55,8 +55,8 @@ int qft_circuit_add_swap(qft_circuit_t *c, int a, int b);
  * qubits a pass may mix (see above), at most the tile size T = min(n, 13)
  * for complex64 and min(n, 12) for complex128; the other tile bits are the
  * lowest qubits the pass does not mix, so that rows of the tile are
- * contiguous.  0 = default: T - 4 (complex64) or T - 3 (complex128), rows of
- * 128 bytes.  The grouping is greedy over the gate list: a pass takes gates
+ * contiguous.  0 = default: T - 3 (complex64) or T - 2 (complex128), rows of
+ * 64 bytes.  The grouping is greedy over the gate list: a pass takes gates
  * in order until the next gate would bring in one qubit too many.           */
 int qft_circuit_compile(qft_circuit_t *c, int tile_qubits);
 

@@ -50,17 +50,21 @@ struct GateRec {
 // value is the same for every element of a tile).
 enum OpKind : int32_t { kOpPair = 0, kOpSwap = 1, kOpDiag = 2 };
 
+// A diagonal run (consecutive diagonal gates, which commute) is applied
+// after a pair operation in the same sweep, or on its own (kOpDiag).  Its
+// records are split over a low table (low tile positions, global bits and
+// at most one high position hx), a high table (high positions and global
+// bits) and a list evaluated per element (gates that pair a low position
+// with a high position other than hx).
 template <typename Real>
 struct DevOp {
   int32_t kind;
-  int32_t a;       // pair: target tile position; swap: tile position; diag: first record
-  int32_t b;       // pair: encoded control or kNoControl; swap: tile position;
-                   // diag: records of the low table
-  int32_t c;       // diag: records of the high table
-  int32_t d;       // diag: records evaluated per element
-  int32_t hx;      // diag: high tile position that extends the low table, or -1
-  int32_t pad[2];
-  c2<Real> u[4];   // pair: row-major 2x2
+  int32_t a;                 // pair: target tile position; swap: tile position
+  int32_t b;                 // pair: encoded control or kNoControl; swap: tile position
+  int32_t r0;                // diagonal run: first record
+  int32_t nlo, nhi, ncross;  // its records in the low table, the high table, per element
+  int32_t hx;                // high tile position that extends the low table, or -1
+  c2<Real> u[4];             // pair: row-major 2x2
 };
 
 // A diagonal gate on qubits (q1, q0): the amplitude is scaled by
@@ -111,50 +115,64 @@ __device__ __forceinline__ c2<Real> diag_factor(const DevDiag<Real> &r, uint32_t
   return b1 ? hi : lo;
 }
 
-// 2x2 matrix u on the pairs (e0, e0 + 2^t) of the tile; with a control in
-// the tile (cq >= 0) only the pairs whose control bit is set.
 template <typename Real>
-__device__ __forceinline__ void apply_pair(c2<Real> *lds, uint32_t TE, int t, int cq,
-                                           c2<Real> u0, c2<Real> u1, c2<Real> u2, c2<Real> u3,
-                                           uint32_t tid) {
+struct RunTables {
+  c2<Real> lo[2 << kLowBits];
+  c2<Real> hi[1 << kMaxHighBits];
+};
+
+// The factor tables of a diagonal run for this tile: thread j < 2^(TL+1)
+// computes low entry j, thread 128 + j high entry j.
+template <typename Real>
+__device__ __forceinline__ void build_tables(const DevOp<Real> &op, const DevDiag<Real> *recs,
+                                             RunTables<Real> &tb, int TL, int TH, uint64_t base,
+                                             uint32_t tid) {
   using C = c2<Real>;
-  if (cq < 0) {
-    for (uint32_t p = tid; p < (TE >> 1); p += kCircThreads) {
-      const uint32_t e0 = insert_zero(p, t), e1 = e0 | (1u << t);
-      const C a = lds[e0], b = lds[e1];
-      lds[e0] = cadd2(cmul2(u0, a), cmul2(u1, b));
-      lds[e1] = cadd2(cmul2(u2, a), cmul2(u3, b));
+  const uint32_t mlo = (1u << TL) - 1u;
+  const int hx = op.hx;
+  if (tid < 128u) {
+    if (tid <= mlo || (hx >= 0 && tid <= 2u * mlo + 1u)) {
+      const uint32_t e = (tid & mlo) | (hx >= 0 ? ((tid >> TL) & 1u) << hx : 0u);
+      C f{(Real)1, (Real)0};
+      const int r1 = op.r0 + op.nlo;
+#pragma unroll 4
+      for (int r = op.r0; r < r1; ++r) f = cmul2(f, diag_factor(recs[r], e, base));
+      tb.lo[tid] = f;
     }
-  } else {
-    const int lo = cq < t ? cq : t, hi = cq < t ? t : cq;
-    for (uint32_t p = tid; p < (TE >> 2); p += kCircThreads) {
-      const uint32_t e0 = insert_zero(insert_zero(p, lo), hi) | (1u << cq);
-      const uint32_t e1 = e0 | (1u << t);
-      const C a = lds[e0], b = lds[e1];
-      lds[e0] = cadd2(cmul2(u0, a), cmul2(u1, b));
-      lds[e1] = cadd2(cmul2(u2, a), cmul2(u3, b));
-    }
+  } else if (tid - 128u < (1u << TH)) {
+    const uint32_t j = tid - 128u;
+    C f{(Real)1, (Real)0};
+    const int r1 = op.r0 + op.nlo, r2 = r1 + op.nhi;
+#pragma unroll 4
+    for (int r = r1; r < r2; ++r) f = cmul2(f, diag_factor(recs[r], j << TL, base));
+    tb.hi[j] = f;
   }
+}
+
+// Table part of the run's factor for tile element e.
+template <typename Real>
+__device__ __forceinline__ c2<Real> table_factor(const RunTables<Real> &tb, uint32_t e, int TL,
+                                                 int hsh, uint32_t hmask) {
+  const uint32_t mlo = (1u << TL) - 1u;
+  return cmul2(tb.lo[(e & mlo) | (((e >> hsh) & hmask) << TL)], tb.hi[e >> TL]);
 }
 
 // One pass: load the tile into LDS (element e = sum over tile positions q of
 // bit q of e at global bit gpos[q], plus the tile's free bits), apply the
 // pass's operations in order, store the tile.
 //  - pair: a 2x2 matrix on a tile qubit, optionally controlled by a tile
-//    qubit or by a global bit (then the whole tile takes it or skips it);
+//    qubit or by a global bit (then the whole tile takes it or skips it),
+//    followed in the same sweep by the diagonal run after it, if any;
 //  - swap of two tile qubits;
-//  - a run of diagonal gates (they commute): the factors that depend only on
-//    global bits and on the low tile positions (plus at most one chosen high
-//    position hx) are multiplied into a low table, those that depend only on
-//    global bits and high positions into a high table, once per tile; each
-//    element takes one entry of each table times its remaining gates, which
-//    straddle both halves.
+//  - diagonal run on its own.
+// The tables of operation i + 1's run are built at the end of operation i
+// (two table buffers), so each operation ends with one barrier.
 template <typename Real>
 __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d, c2<Real> *psi) {
   using C = c2<Real>;
   extern __shared__ __align__(16) unsigned char circ_smem[];
   C *lds = reinterpret_cast<C *>(circ_smem);
-  __shared__ C flo[2 << kLowBits], fhi[1 << kMaxHighBits];
+  __shared__ RunTables<Real> tabs[2];
   __shared__ uint64_t alo[1 << kLowBits], ahi[1 << kMaxHighBits];
   const uint32_t tid = threadIdx.x;
   uint32_t tile = blockIdx.x;
@@ -166,6 +184,8 @@ __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d,
   for (int b = 0; b < d.nfree; ++b) base |= (uint64_t)((tile >> b) & 1u) << pos_get(d.free_w, b);
   const int TL = d.TL, TH = d.T - d.TL;
   const uint32_t mlo = (1u << TL) - 1u;
+  const DevOp<Real> *ops = (const DevOp<Real> *)d.ops;
+  const DevDiag<Real> *recs = (const DevDiag<Real> *)d.recs;
   // element e of the tile is psi[alo[e & mlo] | ahi[e >> TL]]
   if (tid < 64u) {
     if (tid <= mlo) {
@@ -180,64 +200,104 @@ __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d,
     ahi[j] = g;
   }
   __syncthreads();
+  if (d.nops > 0) build_tables<Real>(ops[0], recs, tabs[0], TL, TH, base, tid);
   const uint32_t TE = 1u << d.T;
   for (uint32_t e = tid; e < TE; e += kCircThreads) lds[e] = psi[alo[e & mlo] | ahi[e >> TL]];
   __syncthreads();
-  const DevOp<Real> *ops = (const DevOp<Real> *)d.ops;
-  const DevDiag<Real> *recs = (const DevDiag<Real> *)d.recs;
   for (int oi = 0; oi < d.nops; ++oi) {
     const DevOp<Real> &op = ops[oi];
+    const RunTables<Real> &tb = tabs[oi & 1];
     const int kind = op.kind;
+    const bool run = op.nlo + op.nhi + op.ncross > 0;
+    const int hsh = op.hx >= 0 ? op.hx : 0;
+    const uint32_t hmask = op.hx >= 0 ? 1u : 0u;
+    const int rc0 = op.r0 + op.nlo + op.nhi, rc1 = rc0 + op.ncross;
     if (kind == kOpPair) {
       const C u0 = op.u[0], u1 = op.u[1], u2 = op.u[2], u3 = op.u[3];
-      const int cq = op.b;
-      // a global control is the same for the whole tile: take or skip
-      const bool take = cq == kNoControl || cq >= 0 || ((base >> (-1 - cq)) & 1u);
-      if (take) apply_pair<Real>(lds, TE, op.a, cq == kNoControl ? -1 : cq, u0, u1, u2, u3, tid);
+      const int t = op.a, cq = op.b;
+      // a global control is the same for the whole tile
+      const bool tile_take = cq == kNoControl || cq >= 0 || ((base >> (-1 - cq)) & 1u);
+      const int cpos = cq >= 0 && cq != kNoControl ? cq : -1;
+      if (!run) {
+        if (tile_take) {
+          if (cpos < 0) {
+            for (uint32_t p = tid; p < (TE >> 1); p += kCircThreads) {
+              const uint32_t e0 = insert_zero(p, t), e1 = e0 | (1u << t);
+              const C a = lds[e0], b = lds[e1];
+              lds[e0] = cadd2(cmul2(u0, a), cmul2(u1, b));
+              lds[e1] = cadd2(cmul2(u2, a), cmul2(u3, b));
+            }
+          } else {
+            const int lo = cpos < t ? cpos : t, hi = cpos < t ? t : cpos;
+            for (uint32_t p = tid; p < (TE >> 2); p += kCircThreads) {
+              const uint32_t e0 = insert_zero(insert_zero(p, lo), hi) | (1u << cpos);
+              const uint32_t e1 = e0 | (1u << t);
+              const C a = lds[e0], b = lds[e1];
+              lds[e0] = cadd2(cmul2(u0, a), cmul2(u1, b));
+              lds[e1] = cadd2(cmul2(u2, a), cmul2(u3, b));
+            }
+          }
+        }
+      } else {
+        // every pair: the matrix where the control allows it, then the
+        // run's factors; kChunk / 2 pairs per read of a per-element record
+        constexpr int kP = kChunk / 2;
+        for (uint32_t p0 = tid; p0 < (TE >> 1); p0 += kP * kCircThreads) {
+          C a[kP], b[kP], f0[kP], f1[kP];
+#pragma unroll
+          for (int i = 0; i < kP; ++i) {
+            const uint32_t p = p0 + i * kCircThreads;
+            const uint32_t e0 = insert_zero(p, t), e1 = e0 | (1u << t);
+            if (p < (TE >> 1)) {
+              const C x0 = lds[e0], x1 = lds[e1];
+              const bool take = tile_take && (cpos < 0 || ((e0 >> cpos) & 1u));
+              a[i] = take ? cadd2(cmul2(u0, x0), cmul2(u1, x1)) : x0;
+              b[i] = take ? cadd2(cmul2(u2, x0), cmul2(u3, x1)) : x1;
+              f0[i] = table_factor<Real>(tb, e0, TL, hsh, hmask);
+              f1[i] = table_factor<Real>(tb, e1, TL, hsh, hmask);
+            }
+          }
+          for (int r = rc0; r < rc1; ++r) {
+            const DevDiag<Real> rec = recs[r];
+#pragma unroll
+            for (int i = 0; i < kP; ++i) {
+              const uint32_t e0 = insert_zero(p0 + i * kCircThreads, t), e1 = e0 | (1u << t);
+              f0[i] = cmul2(f0[i], diag_factor(rec, e0, base));
+              f1[i] = cmul2(f1[i], diag_factor(rec, e1, base));
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < kP; ++i) {
+            const uint32_t p = p0 + i * kCircThreads;
+            const uint32_t e0 = insert_zero(p, t), e1 = e0 | (1u << t);
+            if (p < (TE >> 1)) {
+              lds[e0] = cmul2(f0[i], a[i]);
+              lds[e1] = cmul2(f1[i], b[i]);
+            }
+          }
+        }
+      }
     } else if (kind == kOpSwap) {
       const int a = op.a, b = op.b;
       const int lo = a < b ? a : b, hi = a < b ? b : a;
       for (uint32_t p = tid; p < (TE >> 2); p += kCircThreads) {
         const uint32_t z = insert_zero(insert_zero(p, lo), hi);
         const uint32_t e0 = z | (1u << a), e1 = z | (1u << b);
-        const C t = lds[e0];
+        const C x = lds[e0];
         lds[e0] = lds[e1];
-        lds[e1] = t;
+        lds[e1] = x;
       }
     } else {
-      const int r0 = op.a, r1 = r0 + op.b, r2 = r1 + op.c, r3 = r2 + op.d;
-      // low table: index bits [0, TL) are the low tile positions, bit TL
-      // (when hx >= 0) is tile position hx
-      const int hx = op.hx;
-      if (tid < 128u) {
-        if (tid <= mlo || (hx >= 0 && tid <= 2u * mlo + 1u)) {
-          const uint32_t e = (tid & mlo) | (hx >= 0 ? ((tid >> TL) & 1u) << hx : 0u);
-          C f{(Real)1, (Real)0};
-#pragma unroll 4
-          for (int r = r0; r < r1; ++r) f = cmul2(f, diag_factor(recs[r], e, base));
-          flo[tid] = f;
-        }
-      } else if (tid - 128u < (1u << TH)) {
-        const uint32_t j = tid - 128u;
-        C f{(Real)1, (Real)0};
-#pragma unroll 4
-        for (int r = r1; r < r2; ++r) f = cmul2(f, diag_factor(recs[r], j << TL, base));
-        fhi[j] = f;
-      }
-      __syncthreads();
-      const int hsh = hx >= 0 ? hx : 0;
-      const uint32_t hmask = hx >= 0 ? 1u : 0u;
       // each thread scales its elements e = tid + 256 i, kChunk at a time:
-      // a record is read once per chunk and applied to all of its elements
+      // a per-element record is read once per chunk
       for (uint32_t e0 = tid; e0 < TE; e0 += kChunk * kCircThreads) {
         C f[kChunk];
 #pragma unroll
         for (int i = 0; i < kChunk; ++i) {
           const uint32_t e = e0 + i * kCircThreads;
-          const uint32_t il = (e & mlo) | (((e >> hsh) & hmask) << TL);
-          f[i] = e < TE ? cmul2(flo[il], fhi[e >> TL]) : C{(Real)1, (Real)0};
+          f[i] = e < TE ? table_factor<Real>(tb, e, TL, hsh, hmask) : C{(Real)1, (Real)0};
         }
-        for (int r = r2; r < r3; ++r) {
+        for (int r = rc0; r < rc1; ++r) {
           const DevDiag<Real> rec = recs[r];
 #pragma unroll
           for (int i = 0; i < kChunk; ++i)
@@ -250,6 +310,7 @@ __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d,
         }
       }
     }
+    if (oi + 1 < d.nops) build_tables<Real>(ops[oi + 1], recs, tabs[(oi + 1) & 1], TL, TH, base, tid);
     __syncthreads();
   }
   for (uint32_t e = tid; e < TE; e += kCircThreads) psi[alo[e & mlo] | ahi[e >> TL]] = lds[e];
@@ -351,18 +412,23 @@ void build_pass_image(const qft_circuit_s *c, int g0, int g1, const std::vector<
       else if (!other_high) lo.push_back(r);
       else cross.push_back(r);
     }
-    DevOp<Real> op;
-    memset(&op, 0, sizeof(op));
-    op.kind = kOpDiag;
-    op.a = (int32_t)img.recs.size();
-    op.b = (int32_t)lo.size();
-    op.c = (int32_t)hi.size();
-    op.d = (int32_t)cross.size();
+    // the run rides on the pair operation just before it, if there is one
+    const bool attach = !img.ops.empty() && img.ops.back().kind == kOpPair;
+    if (!attach) {
+      DevOp<Real> op;
+      memset(&op, 0, sizeof(op));
+      op.kind = kOpDiag;
+      img.ops.push_back(op);
+    }
+    DevOp<Real> &op = img.ops.back();
+    op.r0 = (int32_t)img.recs.size();
+    op.nlo = (int32_t)lo.size();
+    op.nhi = (int32_t)hi.size();
+    op.ncross = (int32_t)cross.size();
     op.hx = hx;
     img.recs.insert(img.recs.end(), lo.begin(), lo.end());
     img.recs.insert(img.recs.end(), hi.begin(), hi.end());
     img.recs.insert(img.recs.end(), cross.begin(), cross.end());
-    img.ops.push_back(op);
     run.clear();
   };
   const c2<Real> one{(Real)1, (Real)0};
@@ -389,6 +455,7 @@ void build_pass_image(const qft_circuit_s *c, int g0, int g1, const std::vector<
     flush();
     DevOp<Real> op;
     memset(&op, 0, sizeof(op));
+    op.hx = -1;  // no diagonal run (yet)
     if (g.kind == kSwap) {
       op.kind = kOpSwap;
       op.a = tpos[g.a];
@@ -443,8 +510,9 @@ int compile(qft_circuit_s *c, int tile_qubits, bool upload) {
   drop_compiled(c);
   const int n = c->n;
   const int T = default_tile_bits(c);
-  // leave about 128 bytes of contiguous elements per tile row by default
-  int B = tile_qubits > 0 ? tile_qubits : T - (c->c128 ? 3 : 4);
+  // by default leave 64 bytes of contiguous elements per tile row (the
+  // passes are bound by their LDS sweeps more than by row length)
+  int B = tile_qubits > 0 ? tile_qubits : T - (c->c128 ? 2 : 3);
   B = std::max(2, std::min(B, T));
   c->tile_qubits = tile_qubits;
   // greedy runs of gates whose tile needs fit in B qubits

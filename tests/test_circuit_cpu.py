@@ -71,7 +71,7 @@ def test_greedy_grouping(n, B, seed, dtype):
     c = build(n, gates, dtype)
     begin, tbits = c.describe(B)
     T = tile_size(n, dtype)
-    default = T - (4 if dtype == "c64" else 3)
+    default = T - (3 if dtype == "c64" else 2)
     Beff = max(2, min(B if B > 0 else default, T))
     assert begin[0] == 0 and begin == sorted(begin)
     ends = begin[1:] + [len(gates)]
