@@ -25,12 +25,20 @@ using namespace qft;
 namespace {
 
 constexpr int kCircThreads = 256;
-constexpr int kMaxTileC64 = 13;   // 2^13 complex64 = 64 KiB of LDS
-constexpr int kMaxTileC128 = 12;  // 2^12 complex128 = 64 KiB of LDS
+constexpr int kMaxTileC64 = 13;   // 2^13 complex64 = 64 KiB of LDS (plus padding)
+constexpr int kMaxTileC128 = 12;  // 2^12 complex128 = 64 KiB of LDS (plus padding)
 constexpr int kLowBits = 6;       // tile positions [0, 6) index the low tables
-constexpr int kMaxHighBits = kMaxTileC64 - kLowBits;
 constexpr int32_t kNoControl = 0x7fffffff;
 constexpr int kChunk = 8;  // elements a thread scales per read of a diagonal record
+
+// Per element type: high tile bits (T - 6), stage size (tile positions whose
+// 2^K elements a thread holds in registers) and diagonal-run tables per stage.
+template <typename Real>
+struct Shape {
+  static constexpr int kHighBits = (sizeof(Real) == 8 ? kMaxTileC128 : kMaxTileC64) - kLowBits;
+  static constexpr int kStageBits = sizeof(Real) == 8 ? 4 : 5;
+  static constexpr int kSlots = sizeof(Real) == 8 ? 4 : 5;
+};
 
 template <typename Real>
 struct alignas(2 * sizeof(Real)) c2 {
@@ -48,23 +56,35 @@ struct GateRec {
 // What a pass does, in order.  A qubit operand is encoded as its tile
 // position p >= 0, or as -1 - g for a global bit g outside the tile (whose
 // value is the same for every element of a tile).
-enum OpKind : int32_t { kOpPair = 0, kOpSwap = 1, kOpDiag = 2 };
+//  - kOpStage: header of a stage, followed by its kOpPair operations.  The
+//    stage's targets are at most kStageBits tile positions; every thread
+//    holds the 2^K elements of a sub-cube over them in registers and applies
+//    all the stage's gates (and their diagonal runs) there.
+//  - kOpPair: a 2x2 matrix on the stage position with index `a`, optionally
+//    controlled, then the diagonal run that follows it in the circuit.
+//  - kOpSwap: swap of two tile qubits.
+//  - kOpDiag: a diagonal run with no non-diagonal gate before it in the pass.
+// A diagonal run (consecutive diagonal gates, which commute) has its records
+// split over a low table (low tile positions, global bits and at most one
+// high position hx), a high table (high positions and global bits) and a
+// list evaluated per element (gates pairing a low position with a high
+// position other than hx).  The tables are built per tile.
+enum OpKind : int32_t { kOpPair = 0, kOpSwap = 1, kOpDiag = 2, kOpStage = 3 };
 
-// A diagonal run (consecutive diagonal gates, which commute) is applied
-// after a pair operation in the same sweep, or on its own (kOpDiag).  Its
-// records are split over a low table (low tile positions, global bits and
-// at most one high position hx), a high table (high positions and global
-// bits) and a list evaluated per element (gates that pair a low position
-// with a high position other than hx).
 template <typename Real>
 struct DevOp {
   int32_t kind;
-  int32_t a;                 // pair: target tile position; swap: tile position
-  int32_t b;                 // pair: encoded control or kNoControl; swap: tile position
-  int32_t r0;                // diagonal run: first record
-  int32_t nlo, nhi, ncross;  // its records in the low table, the high table, per element
-  int32_t hx;                // high tile position that extends the low table, or -1
-  c2<Real> u[4];             // pair: row-major 2x2
+  int32_t a;       // pair: stage index of the target; swap: tile position;
+                   // stage: number of pair operations that follow
+  int32_t b;       // pair: encoded control or kNoControl; swap: tile position;
+                   // stage: number of positions K
+  int32_t r0;      // run: first record; stage: positions, 4 bits each, ascending
+  int32_t nlo, nhi, ncross;  // run: records in the low table, high table, per element
+                             // (stage: nlo = number of runs)
+  int32_t hx;      // run: high tile position that extends the low table, or -1
+  int32_t slot;    // pair: table slot of its run
+  int32_t pad[3];
+  c2<Real> u[4];   // pair: row-major 2x2
 };
 
 // A diagonal gate on qubits (q1, q0): the amplitude is scaled by
@@ -92,6 +112,10 @@ __device__ __forceinline__ uint32_t insert_zero(uint32_t x, int pos) {
   return ((x & ~low) << 1) | (x & low);
 }
 
+// LDS slot of tile element e: one pad element per 32 spreads the banks of
+// sweeps whose lanes step over a gap of tile positions.
+__device__ __forceinline__ uint32_t lidx(uint32_t e) { return e + (e >> 5); }
+
 template <typename Real>
 __device__ __forceinline__ c2<Real> cmul2(c2<Real> a, c2<Real> b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
@@ -118,7 +142,7 @@ __device__ __forceinline__ c2<Real> diag_factor(const DevDiag<Real> &r, uint32_t
 template <typename Real>
 struct RunTables {
   c2<Real> lo[2 << kLowBits];
-  c2<Real> hi[1 << kMaxHighBits];
+  c2<Real> hi[1 << Shape<Real>::kHighBits];
 };
 
 // The factor tables of a diagonal run for this tile: thread j < 2^(TL+1)
@@ -149,31 +173,106 @@ __device__ __forceinline__ void build_tables(const DevOp<Real> &op, const DevDia
   }
 }
 
-// Table part of the run's factor for tile element e.
+// Table part of a run's factor for tile element e.
 template <typename Real>
 __device__ __forceinline__ c2<Real> table_factor(const RunTables<Real> &tb, uint32_t e, int TL,
-                                                 int hsh, uint32_t hmask) {
+                                                 int hx) {
   const uint32_t mlo = (1u << TL) - 1u;
-  return cmul2(tb.lo[(e & mlo) | (((e >> hsh) & hmask) << TL)], tb.hi[e >> TL]);
+  const uint32_t xb = hx >= 0 ? ((e >> hx) & 1u) << TL : 0u;
+  return cmul2(tb.lo[(e & mlo) | xb], tb.hi[e >> TL]);
+}
+
+// Matrix u on the register pairs (c, c + 2^J) of a sub-cube whose corner c
+// is tile element eb | off[c]; where the control bit of a pair is clear it
+// is left alone.
+template <typename Real, int K, int J>
+__device__ __forceinline__ void stage_pair(c2<Real> (&v)[1 << K], uint32_t eb,
+                                           const uint32_t (&off)[1 << K], int cq, uint64_t base,
+                                           c2<Real> u0, c2<Real> u1, c2<Real> u2, c2<Real> u3) {
+  using C = c2<Real>;
+#pragma unroll
+  for (int c = 0; c < (1 << K); ++c) {
+    if (c & (1 << J)) continue;
+    const int c1 = c | (1 << J);
+    const bool take = cq == kNoControl || qbit(cq, eb | off[c], base);
+    const C a = v[c], b = v[c1];
+    const C na = cadd2(cmul2(u0, a), cmul2(u1, b));
+    const C nb = cadd2(cmul2(u2, a), cmul2(u3, b));
+    v[c] = take ? na : a;
+    v[c1] = take ? nb : b;
+  }
+}
+
+// One stage over K tile positions (packed ascending in `packed`): each
+// thread takes sub-cubes s = tid + 256 i, loads their 2^K elements from LDS,
+// applies the stage's operations in order and stores them back.
+template <typename Real, int K>
+__device__ __forceinline__ void stage_sweep(c2<Real> *lds, const DevOp<Real> *sops, int nsops,
+                                            uint32_t packed, const RunTables<Real> *tabs,
+                                            const DevDiag<Real> *recs, uint64_t base, int TL,
+                                            uint32_t TE, uint32_t tid) {
+  using C = c2<Real>;
+  constexpr int R = 1 << K;
+  int pos[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) pos[j] = (int)((packed >> (4 * j)) & 15u);
+  uint32_t off[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    uint32_t o = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) o |= (uint32_t)((c >> j) & 1) << pos[j];
+    off[c] = o;
+  }
+  for (uint32_t s = tid; s < (TE >> K); s += kCircThreads) {
+    uint32_t eb = s;
+#pragma unroll
+    for (int j = 0; j < K; ++j) eb = insert_zero(eb, pos[j]);
+    C v[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) v[c] = lds[lidx(eb | off[c])];
+    for (int oi = 0; oi < nsops; ++oi) {
+      const DevOp<Real> &op = sops[oi];
+      const C u0 = op.u[0], u1 = op.u[1], u2 = op.u[2], u3 = op.u[3];
+      const int cq = op.b;
+      switch (op.a) {
+        case 0: stage_pair<Real, K, 0>(v, eb, off, cq, base, u0, u1, u2, u3); break;
+        case 1: if constexpr (K > 1) stage_pair<Real, K, 1>(v, eb, off, cq, base, u0, u1, u2, u3); break;
+        case 2: if constexpr (K > 2) stage_pair<Real, K, 2>(v, eb, off, cq, base, u0, u1, u2, u3); break;
+        case 3: if constexpr (K > 3) stage_pair<Real, K, 3>(v, eb, off, cq, base, u0, u1, u2, u3); break;
+        case 4: if constexpr (K > 4) stage_pair<Real, K, 4>(v, eb, off, cq, base, u0, u1, u2, u3); break;
+        default: break;
+      }
+      if (op.nlo + op.nhi + op.ncross > 0) {
+        const RunTables<Real> &tb = tabs[op.slot];
+        const int hx = op.hx;
+#pragma unroll
+        for (int c = 0; c < R; ++c) v[c] = cmul2(table_factor<Real>(tb, eb | off[c], TL, hx), v[c]);
+        const int rc0 = op.r0 + op.nlo + op.nhi, rc1 = rc0 + op.ncross;
+        for (int r = rc0; r < rc1; ++r) {
+          const DevDiag<Real> rec = recs[r];
+#pragma unroll
+          for (int c = 0; c < R; ++c) v[c] = cmul2(diag_factor(rec, eb | off[c], base), v[c]);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) lds[lidx(eb | off[c])] = v[c];
+  }
 }
 
 // One pass: load the tile into LDS (element e = sum over tile positions q of
 // bit q of e at global bit gpos[q], plus the tile's free bits), apply the
-// pass's operations in order, store the tile.
-//  - pair: a 2x2 matrix on a tile qubit, optionally controlled by a tile
-//    qubit or by a global bit (then the whole tile takes it or skips it),
-//    followed in the same sweep by the diagonal run after it, if any;
-//  - swap of two tile qubits;
-//  - diagonal run on its own.
-// The tables of operation i + 1's run are built at the end of operation i
-// (two table buffers), so each operation ends with one barrier.
+// pass's operations in order (stages in registers, swaps and lone diagonal
+// runs as LDS sweeps), one barrier after each, store the tile.
 template <typename Real>
 __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d, c2<Real> *psi) {
   using C = c2<Real>;
+  using S = Shape<Real>;
   extern __shared__ __align__(16) unsigned char circ_smem[];
   C *lds = reinterpret_cast<C *>(circ_smem);
-  __shared__ RunTables<Real> tabs[2];
-  __shared__ uint64_t alo[1 << kLowBits], ahi[1 << kMaxHighBits];
+  __shared__ RunTables<Real> tabs[S::kSlots];
+  __shared__ uint64_t alo[1 << kLowBits], ahi[1 << S::kHighBits];
   const uint32_t tid = threadIdx.x;
   uint32_t tile = blockIdx.x;
   if (d.xcd_remap) {
@@ -200,102 +299,59 @@ __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d,
     ahi[j] = g;
   }
   __syncthreads();
-  if (d.nops > 0) build_tables<Real>(ops[0], recs, tabs[0], TL, TH, base, tid);
   const uint32_t TE = 1u << d.T;
-  for (uint32_t e = tid; e < TE; e += kCircThreads) lds[e] = psi[alo[e & mlo] | ahi[e >> TL]];
+  for (uint32_t e = tid; e < TE; e += kCircThreads) lds[lidx(e)] = psi[alo[e & mlo] | ahi[e >> TL]];
   __syncthreads();
-  for (int oi = 0; oi < d.nops; ++oi) {
+  int oi = 0;
+  while (oi < d.nops) {
     const DevOp<Real> &op = ops[oi];
-    const RunTables<Real> &tb = tabs[oi & 1];
     const int kind = op.kind;
-    const bool run = op.nlo + op.nhi + op.ncross > 0;
-    const int hsh = op.hx >= 0 ? op.hx : 0;
-    const uint32_t hmask = op.hx >= 0 ? 1u : 0u;
-    const int rc0 = op.r0 + op.nlo + op.nhi, rc1 = rc0 + op.ncross;
-    if (kind == kOpPair) {
-      const C u0 = op.u[0], u1 = op.u[1], u2 = op.u[2], u3 = op.u[3];
-      const int t = op.a, cq = op.b;
-      // a global control is the same for the whole tile
-      const bool tile_take = cq == kNoControl || cq >= 0 || ((base >> (-1 - cq)) & 1u);
-      const int cpos = cq >= 0 && cq != kNoControl ? cq : -1;
-      if (!run) {
-        if (tile_take) {
-          if (cpos < 0) {
-            for (uint32_t p = tid; p < (TE >> 1); p += kCircThreads) {
-              const uint32_t e0 = insert_zero(p, t), e1 = e0 | (1u << t);
-              const C a = lds[e0], b = lds[e1];
-              lds[e0] = cadd2(cmul2(u0, a), cmul2(u1, b));
-              lds[e1] = cadd2(cmul2(u2, a), cmul2(u3, b));
-            }
-          } else {
-            const int lo = cpos < t ? cpos : t, hi = cpos < t ? t : cpos;
-            for (uint32_t p = tid; p < (TE >> 2); p += kCircThreads) {
-              const uint32_t e0 = insert_zero(insert_zero(p, lo), hi) | (1u << cpos);
-              const uint32_t e1 = e0 | (1u << t);
-              const C a = lds[e0], b = lds[e1];
-              lds[e0] = cadd2(cmul2(u0, a), cmul2(u1, b));
-              lds[e1] = cadd2(cmul2(u2, a), cmul2(u3, b));
-            }
-          }
+    if (kind == kOpStage) {
+      const int cnt = op.a;
+      if (op.nlo > 0) {  // the stage has diagonal runs: build their tables
+        for (int i = 1; i <= cnt; ++i) {
+          const DevOp<Real> &po = ops[oi + i];
+          if (po.nlo + po.nhi + po.ncross > 0)
+            build_tables<Real>(po, recs, tabs[po.slot], TL, TH, base, tid);
         }
-      } else {
-        // every pair: the matrix where the control allows it, then the
-        // run's factors; kChunk / 2 pairs per read of a per-element record
-        constexpr int kP = kChunk / 2;
-        for (uint32_t p0 = tid; p0 < (TE >> 1); p0 += kP * kCircThreads) {
-          C a[kP], b[kP], f0[kP], f1[kP];
-#pragma unroll
-          for (int i = 0; i < kP; ++i) {
-            const uint32_t p = p0 + i * kCircThreads;
-            const uint32_t e0 = insert_zero(p, t), e1 = e0 | (1u << t);
-            if (p < (TE >> 1)) {
-              const C x0 = lds[e0], x1 = lds[e1];
-              const bool take = tile_take && (cpos < 0 || ((e0 >> cpos) & 1u));
-              a[i] = take ? cadd2(cmul2(u0, x0), cmul2(u1, x1)) : x0;
-              b[i] = take ? cadd2(cmul2(u2, x0), cmul2(u3, x1)) : x1;
-              f0[i] = table_factor<Real>(tb, e0, TL, hsh, hmask);
-              f1[i] = table_factor<Real>(tb, e1, TL, hsh, hmask);
-            }
-          }
-          for (int r = rc0; r < rc1; ++r) {
-            const DevDiag<Real> rec = recs[r];
-#pragma unroll
-            for (int i = 0; i < kP; ++i) {
-              const uint32_t e0 = insert_zero(p0 + i * kCircThreads, t), e1 = e0 | (1u << t);
-              f0[i] = cmul2(f0[i], diag_factor(rec, e0, base));
-              f1[i] = cmul2(f1[i], diag_factor(rec, e1, base));
-            }
-          }
-#pragma unroll
-          for (int i = 0; i < kP; ++i) {
-            const uint32_t p = p0 + i * kCircThreads;
-            const uint32_t e0 = insert_zero(p, t), e1 = e0 | (1u << t);
-            if (p < (TE >> 1)) {
-              lds[e0] = cmul2(f0[i], a[i]);
-              lds[e1] = cmul2(f1[i], b[i]);
-            }
-          }
-        }
+        __syncthreads();
       }
+      const uint32_t packed = (uint32_t)op.r0;
+      switch (op.b) {
+        case 1: stage_sweep<Real, 1>(lds, ops + oi + 1, cnt, packed, tabs, recs, base, TL, TE, tid); break;
+        case 2: stage_sweep<Real, 2>(lds, ops + oi + 1, cnt, packed, tabs, recs, base, TL, TE, tid); break;
+        case 3: stage_sweep<Real, 3>(lds, ops + oi + 1, cnt, packed, tabs, recs, base, TL, TE, tid); break;
+        case 4: stage_sweep<Real, 4>(lds, ops + oi + 1, cnt, packed, tabs, recs, base, TL, TE, tid); break;
+        case 5:
+          if constexpr (S::kStageBits >= 5)
+            stage_sweep<Real, 5>(lds, ops + oi + 1, cnt, packed, tabs, recs, base, TL, TE, tid);
+          break;
+        default: break;
+      }
+      oi += 1 + cnt;
     } else if (kind == kOpSwap) {
       const int a = op.a, b = op.b;
       const int lo = a < b ? a : b, hi = a < b ? b : a;
       for (uint32_t p = tid; p < (TE >> 2); p += kCircThreads) {
         const uint32_t z = insert_zero(insert_zero(p, lo), hi);
-        const uint32_t e0 = z | (1u << a), e1 = z | (1u << b);
+        const uint32_t e0 = lidx(z | (1u << a)), e1 = lidx(z | (1u << b));
         const C x = lds[e0];
         lds[e0] = lds[e1];
         lds[e1] = x;
       }
+      oi += 1;
     } else {
+      build_tables<Real>(op, recs, tabs[0], TL, TH, base, tid);
+      __syncthreads();
       // each thread scales its elements e = tid + 256 i, kChunk at a time:
       // a per-element record is read once per chunk
+      const int rc0 = op.r0 + op.nlo + op.nhi, rc1 = rc0 + op.ncross;
       for (uint32_t e0 = tid; e0 < TE; e0 += kChunk * kCircThreads) {
         C f[kChunk];
 #pragma unroll
         for (int i = 0; i < kChunk; ++i) {
           const uint32_t e = e0 + i * kCircThreads;
-          f[i] = e < TE ? table_factor<Real>(tb, e, TL, hsh, hmask) : C{(Real)1, (Real)0};
+          f[i] = e < TE ? table_factor<Real>(tabs[0], e, TL, op.hx) : C{(Real)1, (Real)0};
         }
         for (int r = rc0; r < rc1; ++r) {
           const DevDiag<Real> rec = recs[r];
@@ -306,14 +362,14 @@ __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d,
 #pragma unroll
         for (int i = 0; i < kChunk; ++i) {
           const uint32_t e = e0 + i * kCircThreads;
-          if (e < TE) lds[e] = cmul2(f[i], lds[e]);
+          if (e < TE) lds[lidx(e)] = cmul2(f[i], lds[lidx(e)]);
         }
       }
+      oi += 1;
     }
-    if (oi + 1 < d.nops) build_tables<Real>(ops[oi + 1], recs, tabs[(oi + 1) & 1], TL, TH, base, tid);
     __syncthreads();
   }
-  for (uint32_t e = tid; e < TE; e += kCircThreads) psi[alo[e & mlo] | ahi[e >> TL]] = lds[e];
+  for (uint32_t e = tid; e < TE; e += kCircThreads) psi[alo[e & mlo] | ahi[e >> TL]] = lds[lidx(e)];
 }
 
 }  // namespace
@@ -471,6 +527,58 @@ void build_pass_image(const qft_circuit_s *c, int g0, int g1, const std::vector<
   flush();
 }
 
+// Group consecutive pair operations into stages: greedily, while their
+// targets span at most kStageBits tile positions and their diagonal runs fit
+// the stage's table slots.  Each stage is a header followed by its pair
+// operations, whose targets become indices into the stage's (ascending)
+// positions.
+template <typename Real>
+void form_stages(PassImage<Real> &img) {
+  const int kmax = Shape<Real>::kStageBits, slots = Shape<Real>::kSlots;
+  std::vector<DevOp<Real>> out;
+  size_t i = 0;
+  while (i < img.ops.size()) {
+    if (img.ops[i].kind != kOpPair) {
+      out.push_back(img.ops[i]);
+      ++i;
+      continue;
+    }
+    std::vector<int> S;
+    int runs = 0;
+    size_t j = i;
+    while (j < img.ops.size() && img.ops[j].kind == kOpPair) {
+      const DevOp<Real> &o = img.ops[j];
+      const bool run = o.nlo + o.nhi + o.ncross > 0;
+      const bool fresh = std::find(S.begin(), S.end(), o.a) == S.end();
+      if ((fresh && (int)S.size() == kmax) || (run && runs == slots)) break;
+      if (fresh) S.push_back(o.a);
+      if (run) ++runs;
+      ++j;
+    }
+    std::sort(S.begin(), S.end());
+    DevOp<Real> h;
+    memset(&h, 0, sizeof(h));
+    h.kind = kOpStage;
+    h.a = (int32_t)(j - i);
+    h.b = (int32_t)S.size();
+    uint32_t packed = 0;
+    for (size_t q = 0; q < S.size(); ++q) packed |= (uint32_t)S[q] << (4 * q);
+    h.r0 = (int32_t)packed;
+    h.nlo = runs;
+    h.hx = -1;
+    out.push_back(h);
+    int slot = 0;
+    for (size_t k = i; k < j; ++k) {
+      DevOp<Real> o = img.ops[k];
+      o.a = (int32_t)(std::find(S.begin(), S.end(), o.a) - S.begin());
+      if (o.nlo + o.nhi + o.ncross > 0) o.slot = slot++;
+      out.push_back(o);
+    }
+    i = j;
+  }
+  img.ops.swap(out);
+}
+
 template <typename Real>
 int upload_passes(qft_circuit_s *c, std::vector<PassImage<Real>> &imgs) {
   size_t bytes = 0;
@@ -569,10 +677,12 @@ int compile(qft_circuit_s *c, int tile_qubits, bool upload) {
     if (c->c128) {
       img64.emplace_back();
       build_pass_image<double>(c, runs[r].first, runs[r].second, tpos, p.TL, img64.back());
+      form_stages<double>(img64.back());
       p.nops = (int)img64.back().ops.size();
     } else {
       img32.emplace_back();
       build_pass_image<float>(c, runs[r].first, runs[r].second, tpos, p.TL, img32.back());
+      form_stages<float>(img32.back());
       p.nops = (int)img32.back().ops.size();
     }
     c->passes.push_back(p);
@@ -586,15 +696,28 @@ int compile(qft_circuit_s *c, int tile_qubits, bool upload) {
 }
 
 template <typename Real>
+constexpr int kMaxTile() {
+  return sizeof(Real) == 8 ? kMaxTileC128 : kMaxTileC64;
+}
+
+// Dynamic LDS of a pass: the tile with one pad element per 32 (see lidx).
+template <typename Real>
+size_t circuit_lds_bytes(int T) {
+  const size_t te = (size_t)1 << T;
+  return (te + (te >> 5)) * sizeof(c2<Real>);
+}
+
+template <typename Real>
 hipError_t launch_circuit_pass(const CircPass &p, void *dev_ptr, hipStream_t s) {
   static std::atomic<int> raised{0};
   if (!raised.load(std::memory_order_acquire)) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_circuit_pass<Real>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)circuit_lds_bytes<Real>(kMaxTile<Real>()));
     if (e != hipSuccess) return e;
     raised.store(1, std::memory_order_release);
   }
-  const size_t lds = ((size_t)1 << p.T) * sizeof(c2<Real>);
+  const size_t lds = circuit_lds_bytes<Real>(p.T);
   hipLaunchKernelGGL(k_circuit_pass<Real>, dim3(p.ntiles), dim3(kCircThreads), lds, s, p,
                      (c2<Real> *)dev_ptr);
   return hipGetLastError();
