@@ -158,6 +158,30 @@ def bench_circuit(torch, Q, n=24, steps=5):
             "qft_plan_ms": ms_plan, "qft_plan_passes": 3}
 
 
+def bench_gate_schedule(torch, Q, n=24, steps=3):
+    """The same transform run gate by gate (one HBM sweep per H, controlled
+    phase and swap, the unfused form) against the fused plan."""
+    N = 1 << n
+    x = torch.empty(N, dtype=torch.complex64, device="cuda")
+    Q.fill_random(x, "gaussian", seed=1003)
+    rows = {}
+    for schedule in ("gates", "fused"):
+        plan = Q.Plan(n, -1, "unitary", "c64", "natural", schedule)
+        ms = time_plan(torch, Q, plan, x, steps, 1)
+        info = plan.info
+        gates = info.gates_h + info.gates_cr + info.gates_swap
+        rows[schedule] = {"ms": ms, "passes": info.num_passes if schedule == "fused" else gates,
+                          "hbm_bytes": info.hbm_bytes, "bytes_per_gate": info.hbm_bytes / gates,
+                          "hbm_gbs": info.hbm_bytes / (ms * 1e-3) / 1e9}
+        plan.close()
+    del x
+    torch.cuda.empty_cache()
+    rows["n"] = n
+    rows["gate_count"] = gates
+    rows["speedup_fused"] = rows["gates"]["ms"] / rows["fused"]["ms"]
+    return rows
+
+
 def bench_batch(torch, Q, reps=10):
     """512 uneven transforms: the batched launches in one HIP graph, the same
     launches enqueued directly, and one plan execute per transform."""
@@ -349,6 +373,18 @@ def main():
     prof = os.path.join(ROOT, "profiles", profile_name(n, args.dtype, args.cutoff))
     out["roofline"]["traffic"] = PS.load_traffic(prof, out["config"])
     out["roofline"]["traffic_source"] = os.path.relpath(prof, ROOT)
+    # HBM bytes per gate of the circuit (H, controlled phases, swaps): the
+    # fused plan's passes shared over its gates, from the algorithmic bytes
+    # and from the counters; a gate-by-gate sweep moves 2*N*S per gate
+    gates = info.gates_h + info.gates_cr + info.gates_swap
+    traffic = out["roofline"]["traffic"]
+    out["bytes_per_gate"] = {
+        "gates": {"h": info.gates_h, "controlled_phase": info.gates_cr,
+                  "swap": info.gates_swap},
+        "algorithmic": info.hbm_bytes / gates,
+        "counters": traffic * info.num_passes / gates if traffic else None,
+        "gate_by_gate_sweep": per_launch_bytes,
+    }
     if args.copy_ref:
         y = torch.empty_like(x)
         ms_copy = None
@@ -377,6 +413,8 @@ def main():
         out["aqft_budget_n28_c64"] = bench_budget(torch, Q, 28, [1e-2, 1e-3, 1e-4], 10)
         print("[bench] complex128", file=sys.stderr, flush=True)
         out["exact_n28_c128"] = bench_aqft(torch, Q, 28, "c128", [-1], 10)[0]
+        print("[bench] gate-by-gate schedule", file=sys.stderr, flush=True)
+        out["gate_schedule_n24_c64"] = bench_gate_schedule(torch, Q)
         print("[bench] general circuit", file=sys.stderr, flush=True)
         out["general_circuit_qft_n24_c64"] = bench_circuit(torch, Q)
         print("[bench] batch", file=sys.stderr, flush=True)

@@ -13,6 +13,7 @@
 
 #include "../../include/qft_circuit.h"
 #include "qft_internal.h"
+#include "qft_kernels.h"
 
 namespace qft {
 int set_error(int code, const std::string &msg);
@@ -709,15 +710,12 @@ size_t circuit_lds_bytes(int T) {
 
 template <typename Real>
 hipError_t launch_circuit_pass(const CircPass &p, void *dev_ptr, hipStream_t s) {
-  static std::atomic<int> raised{0};
-  if (!raised.load(std::memory_order_acquire)) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_circuit_pass<Real>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)circuit_lds_bytes<Real>(kMaxTile<Real>()));
-    if (e != hipSuccess) return e;
-    raised.store(1, std::memory_order_release);
-  }
   const size_t lds = circuit_lds_bytes<Real>(p.T);
+  if (lds > 65536) {
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void *>(&k_circuit_pass<Real>),
+                                    (int)circuit_lds_bytes<Real>(kMaxTile<Real>()));
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_circuit_pass<Real>, dim3(p.ntiles), dim3(kCircThreads), lds, s, p,
                      (c2<Real> *)dev_ptr);
   return hipGetLastError();

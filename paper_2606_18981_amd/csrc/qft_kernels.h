@@ -7,6 +7,11 @@
 
 namespace qft {
 
+// Let kernel `fn` use up to `bytes` of dynamic LDS (above the 64 KiB
+// default) on the current device.  The attribute is per device, so it is set
+// once per (device, kernel) pair; thread-safe.
+hipError_t ensure_lds_limit(const void *fn, int bytes);
+
 // One fused HBM pass (see qft_internal.h).
 hipError_t launch_fused_pass(const PassLaunch &L, bool c128, const void *in, void *out,
                              hipStream_t s);

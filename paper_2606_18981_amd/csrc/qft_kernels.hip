@@ -18,11 +18,29 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <mutex>
+#include <set>
+#include <utility>
 
 #include "qft_internal.h"
 #include "qft_kernels.h"
 
 namespace qft {
+
+hipError_t ensure_lds_limit(const void *fn, int bytes) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  static std::mutex mu;
+  static std::set<std::pair<int, const void *>> done;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count({dev, fn})) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  done.insert({dev, fn});
+  return hipSuccess;
+}
+
 
 template <typename Real>
 struct alignas(2 * sizeof(Real)) cplx {
@@ -574,15 +592,8 @@ static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, 
     }
   }
   if (L.lds_bytes > 65536) {
-    // raise the LDS limit once per kernel instance
-    static std::atomic<uint32_t> raised{0};
-    const uint32_t bit = 1u << inst;
-    if (!(raised.load(std::memory_order_acquire) & bit)) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-      if (e != hipSuccess) return e;
-      raised.fetch_or(bit, std::memory_order_release);
-    }
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void *>(fn), 163840);
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(fn, dim3(L.grid), dim3(L.threads), L.lds_bytes, s, L.d,
                      (const cplx<Real> *)in, (cplx<Real> *)out);
@@ -679,15 +690,8 @@ static hipError_t launch_group_t(const BatchGroup &g, hipStream_t s) {
     }
   }
   if (g.lds_bytes > 65536) {
-    // raise the LDS limit once per kernel instance
-    static std::atomic<uint32_t> raised{0};
-    const uint32_t bit = 1u << g.shape;
-    if (!(raised.load(std::memory_order_acquire) & bit)) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-      if (e != hipSuccess) return e;
-      raised.fetch_or(bit, std::memory_order_release);
-    }
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void *>(fn), 163840);
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(fn, dim3(g.items), dim3(g.threads), g.lds_bytes, s, g.segs, g.nseg, g.descs,
                      g.io);
