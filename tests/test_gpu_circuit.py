@@ -138,3 +138,19 @@ def test_qft_as_general_circuit(env, dtype, n, k):
     y, info = run(torch, Q, n, O.qft_as_gates(n, k), x, dtype)
     ref = O.qft_fused_targets(x, k)
     assert O.rel_l2(y, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_empty_and_swap_only_circuits(env, dtype):
+    """No gates: no pass, the state is untouched.  Only swaps: a permutation
+    of the amplitudes, exact to the bit."""
+    torch, Q = env
+    n = 15
+    x = I.gaussian(n, 9600)
+    y, info = run(torch, Q, n, [], x, dtype)
+    assert info["passes"] == 0
+    assert np.array_equal(y, x.astype(NPDT[dtype]).astype(np.complex128))
+    gates = [("SWAP", a, n - 1 - a) for a in range(n // 2)] + [("SWAP", 0, 7), ("SWAP", 3, 14)]
+    y, info = run(torch, Q, n, gates, x, dtype)
+    ref = O.apply_gates(x.astype(NPDT[dtype]).astype(np.complex128), gates)
+    assert np.array_equal(y, ref)

@@ -157,16 +157,29 @@ def test_n24_gaussian_and_tones(torch_cuda, Q, dtype):
 
 # ---- config 3: n = 28 exact and AQFT, sampled outputs ----------------------
 
-@pytest.mark.parametrize("k", [-1, 6, 14])
-def test_n28_sampled_bins(torch_cuda, Q, k):
+@pytest.mark.parametrize("k,dtype", [(-1, "c64"), (6, "c64"), (14, "c64"), (-1, "c128"),
+                                     (10, "c128")])
+def test_n28_sampled_bins(torch_cuda, Q, k, dtype):
     n = 28
+    print(f"[gpu] n=28 sampled bins k={k} {dtype}", flush=True)
     x = I.gaussian(n, 1003)
-    y = run_gpu(torch_cuda, Q, x, n, k, "unitary", "c64", "natural")
+    y = run_gpu(torch_cuda, Q, x, n, k, "unitary", dtype, "natural")
     bins = np.random.default_rng(28).choice(1 << n, 12, replace=False)
     ref = O.dft_bins(x, bins) if k < 0 else O.aqft_bins(x, bins, k)
-    assert O.rel_l2(y[bins], ref) <= TOL["c64"]
+    assert O.rel_l2(y[bins], ref) <= TOL[dtype]
     # the AQFT is unitary: Parseval at any size
-    assert np.linalg.norm(y) == pytest.approx(np.linalg.norm(x), rel=1e-5)
+    assert np.linalg.norm(y) == pytest.approx(np.linalg.norm(x), rel=1e-5 if dtype == "c64" else 1e-12)
+
+
+@pytest.mark.parametrize("k", [-1, 5])
+def test_wide_first_pass_plan(torch_cuda, Q, k):
+    """The first pass with one more tile bit than the others (2^11 against
+    2^10), the rule that n = 30 takes at the default tiles."""
+    n = 21
+    cfg = dict(tile_log2=10, radix_log2=4, spec_log2=3, rev_spec_log2=3)
+    x = I.gaussian(n, 2100)
+    y = run_gpu(torch_cuda, Q, x, n, k, "unitary", "c64", "natural", "fused", cfg)
+    assert O.rel_l2(y, O.qft_fused_targets(x, None if k < 0 else k)) <= TOL["c64"]
 
 
 # ---- inverse (conjugate-phase) transform ----------------------------------

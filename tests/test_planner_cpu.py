@@ -298,3 +298,24 @@ def test_split_exchange_lds():
             assert info.pass_kernel[p]
             full = (1 << d.T) * es
             assert launch[1] == (full // 2 if half else full)
+
+
+def test_wide_first_pass():
+    """A first pass that would hold fewer than 4 row bits (64-byte complex64
+    rows) takes one more tile bit: n = 30 at the default tiles, and a small
+    plan with 2^10 tiles, checked by emulation."""
+    info = Q.describe(30, dtype="c64")
+    assert list(info.pass_bits)[:3] == [10, 10, 10]
+    assert list(info.pass_spec)[:3] == [4, 3, 3]
+    for n, spec in ((28, [4, 3, 4]), (29, [4, 3, 3])):
+        assert list(Q.describe(n, dtype="c64").pass_spec)[:3] == spec
+    assert list(Q.describe(29, dtype="c128").pass_spec)[:3] == [3, 2, 2]  # complex64 only
+    cfg = dict(tile_log2=10, radix_log2=4, spec_log2=3, rev_spec_log2=3)
+    n = 21
+    info = Q.describe(n, -1, "unitary", "c64", "natural", "fused", cfg)
+    assert list(info.pass_bits)[:3] == [7, 7, 7]
+    assert list(info.pass_spec)[:3] == [4, 3, 3]
+    x = I.gaussian(n, 21)
+    for k in (None, 5):
+        y = E.emulate(x, n, -1 if k is None else k, "unitary", "c64", "natural", cfg)
+        assert O.rel_l2(y, O.qft_fused_targets(x, k)) < 2e-6
