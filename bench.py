@@ -251,6 +251,9 @@ def bench_serve(torch, Q, seconds, rate=2000.0):
     return out
 
 
+EXTRA_LEGS = ("aqft", "budget", "c128", "gates", "circuit", "batch", "serve")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +266,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline measurement")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated legs after the headline: " + ",".join(EXTRA_LEGS))
     ap.add_argument("--copy-ref", action="store_true",
                     help="also time a plain device copy of the state (read + write of "
                          "N*S bytes each) as the reference for HBM counters")
@@ -271,6 +276,15 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
+
+    legs = set(EXTRA_LEGS) if args.extras == "all" else set(args.extras.split(","))
+    unknown = legs - set(EXTRA_LEGS)
+    if unknown:
+        print(f"unknown --extras legs {sorted(unknown)}; known: {', '.join(EXTRA_LEGS)}",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.no_extras:
+        legs = set()
 
     import torch
 
@@ -405,20 +419,26 @@ def main():
     plan.close()
     del x
     torch.cuda.empty_cache()
-    if not args.no_extras:
+    if "aqft" in legs:
         print("[bench] aqft sweep", file=sys.stderr, flush=True)
         out["aqft_n28_c64"] = bench_aqft(torch, Q, 28, "c64", [-1, 6, 10, 14, 18], 10)
         out["aqft_n30_c64"] = bench_aqft(torch, Q, 30, "c64", [-1, 6, 10, 14, 18], 10)
+    if "budget" in legs:
         print("[bench] cutoff by accuracy budget", file=sys.stderr, flush=True)
         out["aqft_budget_n28_c64"] = bench_budget(torch, Q, 28, [1e-2, 1e-3, 1e-4], 10)
+    if "c128" in legs:
         print("[bench] complex128", file=sys.stderr, flush=True)
         out["exact_n28_c128"] = bench_aqft(torch, Q, 28, "c128", [-1], 10)[0]
+    if "gates" in legs:
         print("[bench] gate-by-gate schedule", file=sys.stderr, flush=True)
         out["gate_schedule_n24_c64"] = bench_gate_schedule(torch, Q)
+    if "circuit" in legs:
         print("[bench] general circuit", file=sys.stderr, flush=True)
         out["general_circuit_qft_n24_c64"] = bench_circuit(torch, Q)
+    if "batch" in legs:
         print("[bench] batch", file=sys.stderr, flush=True)
         out["batch_512"] = bench_batch(torch, Q)
+    if "serve" in legs:
         print("[bench] serve", file=sys.stderr, flush=True)
         out["serve"] = bench_serve(torch, Q, args.serve_seconds)
         out["p50_ms"] = out["serve"]["continuous"].get("p50_ms")
