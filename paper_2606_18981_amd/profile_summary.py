@@ -82,6 +82,28 @@ def counter_means(path, counter):
     return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
 
 
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
+               "SQ_INSTS_VMEM_WR", "SQ_INSTS_SALU", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES")
+
+
+def sq_per_wave(path):
+    """Per kernel: SQ counters summed over its dispatches and divided by the
+    summed SQ_WAVES (instructions or cycles per wave)."""
+    cur = _db(path).cursor()
+    rows = cur.execute("select kernel_name, counter_name, sum(value) from counters_collection "
+                       "group by kernel_name, counter_name").fetchall()
+    tot = collections.defaultdict(dict)
+    for k, c, v in rows:
+        tot[k][c] = v
+    out = {}
+    for k, cs in tot.items():
+        waves = cs.get("SQ_WAVES")
+        if waves:
+            out[k] = {c: cs[c] / waves for c in cs if c != "SQ_WAVES"}
+            out[k]["waves"] = waves
+    return out
+
+
 def _pooled(means, pred):
     tot, cnt = 0.0, 0
     for (k, _g), (m, c) in means.items():
@@ -167,6 +189,24 @@ def summarize(a):
         out.append(f"Bench line of the traced run: {bench['ms_per_step']:.4f} ms per step, "
                    f"pass mean from HIP events {1e3 * r.get('algorithmic_bytes_per_launch', 0) / max(r.get('achieved', 1), 1e-9) / 1e9:.4f} ms "
                    f"per launch; rocprofv3 average {avg_ns / 1e6 if avg_ns else float('nan'):.4f} ms.")
+    if getattr(a, "sq", None):
+        sq = sq_per_wave(a.sq)
+        cols = [c for c in SQ_COUNTERS if c != "SQ_WAVES"]
+        out.append("")
+        out.append("## SQ counters per wave\n")
+        out.append(f"* SQ counters: `{a.cmd_sq}`\n")
+        out.append("| kernel | waves | " + " | ".join(c[3:] for c in cols) + " |")
+        out.append("|---|---|" + "---|" * len(cols))
+        for k in sorted(sq):
+            if not is_pass(k):
+                continue
+            v = sq[k]
+            out.append(f"| `{k[:90]}` | {v['waves']:.0f} | "
+                       + " | ".join(f"{v.get(c, float('nan')):.0f}" for c in cols) + " |")
+        out.append("")
+        out.append("Instruction counts are per wave. SQ_WAVE_CYCLES and SQ_WAIT_INST_ANY are "
+                   "summed over waves by the hardware, in its own cycle units, and divided "
+                   "the same way.")
     out.append("")
     out.append("## Machine-readable\n")
     out.append("```json")
@@ -209,6 +249,8 @@ def main():
     ap.add_argument("--cmd-fetch", required=True)
     ap.add_argument("--cmd-write", required=True)
     ap.add_argument("--bench-json", default=None)
+    ap.add_argument("--sq", default=None, help="rocprofv3 --pmc run of the SQ counters")
+    ap.add_argument("--cmd-sq", default="")
     ap.add_argument("--title", default="Fused pass kernel, exact QFT n = 28 complex64")
     print(summarize(ap.parse_args()), end="")
 

@@ -64,3 +64,18 @@ def test_summary_scales_counters_by_the_copy_and_round_trips(tmp_path):
     assert PS.load_traffic(str(path).replace("s.md", "none.md"), config) is None
     path.write_text(md.replace(PS.source_digest(), "0" * 16))
     assert PS.load_traffic(str(path), config) is None
+
+
+def test_sq_counters_per_wave(tmp_path):
+    db = sqlite3.connect(tmp_path / "sq.db")
+    db.execute("create table counters_collection (kernel_name, grid_size, counter_name, value)")
+    for _ in range(2):  # two dispatches of 100 waves each
+        for c, v in (("SQ_WAVES", 100), ("SQ_INSTS_VALU", 170000), ("SQ_INSTS_LDS", 9000),
+                     ("SQ_WAVE_CYCLES", 5.0e6)):
+            db.execute("insert into counters_collection values (?,?,?,?)", (PASS, 1 << 20, c, v))
+    db.commit()
+    sq = PS.sq_per_wave(str(tmp_path / "sq.db"))
+    assert sq[PASS]["waves"] == 200
+    assert sq[PASS]["SQ_INSTS_VALU"] == 1700
+    assert sq[PASS]["SQ_INSTS_LDS"] == 90
+    assert sq[PASS]["SQ_WAVE_CYCLES"] == 50000
