@@ -121,12 +121,27 @@ struct GpuDevice {
     int best = 0;
     for (int i = 1; i < (int)srv->streams.size(); ++i)
       if (stream_load[i] < stream_load[best]) best = i;
-    s.stream = best;
     hipStream_t st = srv->streams[best];
+    int rc = enqueue(q, p, s, st);
+    if (rc != QFT_OK) {
+      // part of the request may be on the stream: let it finish before
+      // release() hands the slot's memory to another request
+      (void)hipStreamSynchronize(st);
+      return rc;
+    }
+    s.stream = best;
+    ++stream_load[best];
+    (*res)[r].stream = best;
+    hbm_bytes += (double)p->hp.hbm_bytes() + (double)s.state_bytes;  // + input write
+    return QFT_OK;
+  }
+  // input generation, transform, optional result copy and completion event
+  int enqueue(const qft_request_t &q, qft_plan_t *p, Slot &s, hipStream_t st) {
     int rc = qft_fill_random(s.state, q.n, q.layout, q.dist, q.seed, 0, st);
     if (rc != QFT_OK) return rc;
     rc = qft_execute_ws(p, s.state, s.ws, st);
     if (rc != QFT_OK) return rc;
+    hipError_t he;
     if (q.out) {
       he = hipMemcpyAsync(q.out, s.state, s.state_bytes, hipMemcpyDeviceToDevice, st);
       if (he != hipSuccess) return hip_error(he, "result copy");
@@ -141,9 +156,6 @@ struct GpuDevice {
     free_events.pop_back();
     he = hipEventRecord(s.ev, st);
     if (he != hipSuccess) return hip_error(he, "event record");
-    ++stream_load[best];
-    (*res)[r].stream = best;
-    hbm_bytes += (double)p->hp.hbm_bytes() + (double)s.state_bytes;  // + input write
     return QFT_OK;
   }
   bool poll(int r, int *status) {
