@@ -171,6 +171,38 @@ def test_n28_sampled_bins(torch_cuda, Q, k, dtype):
     assert np.linalg.norm(y) == pytest.approx(np.linalg.norm(x), rel=1e-5 if dtype == "c64" else 1e-12)
 
 
+@pytest.mark.timeout(900)
+def test_n31_maximum_size(torch_cuda, Q):
+    """The largest supported transform, 2^31 complex64 elements (16 GiB, a
+    four-pass plan), exact and AQFT, on sampled bins, and Parseval."""
+    torch = torch_cuda
+    n = 31
+    print("[gpu] n=31 input", flush=True)
+    x = I.gaussian(n, 3100)
+    bins = np.random.default_rng(31).choice(1 << n, 12, replace=False)
+    nx = float(np.sqrt(np.vdot(x, x).real))
+    print("[gpu] n=31 oracle bins", flush=True)
+    refs = {-1: O.dft_bins(x, bins), 10: O.aqft_bins(x, bins, 10)}
+    xd = torch.from_numpy(x.astype(np.complex64)).cuda()
+    del x
+    bd = torch.from_numpy(bins).cuda()
+    for k in (-1, 10):
+        print(f"[gpu] n=31 cutoff={k}", flush=True)
+        plan = Q.Plan(n, k, "unitary", "c64", "natural")
+        assert plan.info.num_passes == 4
+        t = xd.clone()
+        plan.execute(t)
+        torch.cuda.synchronize()
+        y = t[bd].cpu().numpy().astype(np.complex128)
+        ny = float(torch.sqrt((t.real.double() ** 2).sum() + (t.imag.double() ** 2).sum()))
+        del t
+        plan.close()
+        assert O.rel_l2(y, refs[k]) <= TOL["c64"]
+        assert ny == pytest.approx(nx, rel=1e-5)
+    del xd
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("k", [-1, 5])
 def test_wide_first_pass_plan(torch_cuda, Q, k):
     """The first pass with one more tile bit than the others (2^11 against
