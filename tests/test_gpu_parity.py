@@ -203,6 +203,38 @@ def test_n31_maximum_size(torch_cuda, Q):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.timeout(900)
+def test_n30_c128_four_pass(torch_cuda, Q):
+    """complex128 at n = 30 (16 GiB): the planner's four-pass plan, exact and
+    AQFT, on sampled bins, and Parseval."""
+    torch = torch_cuda
+    n = 30
+    print("[gpu] n=30 c128 input", flush=True)
+    x = I.gaussian(n, 3000)
+    bins = np.random.default_rng(30).choice(1 << n, 12, replace=False)
+    nx = float(np.sqrt(np.vdot(x, x).real))
+    print("[gpu] n=30 c128 oracle bins", flush=True)
+    refs = {-1: O.dft_bins(x, bins), 9: O.aqft_bins(x, bins, 9)}
+    xd = torch.from_numpy(x).cuda()
+    del x
+    bd = torch.from_numpy(bins).cuda()
+    for k in (-1, 9):
+        print(f"[gpu] n=30 c128 cutoff={k}", flush=True)
+        plan = Q.Plan(n, k, "unitary", "c128", "natural")
+        assert plan.info.num_passes == 4
+        t = xd.clone()
+        plan.execute(t)
+        torch.cuda.synchronize()
+        y = t[bd].cpu().numpy()
+        ny = float(torch.linalg.vector_norm(t))
+        del t
+        plan.close()
+        assert O.rel_l2(y, refs[k]) <= TOL["c128"]
+        assert ny == pytest.approx(nx, rel=1e-12)
+    del xd
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("k", [-1, 5])
 def test_wide_first_pass_plan(torch_cuda, Q, k):
     """The first pass with one more tile bit than the others (2^11 against

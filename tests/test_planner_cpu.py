@@ -99,11 +99,14 @@ def test_pass_partition_covers_each_qubit_once(n, dtype, order):
 
 
 def test_headline_pass_counts():
-    # n = 28 and 30 in three HBM passes for both element sizes; n <= 13
-    # (complex64) or <= 12 (complex128) in one
+    # n = 28 in three HBM passes for both element sizes, n = 30 in three
+    # (complex64) or four (complex128: a three-pass first pass would read
+    # 64-byte rows); n <= 13 (complex64) or <= 12 (complex128) in one
     for dt in ("c64", "c128"):
         assert Q.describe(28, dtype=dt).num_passes == 3
-        assert Q.describe(30, dtype=dt).num_passes == 3
+    assert Q.describe(30, dtype="c64").num_passes == 3
+    assert Q.describe(30, dtype="c128").num_passes == 4
+    assert list(Q.describe(30, dtype="c128").pass_bits)[:4] == [6, 8, 8, 8]
     assert Q.describe(13, dtype="c64").num_passes == 1
     assert Q.describe(12, dtype="c128").num_passes == 1
 
@@ -319,3 +322,21 @@ def test_wide_first_pass():
     for k in (None, 5):
         y = E.emulate(x, n, -1 if k is None else k, "unitary", "c64", "natural", cfg)
         assert O.rel_l2(y, O.qft_fused_targets(x, k)) < 2e-6
+
+
+def test_four_pass_split():
+    """With four or more passes the bit-reversing last pass keeps 4 spectator
+    bits, the middle passes take the rounded-up share of the rest and the
+    first pass what remains; three-pass plans keep wide middle passes."""
+    assert list(Q.describe(31, dtype="c64").pass_bits)[:4] == [6, 8, 8, 9]
+    assert list(Q.describe(31, dtype="c128").pass_bits)[:4] == [7, 8, 8, 8]
+    for dtype in ("c64", "c128"):
+        info = Q.describe(31, dtype=dtype)
+        assert info.num_passes == 4 and info.pass_spec[3] == 4
+    assert list(Q.describe(28, dtype="c64").pass_bits)[:3] == [9, 10, 9]
+    # every split of a small-tile configuration still covers each qubit once
+    cfg = dict(tile_log2=9, radix_log2=5, spec_log2=4, rev_spec_log2=4)
+    for n in range(10, 26):
+        info = Q.describe(n, -1, "unitary", "c64", "natural", "fused", cfg)
+        bits = list(info.pass_bits)[:info.num_passes]
+        assert sum(bits) == n and min(bits) >= 1
