@@ -171,6 +171,19 @@ def test_n28_sampled_bins(torch_cuda, Q, k, dtype):
     assert np.linalg.norm(y) == pytest.approx(np.linalg.norm(x), rel=1e-5 if dtype == "c64" else 1e-12)
 
 
+@pytest.mark.parametrize("n,dtype", [(25, "c64"), (26, "c64"), (27, "c64"), (29, "c64"),
+                                     (25, "c128"), (26, "c128"), (27, "c128"), (29, "c128")])
+def test_default_splits_sampled_bins(torch_cuda, Q, n, dtype):
+    """Every default three-pass split between n = 25 and 29 (the planner's
+    last-pass and first-pass rules pick them), on sampled bins."""
+    print(f"[gpu] n={n} {dtype} default split", flush=True)
+    x = I.gaussian(n, 2500 + n)
+    y = run_gpu(torch_cuda, Q, x, n, -1, "unitary", dtype, "natural")
+    bins = np.random.default_rng(n).choice(1 << n, 12, replace=False)
+    assert O.rel_l2(y[bins], O.dft_bins(x, bins)) <= TOL[dtype]
+    assert np.linalg.norm(y) == pytest.approx(np.linalg.norm(x), rel=1e-5 if dtype == "c64" else 1e-12)
+
+
 @pytest.mark.timeout(900)
 def test_n31_maximum_size(torch_cuda, Q):
     """The largest supported transform, 2^31 complex64 elements (16 GiB, a

@@ -340,3 +340,18 @@ def test_four_pass_split():
         info = Q.describe(n, -1, "unitary", "c64", "natural", "fused", cfg)
         bits = list(info.pass_bits)[:info.num_passes]
         assert sum(bits) == n and min(bits) >= 1
+
+
+def test_three_pass_last_pass_rule():
+    """Three-pass plans give the bit-reversing last pass T - 4 bits where the
+    first pass keeps at least 6 bits and 256-byte rows, and otherwise split
+    the outer passes evenly."""
+    expect = {("c64", 24): [7, 10, 7], ("c64", 25): [6, 10, 9], ("c64", 26): [7, 10, 9],
+              ("c64", 27): [8, 10, 9], ("c64", 28): [9, 10, 9], ("c64", 29): [9, 10, 10],
+              ("c128", 24): [6, 10, 8], ("c128", 26): [8, 10, 8], ("c128", 27): [8, 10, 9],
+              ("c128", 28): [9, 10, 9]}
+    for (dtype, n), bits in expect.items():
+        info = Q.describe(n, dtype=dtype)
+        assert list(info.pass_bits)[:info.num_passes] == bits, (dtype, n)
+    # bit-reversed plans have no reversing pass: the even split stays
+    assert list(Q.describe(26, dtype="c64", order="bitrev").pass_bits)[:3] != [7, 10, 9]
