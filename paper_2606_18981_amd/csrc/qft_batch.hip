@@ -19,6 +19,11 @@ namespace qft {
 
 namespace {
 
+// The groups of one pass level touch different transforms, so they may run
+// at the same time: up to this many streams (the caller's and the side
+// streams of the batch entry), joined again before the next level.
+constexpr int kForkStreams = 4;
+
 struct BatchEntry {
   std::vector<qft_plan_t *> plans;
   std::vector<void *> ptrs;
@@ -26,15 +31,31 @@ struct BatchEntry {
   std::vector<BatchGroup> groups;    // launch order: pass level by pass level
   void *d_mem = nullptr;             // segments, descriptors, io
   std::vector<void *> workspaces;    // one per natural-order multi-pass job
+  std::vector<int> levels;           // pass level of each group
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int device = 0;
+  // side streams (default priority) and events for the fork / join of the
+  // groups of one level
+  hipStream_t side[kForkStreams - 1] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kForkStreams - 1] = {};
 
   void release() {
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);
     for (void *w : workspaces) hipFree(w);
     if (d_mem) hipFree(d_mem);
+    for (hipStream_t &st : side) {
+      if (st) hipStreamDestroy(st);
+      st = nullptr;
+    }
+    if (fork_ev) hipEventDestroy(fork_ev);
+    fork_ev = nullptr;
+    for (hipEvent_t &ev : join_ev) {
+      if (ev) hipEventDestroy(ev);
+      ev = nullptr;
+    }
     exec = nullptr;
     graph = nullptr;
     d_mem = nullptr;
@@ -144,14 +165,72 @@ int build_entry(BatchEntry *e) {
     g.r = gb[i].r;
     g.shape = gb[i].shape;
     e->groups.push_back(g);
+    e->levels.push_back(gb[i].level);
+  }
+  for (hipStream_t &st : e->side) {
+    he = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (he != hipSuccess) {
+      st = nullptr;
+      return hip_error(he, "batch side stream");
+    }
+  }
+  he = hipEventCreateWithFlags(&e->fork_ev, hipEventDisableTiming);
+  if (he != hipSuccess) {
+    e->fork_ev = nullptr;
+    return hip_error(he, "batch event");
+  }
+  for (hipEvent_t &ev : e->join_ev) {
+    he = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (he != hipSuccess) {
+      ev = nullptr;
+      return hip_error(he, "batch event");
+    }
   }
   return QFT_OK;
 }
 
+// Level by level: a level with one group runs on `s`; the groups of a wider
+// level are dealt round-robin, largest first, over `s` and the side streams,
+// which wait for `s` before and are waited for by `s` after.  Under graph
+// capture the same calls record the fork and join as graph edges.
 hipError_t launch_entry(BatchEntry *e, hipStream_t s) {
-  for (const BatchGroup &g : e->groups) {
-    hipError_t he = launch_batch_group(e->c128, g, s);
+  const size_t ng = e->groups.size();
+  size_t i = 0;
+  while (i < ng) {
+    size_t j = i;
+    while (j < ng && e->levels[j] == e->levels[i]) ++j;
+    if (j - i == 1) {
+      hipError_t he = launch_batch_group(e->c128, e->groups[i], s);
+      if (he != hipSuccess) return he;
+      i = j;
+      continue;
+    }
+    std::vector<size_t> order;
+    for (size_t k = i; k < j; ++k) order.push_back(k);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+      return (uint64_t)e->groups[a].items * e->groups[a].threads >
+             (uint64_t)e->groups[b].items * e->groups[b].threads;
+    });
+    const int used = (int)std::min<size_t>(order.size(), kForkStreams);
+    hipError_t he = hipEventRecord(e->fork_ev, s);
     if (he != hipSuccess) return he;
+    for (int k = 1; k < used; ++k) {
+      he = hipStreamWaitEvent(e->side[k - 1], e->fork_ev, 0);
+      if (he != hipSuccess) return he;
+    }
+    for (size_t k = 0; k < order.size(); ++k) {
+      const int lane = (int)(k % (size_t)used);
+      hipStream_t st = lane == 0 ? s : e->side[lane - 1];
+      he = launch_batch_group(e->c128, e->groups[order[k]], st);
+      if (he != hipSuccess) return he;
+    }
+    for (int k = 1; k < used; ++k) {
+      he = hipEventRecord(e->join_ev[k - 1], e->side[k - 1]);
+      if (he != hipSuccess) return he;
+      he = hipStreamWaitEvent(s, e->join_ev[k - 1], 0);
+      if (he != hipSuccess) return he;
+    }
+    i = j;
   }
   return hipSuccess;
 }
