@@ -274,15 +274,19 @@ int plan_fused(HostPlan &p, std::string &err) {
       // (bit-reversed rows) share the rest evenly
       const int rem = n - (P - 2) * hmax;
       int a = std::max(std::min(amax, (rem + 1) / 2), rem - hmax);
-      // A bit-reversing last pass of T - 4 bits (4 spectator bits) beats a
-      // narrower one, where the first pass still gets at least 6 bits and
-      // rows of at least 256 bytes: complex64 n = 26 [7, 10, 9] 0.65 ms
-      // against [8, 10, 8] 0.70 ms; complex128 n = 27 [9, 10, 8], whose
-      // first pass reads 128-byte rows, is 7 % slower than [8, 10, 9].
+      // A bit-reversing last pass of T - 4 bits (4 spectator bits) beats
+      // the others, where the first pass still gets at least 6 bits and
+      // rows of at least 256 bytes, or 128 bytes through the wider complex64
+      // first-pass tile: complex64 n = 26 [7, 10, 9] 0.65 ms against
+      // [8, 10, 8] 0.70 ms, n = 29 [10, 10, 9] 5.95 ms against [9, 10, 10]
+      // 6.47 ms; complex128 n = 27 [9, 10, 8], whose first pass reads
+      // 128-byte rows from a 2^12 tile, is 7 % slower than [8, 10, 9].
       if (P == 3 && !p.bitrev) {
         const int a4 = std::min(amax, T - 4), f4 = rem - a4;
-        if (a4 > a && f4 >= 6 && f4 <= hmax && (p.elem_bytes << std::min(T - f4, n - f4)) >= 256)
-          a = a4;
+        const bool wide = !p.c128 && T - f4 < 4;  // the first-pass rule below
+        const int spec0 = std::min((wide ? T + 1 : T) - f4, n - f4);
+        const size_t rows = p.elem_bytes << std::max(0, spec0);
+        if (a4 != a && f4 >= 6 && f4 <= hmax && rows >= (wide ? 128u : 256u)) a = a4;
       }
       widths.push_back(rem - a);
       for (int i = 0; i < P - 2; ++i) widths.push_back(hmax);

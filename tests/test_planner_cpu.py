@@ -310,7 +310,7 @@ def test_wide_first_pass():
     info = Q.describe(30, dtype="c64")
     assert list(info.pass_bits)[:3] == [10, 10, 10]
     assert list(info.pass_spec)[:3] == [4, 3, 3]
-    for n, spec in ((28, [4, 3, 4]), (29, [4, 3, 3])):
+    for n, spec in ((28, [4, 3, 4]), (29, [4, 3, 4])):
         assert list(Q.describe(n, dtype="c64").pass_spec)[:3] == spec
     assert list(Q.describe(29, dtype="c128").pass_spec)[:3] == [3, 2, 2]  # complex64 only
     cfg = dict(tile_log2=10, radix_log2=4, spec_log2=3, rev_spec_log2=3)
@@ -344,10 +344,11 @@ def test_four_pass_split():
 
 def test_three_pass_last_pass_rule():
     """Three-pass plans give the bit-reversing last pass T - 4 bits where the
-    first pass keeps at least 6 bits and 256-byte rows, and otherwise split
-    the outer passes evenly."""
+    first pass keeps at least 6 bits and 256-byte rows (128-byte rows through
+    the wider complex64 first-pass tile), and otherwise split the outer
+    passes evenly."""
     expect = {("c64", 24): [7, 10, 7], ("c64", 25): [6, 10, 9], ("c64", 26): [7, 10, 9],
-              ("c64", 27): [8, 10, 9], ("c64", 28): [9, 10, 9], ("c64", 29): [9, 10, 10],
+              ("c64", 27): [8, 10, 9], ("c64", 28): [9, 10, 9], ("c64", 29): [10, 10, 9],
               ("c128", 24): [6, 10, 8], ("c128", 26): [8, 10, 8], ("c128", 27): [8, 10, 9],
               ("c128", 28): [9, 10, 9]}
     for (dtype, n), bits in expect.items():
