@@ -182,6 +182,31 @@ def bench_gate_schedule(torch, Q, n=24, steps=3):
     return rows
 
 
+def bench_configs(torch, Q):
+    """The small configurations: n = 10 complex128 (gate by gate and fused,
+    launch-bound, microseconds) and n = 24 in both element types."""
+    rows = []
+    for n, dtype, schedule, steps in ((10, "c128", "gates", 200), (10, "c128", "fused", 200),
+                                      (24, "c64", "fused", 20), (24, "c128", "fused", 20)):
+        N = 1 << n
+        x = torch.empty(N, dtype=torch.complex64 if dtype == "c64" else torch.complex128,
+                        device="cuda")
+        Q.fill_random(x, "uniform" if n == 10 else "gaussian", seed=1001 if n == 10 else 1002)
+        plan = Q.Plan(n, -1, "unitary", dtype, "natural", schedule)
+        ms = time_plan(torch, Q, plan, x, steps, 5)
+        info = plan.info
+        # one launch per gate sweep (the unitary norm needs no scaling sweep)
+        launches = info.num_passes if schedule == "fused" else (
+            info.gates_h + info.gates_cr + info.gates_swap)
+        rows.append({"n": n, "dtype": dtype, "schedule": schedule, "us": ms * 1e3,
+                     "launches": launches, "gflops_equiv": 5.0 * N * n / (ms * 1e-3) / 1e9,
+                     "hbm_gbs": info.hbm_bytes / (ms * 1e-3) / 1e9})
+        plan.close()
+        del x
+    torch.cuda.empty_cache()
+    return rows
+
+
 def bench_batch(torch, Q, reps=10):
     """512 uneven transforms: the batched launches in one HIP graph, the same
     launches enqueued directly, and one plan execute per transform."""
@@ -251,7 +276,7 @@ def bench_serve(torch, Q, seconds, rate=2000.0):
     return out
 
 
-EXTRA_LEGS = ("aqft", "budget", "c128", "gates", "circuit", "batch", "serve")
+EXTRA_LEGS = ("configs", "aqft", "budget", "c128", "gates", "circuit", "batch", "serve")
 
 
 def main():
@@ -419,6 +444,9 @@ def main():
     plan.close()
     del x
     torch.cuda.empty_cache()
+    if "configs" in legs:
+        print("[bench] n = 10 and n = 24", file=sys.stderr, flush=True)
+        out["small_configs"] = bench_configs(torch, Q)
     if "aqft" in legs:
         print("[bench] aqft sweep", file=sys.stderr, flush=True)
         out["aqft_n28_c64"] = bench_aqft(torch, Q, 28, "c64", [-1, 6, 10, 14, 18], 10)
