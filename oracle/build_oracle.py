@@ -1,6 +1,6 @@
 """Build the oracle's C helper (liboracle_bins.so) with gcc.
 
-Part of the test infrastructure; called by ``__graft_entry__.build()``.
+Part of the test infrastructure; called by the repository's build entry point.
 """
 
 import os

@@ -28,7 +28,7 @@ Simulation"):
   real, so the circuit's matrix becomes its complex conjugate; the QFT and
   AQFT matrices are symmetric, so that is also their adjoint (inverse).
 
-Conventions (readings of the paper; each is also listed in the design doc):
+Conventions (readings of the paper):
   - qubit q_j is bit j of the array index (Sec. 2: a 1-wire gate on q_j is
     I_{2^{n-1-j}} (x) U (x) I_{2^j}; Fig. 1: MSB q_{n-1}, LSB q_0);
   - forward sign exp(-2 pi i jk/N) (Sec. 2 definitions of w_N and R_k);

@@ -12,10 +12,10 @@ sources still have that digest.
 Usage (from the repository root)::
 
     python -m paper_2606_18981_amd.profile_summary \
-        --trace gpurun_out/prof/trace --fetch gpurun_out/prof/fetch \
-        --write gpurun_out/prof/write --copy-bytes 2147483648 \
+        --trace out/prof/trace --fetch out/prof/fetch \
+        --write out/prof/write --copy-bytes 2147483648 \
         --cmd-trace "..." --cmd-fetch "..." --cmd-write "..." \
-        --bench-json gpurun_out/prof/trace.log > profiles/<name>.md
+        --bench-json out/prof/trace.log > profiles/<name>.md
 """
 
 import argparse

@@ -53,9 +53,11 @@ def aqft_error_rows(n, seed):
                      "max_err": O.max_err(y, ref_b)})
     del xt
     torch.cuda.empty_cache()
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(f"gpurun_out/aqft_accuracy_n{n}.json", "w") as f:
-        json.dump(rows, f, indent=1)
+    out_dir = os.environ.get("QFT_RESULTS_DIR")  # optional copy of the table
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, f"aqft_accuracy_n{n}.json"), "w") as f:
+            json.dump(rows, f, indent=1)
     print(json.dumps(rows), flush=True)
     return rows
 
