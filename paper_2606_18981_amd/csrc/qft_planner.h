@@ -31,6 +31,7 @@ struct HostPlan {
   bool inverse = false; // conjugate-phase circuit (QFT_INVERSE)
   Schedule schedule = Schedule::Fused;
   qft_config_t cfg{};  // resolved configuration
+  bool auto_radix = true;  // radix_log2 not given: the planner may pick it
   size_t elem_bytes = 0;
   size_t state_bytes = 0;
   size_t ws_bytes = 0;

@@ -356,3 +356,13 @@ def test_three_pass_last_pass_rule():
         assert list(info.pass_bits)[:info.num_passes] == bits, (dtype, n)
     # bit-reversed plans have no reversing pass: the even split stays
     assert list(Q.describe(26, dtype="c64", order="bitrev").pass_bits)[:3] != [7, 10, 9]
+
+
+def test_one_pass_radix():
+    """One-pass plans take the fewest register groups, then the most
+    threads, unless the configuration names a radix."""
+    for dtype in ("c64", "c128"):
+        lay = Q.layout_flags(dtype)
+        got = {n: E.get_pass(n, -1, "unitary", lay, None, 0)[0].r for n in (9, 10, 11, 12, 13)}
+        assert got == {9: 5, 10: 5, 11: 4, 12: 4, 13: 5}, (dtype, got)
+        assert E.get_pass(12, -1, "unitary", lay, dict(radix_log2=5), 0)[0].r == 5
