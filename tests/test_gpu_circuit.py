@@ -76,17 +76,27 @@ def diagonal(rng):
     return np.diag(rng.uniform(0.9, 1.1, 2) * np.exp(1j * rng.uniform(0, 2 * np.pi, 2)))
 
 
+def phase(rng):
+    """diag(1, e^{i phi}): a phase gate."""
+    return np.diag([1.0, np.exp(1j * rng.uniform(-np.pi, np.pi))])
+
+
 def mixed_gates(n, count, seed):
-    """Non-diagonal and diagonal one-qubit gates, controlled gates of both
-    kinds and swaps, on qubits anywhere in the register."""
+    """Non-diagonal, diagonal and phase one-qubit gates, controlled gates of
+    all three kinds and swaps, on qubits anywhere in the register."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
-        kind = rng.integers(0, 5) if n > 1 else rng.integers(0, 2)
+        kind = rng.integers(0, 7) if n > 1 else rng.integers(0, 2)
         if kind == 0:
             out.append(("U", int(rng.integers(0, n)), unitary(rng)))
         elif kind == 1:
             out.append(("U", int(rng.integers(0, n)), diagonal(rng)))
+        elif kind == 5:
+            out.append(("U", int(rng.integers(0, n)), phase(rng)))
+        elif kind == 6:
+            a, b = rng.choice(n, 2, replace=False)
+            out.append(("CU", int(a), int(b), phase(rng)))
         else:
             a, b = rng.choice(n, 2, replace=False)
             if kind == 2:
