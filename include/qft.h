@@ -186,6 +186,13 @@ const char *qft_last_error(void);
 
 int qft_plan_info(const qft_plan_t *plan, qft_plan_info_t *out);
 
+/* Device memory the plan holds, in bytes: its twiddle tables, its workspace
+ * (none for QFT_PLAN_NO_WORKSPACE plans) and, once qft_execute_norm has run,
+ * its norm partial sums.  The state array is the caller's and is not
+ * counted.  For admission by HBM budget (the plan / execute split of
+ * Sec. 3.1).  0 for NULL.                                                   */
+size_t qft_plan_device_bytes(const qft_plan_t *plan);
+
 /* Run only the host planner (no device use) and describe the plan that
  * qft_plan_config would build.                                             */
 int qft_plan_describe(int n, int cutoff, int norm, int layout,

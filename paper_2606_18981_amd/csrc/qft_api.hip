@@ -272,6 +272,13 @@ int qft_plan_info(const qft_plan_t *plan, qft_plan_info_t *out) {
   return QFT_OK;
 }
 
+size_t qft_plan_device_bytes(const qft_plan_t *plan) {
+  if (!plan) return 0;
+  const HostPlan &hp = plan->hp;
+  return hp.tables.size() + (plan->d_ws ? hp.ws_bytes : 0) +
+         (plan->d_norm ? (size_t)plan->norm_parts * sizeof(double) : 0);
+}
+
 int qft_plan_describe(int n, int cutoff, int norm, int layout, const qft_config_t *config,
                       qft_plan_info_t *out) {
   clear_error();

@@ -114,6 +114,7 @@ def _load():
         "qft_destroy": (None, [P]),
         "qft_last_error": (ctypes.c_char_p, []),
         "qft_plan_info": (I, [P, ctypes.POINTER(PlanInfo)]),
+        "qft_plan_device_bytes": (ctypes.c_size_t, [P]),
         "qft_plan_describe": (I, [I, I, I, I, ctypes.POINTER(Config), ctypes.POINTER(PlanInfo)]),
         "qft_plan_set_timing": (I, [P, I]),
         "qft_plan_pass_times": (I, [P, ctypes.POINTER(ctypes.c_double), I,
@@ -251,6 +252,11 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    @property
+    def device_bytes(self) -> int:
+        """Device memory the plan holds (tables, workspace, norm partials)."""
+        return int(lib.qft_plan_device_bytes(self._h))
 
     def _check_tensor(self, x):
         import torch

@@ -413,6 +413,13 @@ def test_abi_errors_and_workspace(torch_cuda, Q):
     plan.execute(c, stream=s2, workspace=ws2)
     torch.cuda.synchronize()
     assert torch.equal(a, b) and torch.equal(a, c)
+    # device memory the plan holds: tables + its own workspace
+    info = plan.info
+    assert plan.device_bytes == info.table_bytes + info.workspace_bytes
+    bare = Q.Plan(n, -1, "unitary", "c64", "natural", workspace=False)
+    assert bare.device_bytes == bare.info.table_bytes
+    bare.close()
+    assert Q.lib.qft_plan_device_bytes(None) == 0
     plan.close()
 
 
