@@ -99,7 +99,9 @@ struct DevDiag {
 
 struct CircPass {
   int32_t n, T, TL, nfree;
-  int32_t nops, pad;
+  int32_t nops;
+  int32_t has_perm;     // the pass ends with swaps, folded into the store
+  uint32_t perm_w[4];   // store: bit q of a tile element comes from position perm[q]
   uint32_t gpos_w[4];   // global bit of tile position q (packed 4 per word)
   uint32_t free_w[8];   // global bits of the non-tile positions, ascending
   uint32_t ntiles;
@@ -274,6 +276,7 @@ __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d,
   C *lds = reinterpret_cast<C *>(circ_smem);
   __shared__ RunTables<Real> tabs[S::kSlots];
   __shared__ uint64_t alo[1 << kLowBits], ahi[1 << S::kHighBits];
+  __shared__ uint32_t plo[1 << kLowBits], phi[1 << S::kHighBits];  // trailing swaps
   const uint32_t tid = threadIdx.x;
   uint32_t tile = blockIdx.x;
   if (d.xcd_remap) {
@@ -290,14 +293,24 @@ __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d,
   if (tid < 64u) {
     if (tid <= mlo) {
       uint64_t g = 0;
-      for (int q = 0; q < TL; ++q) g |= (uint64_t)((tid >> q) & 1u) << pos_get(d.gpos_w, q);
+      uint32_t sp = 0;
+      for (int q = 0; q < TL; ++q) {
+        g |= (uint64_t)((tid >> q) & 1u) << pos_get(d.gpos_w, q);
+        sp |= ((tid >> q) & 1u) << pos_get(d.perm_w, q);
+      }
       alo[tid] = g;
+      plo[tid] = sp;
     }
   } else if (tid - 64u < (1u << TH)) {
     const uint32_t j = tid - 64u;
     uint64_t g = base;
-    for (int q = 0; q < TH; ++q) g |= (uint64_t)((j >> q) & 1u) << pos_get(d.gpos_w, TL + q);
+    uint32_t sp = 0;
+    for (int q = 0; q < TH; ++q) {
+      g |= (uint64_t)((j >> q) & 1u) << pos_get(d.gpos_w, TL + q);
+      sp |= ((j >> q) & 1u) << pos_get(d.perm_w, TL + q);
+    }
     ahi[j] = g;
+    phi[j] = sp;
   }
   __syncthreads();
   const uint32_t TE = 1u << d.T;
@@ -370,7 +383,13 @@ __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d,
     }
     __syncthreads();
   }
-  for (uint32_t e = tid; e < TE; e += kCircThreads) psi[alo[e & mlo] | ahi[e >> TL]] = lds[lidx(e)];
+  // the trailing swaps: tile element e takes the element at plo | phi
+  if (d.has_perm) {
+    for (uint32_t e = tid; e < TE; e += kCircThreads)
+      psi[alo[e & mlo] | ahi[e >> TL]] = lds[lidx(plo[e & mlo] | phi[e >> TL])];
+  } else {
+    for (uint32_t e = tid; e < TE; e += kCircThreads) psi[alo[e & mlo] | ahi[e >> TL]] = lds[lidx(e)];
+  }
 }
 
 }  // namespace
@@ -533,6 +552,28 @@ void build_pass_image(const qft_circuit_s *c, int g0, int g1, const std::vector<
 // the stage's table slots.  Each stage is a header followed by its pair
 // operations, whose targets become indices into the stage's (ascending)
 // positions.
+// Fold the swaps that end a pass into its store: bit q of a stored tile
+// element is bit perm[q] of the element read from LDS.  A swap of positions
+// (a, b) maps state[e] to state[P(e)] with P exchanging bits a and b, so
+// after swaps P_1 ... P_k the store reads P_1(P_2(... P_k(e))).
+template <typename Real>
+void fold_trailing_swaps(PassImage<Real> &img, CircPass &p) {
+  for (int q = 0; q < p.T; ++q) pos_set(p.perm_w, q, (uint32_t)q);
+  size_t first = img.ops.size();
+  while (first > 0 && img.ops[first - 1].kind == kOpSwap) --first;
+  if (first == img.ops.size()) return;
+  for (int q = 0; q < p.T; ++q) {
+    int at = q;
+    for (size_t i = img.ops.size(); i-- > first;) {
+      const int a = img.ops[i].a, b = img.ops[i].b;
+      at = at == a ? b : (at == b ? a : at);
+    }
+    pos_set(p.perm_w, q, (uint32_t)at);
+  }
+  img.ops.resize(first);
+  p.has_perm = 1;
+}
+
 template <typename Real>
 void form_stages(PassImage<Real> &img) {
   const int kmax = Shape<Real>::kStageBits, slots = Shape<Real>::kSlots;
@@ -678,11 +719,13 @@ int compile(qft_circuit_s *c, int tile_qubits, bool upload) {
     if (c->c128) {
       img64.emplace_back();
       build_pass_image<double>(c, runs[r].first, runs[r].second, tpos, p.TL, img64.back());
+      fold_trailing_swaps<double>(img64.back(), p);
       form_stages<double>(img64.back());
       p.nops = (int)img64.back().ops.size();
     } else {
       img32.emplace_back();
       build_pass_image<float>(c, runs[r].first, runs[r].second, tpos, p.TL, img32.back());
+      fold_trailing_swaps<float>(img32.back(), p);
       form_stages<float>(img32.back());
       p.nops = (int)img32.back().ops.size();
     }
