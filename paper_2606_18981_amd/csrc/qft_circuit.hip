@@ -63,14 +63,15 @@ struct GateRec {
 //    all the stage's gates (and their diagonal runs) there.
 //  - kOpPair: a 2x2 matrix on the stage position with index `a`, optionally
 //    controlled, then the diagonal run that follows it in the circuit.
-//  - kOpSwap: swap of two tile qubits.
 //  - kOpDiag: a diagonal run with no non-diagonal gate before it in the pass.
+// Swaps move no data in the pass: they relabel tile positions, operands are
+// LDS (physical) positions, and the store applies the final relabelling.
 // A diagonal run (consecutive diagonal gates, which commute) has its records
 // split over a low table (low tile positions, global bits and at most one
 // high position hx), a high table (high positions and global bits) and a
 // list evaluated per element (gates pairing a low position with a high
 // position other than hx).  The tables are built per tile.
-enum OpKind : int32_t { kOpPair = 0, kOpSwap = 1, kOpDiag = 2, kOpStage = 3 };
+enum OpKind : int32_t { kOpPair = 0, kOpDiag = 2, kOpStage = 3 };
 
 template <typename Real>
 struct DevOp {
@@ -266,8 +267,9 @@ __device__ __forceinline__ void stage_sweep(c2<Real> *lds, const DevOp<Real> *so
 
 // One pass: load the tile into LDS (element e = sum over tile positions q of
 // bit q of e at global bit gpos[q], plus the tile's free bits), apply the
-// pass's operations in order (stages in registers, swaps and lone diagonal
-// runs as LDS sweeps), one barrier after each, store the tile.
+// pass's operations in order (stages in registers, lone diagonal runs as LDS
+// sweeps), one barrier after each, and store the tile through the pass's
+// relabelling of tile positions (its swaps).
 template <typename Real>
 __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d, c2<Real> *psi) {
   using C = c2<Real>;
@@ -343,17 +345,6 @@ __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d,
         default: break;
       }
       oi += 1 + cnt;
-    } else if (kind == kOpSwap) {
-      const int a = op.a, b = op.b;
-      const int lo = a < b ? a : b, hi = a < b ? b : a;
-      for (uint32_t p = tid; p < (TE >> 2); p += kCircThreads) {
-        const uint32_t z = insert_zero(insert_zero(p, lo), hi);
-        const uint32_t e0 = lidx(z | (1u << a)), e1 = lidx(z | (1u << b));
-        const C x = lds[e0];
-        lds[e0] = lds[e1];
-        lds[e1] = x;
-      }
-      oi += 1;
     } else {
       build_tables<Real>(op, recs, tabs[0], TL, TH, base, tid);
       __syncthreads();
@@ -460,8 +451,15 @@ c2<Real> cval(const double *u, int i) {
 
 template <typename Real>
 void build_pass_image(const qft_circuit_s *c, int g0, int g1, const std::vector<int> &tpos,
-                      int TL, PassImage<Real> &img) {
-  auto enc = [&](int q) { return tpos[q] >= 0 ? tpos[q] : -1 - q; };
+                      int TL, PassImage<Real> &img, CircPass &pass) {
+  // Swaps move no data: lab[q] is the LDS bit that holds logical tile
+  // position q.  A swap of logical positions a and b maps state[e] to
+  // state[P(e)], P exchanging bits a and b, so it exchanges lab[a] and
+  // lab[b]; every later operand is a physical position, and the store
+  // writes logical element e from the LDS element with bit lab[q] = bit q.
+  std::vector<int> lab(pass.T);
+  for (int q = 0; q < pass.T; ++q) lab[q] = q;
+  auto enc = [&](int q) { return tpos[q] >= 0 ? lab[tpos[q]] : -1 - q; };
   std::vector<DevDiag<Real>> run;
   // Split a run of diagonal records over the low table (low positions,
   // global bits and the high position hx), the high table (high positions
@@ -528,23 +526,28 @@ void build_pass_image(const qft_circuit_s *c, int g0, int g1, const std::vector<
       run.push_back(r);
       continue;
     }
+    if (g.kind == kSwap) {
+      // diagonal records already hold physical positions, so a run may
+      // continue across the relabelling
+      std::swap(lab[tpos[g.a]], lab[tpos[g.b]]);
+      continue;
+    }
     flush();
     DevOp<Real> op;
     memset(&op, 0, sizeof(op));
     op.hx = -1;  // no diagonal run (yet)
-    if (g.kind == kSwap) {
-      op.kind = kOpSwap;
-      op.a = tpos[g.a];
-      op.b = tpos[g.b];
-    } else {
-      op.kind = kOpPair;
-      op.a = tpos[g.kind == kOne ? g.a : g.b];
-      op.b = g.kind == kOne ? kNoControl : enc(g.a);
-      for (int j = 0; j < 4; ++j) op.u[j] = cval<Real>(g.u, j);
-    }
+    op.kind = kOpPair;
+    op.a = lab[tpos[g.kind == kOne ? g.a : g.b]];
+    op.b = g.kind == kOne ? kNoControl : enc(g.a);
+    for (int j = 0; j < 4; ++j) op.u[j] = cval<Real>(g.u, j);
     img.ops.push_back(op);
   }
   flush();
+  pass.has_perm = 0;
+  for (int q = 0; q < pass.T; ++q) {
+    pos_set(pass.perm_w, q, (uint32_t)lab[q]);
+    if (lab[q] != q) pass.has_perm = 1;
+  }
 }
 
 // Group consecutive pair operations into stages: greedily, while their
@@ -552,28 +555,6 @@ void build_pass_image(const qft_circuit_s *c, int g0, int g1, const std::vector<
 // the stage's table slots.  Each stage is a header followed by its pair
 // operations, whose targets become indices into the stage's (ascending)
 // positions.
-// Fold the swaps that end a pass into its store: bit q of a stored tile
-// element is bit perm[q] of the element read from LDS.  A swap of positions
-// (a, b) maps state[e] to state[P(e)] with P exchanging bits a and b, so
-// after swaps P_1 ... P_k the store reads P_1(P_2(... P_k(e))).
-template <typename Real>
-void fold_trailing_swaps(PassImage<Real> &img, CircPass &p) {
-  for (int q = 0; q < p.T; ++q) pos_set(p.perm_w, q, (uint32_t)q);
-  size_t first = img.ops.size();
-  while (first > 0 && img.ops[first - 1].kind == kOpSwap) --first;
-  if (first == img.ops.size()) return;
-  for (int q = 0; q < p.T; ++q) {
-    int at = q;
-    for (size_t i = img.ops.size(); i-- > first;) {
-      const int a = img.ops[i].a, b = img.ops[i].b;
-      at = at == a ? b : (at == b ? a : at);
-    }
-    pos_set(p.perm_w, q, (uint32_t)at);
-  }
-  img.ops.resize(first);
-  p.has_perm = 1;
-}
-
 template <typename Real>
 void form_stages(PassImage<Real> &img) {
   const int kmax = Shape<Real>::kStageBits, slots = Shape<Real>::kSlots;
@@ -718,14 +699,12 @@ int compile(qft_circuit_s *c, int tile_qubits, bool upload) {
     p.xcd_remap = (p.ntiles >= 8 && p.ntiles % 8 == 0) ? 1 : 0;
     if (c->c128) {
       img64.emplace_back();
-      build_pass_image<double>(c, runs[r].first, runs[r].second, tpos, p.TL, img64.back());
-      fold_trailing_swaps<double>(img64.back(), p);
+      build_pass_image<double>(c, runs[r].first, runs[r].second, tpos, p.TL, img64.back(), p);
       form_stages<double>(img64.back());
       p.nops = (int)img64.back().ops.size();
     } else {
       img32.emplace_back();
-      build_pass_image<float>(c, runs[r].first, runs[r].second, tpos, p.TL, img32.back());
-      fold_trailing_swaps<float>(img32.back(), p);
+      build_pass_image<float>(c, runs[r].first, runs[r].second, tpos, p.TL, img32.back(), p);
       form_stages<float>(img32.back());
       p.nops = (int)img32.back().ops.size();
     }
