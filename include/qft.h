@@ -220,7 +220,10 @@ int qft_plan_pass_times(qft_plan_t *plan, double *ms, int max, long long *execs)
  * natural-order multi-pass transform) and captures the launches into a HIP
  * graph; later calls replay the graph.  Plans must be fused-schedule plans
  * of one element type.  Destroying a plan drops the cached sets that use
- * it.                                                                       */
+ * it.  At most 64 sets stay cached: a new set beyond that synchronises the
+ * device once and releases the oldest.  The graph's launches of one pass
+ * level are spread over the caller's stream and three streams of the set,
+ * joined before the next level.                                            */
 int qft_execute_batch(qft_plan_t *const *plans, void *const *dev_ptrs,
                       int count, qft_stream_t stream);
 

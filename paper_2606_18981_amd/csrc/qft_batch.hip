@@ -24,6 +24,10 @@ namespace {
 // streams of the batch entry), joined again before the next level.
 constexpr int kForkStreams = 4;
 
+// Cached (plans, pointers) sets, each with its graph, workspaces, streams
+// and events; beyond this many the oldest is released.
+constexpr size_t kMaxCachedSets = 64;
+
 struct BatchEntry {
   std::vector<qft_plan_t *> plans;
   std::vector<void *> ptrs;
@@ -317,6 +321,14 @@ int qft_execute_batch_ex(qft_plan_t *const *plans, void *const *dev_ptrs, int co
       e->release();
       delete e;
       return rc;
+    }
+    if (g_cache.size() >= kMaxCachedSets) {
+      // the oldest set may still run on some stream: wait for the device
+      // before its graph, workspaces and streams are released
+      hipDeviceSynchronize();
+      g_cache.front()->release();
+      delete g_cache.front();
+      g_cache.erase(g_cache.begin());
     }
     g_cache.push_back(e);
   }

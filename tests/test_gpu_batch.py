@@ -133,3 +133,27 @@ def test_batch_with_inverse_plans(env):
         assert O.rel_l2(t.cpu().numpy().astype(np.complex128), ref) <= 1e-5
     for p in plans:
         p.close()
+
+
+def test_cache_bound_evicts_oldest(env):
+    """More than 64 distinct (plans, pointers) sets: the oldest cached sets
+    are released and every call still gives the result of running alone."""
+    torch, Q = env
+    plan = Q.Plan(10, -1, "unitary", "c64", "natural")
+    x = I.uniform_pm1(10, 4242)
+    ref = alone(torch, Q, [plan], [x], "c64")[0]
+    keep = []  # every tensor stays alive, so each call is a new pointer set
+    for i in range(70):
+        t = torch.from_numpy(x.astype(np.complex64)).cuda()
+        keep.append(t)
+        Q.execute_batch([plan], [t], graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(t.cpu().numpy(), ref), f"set {i}"
+    assert len({t.data_ptr() for t in keep}) == 70
+    # the first (evicted) set runs again, rebuilt
+    t0 = keep[0]
+    t0.copy_(torch.from_numpy(x.astype(np.complex64)))
+    Q.execute_batch([plan], [t0], graph=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(t0.cpu().numpy(), ref)
+    plan.close()
