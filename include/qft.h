@@ -200,8 +200,11 @@ int qft_plan_describe(int n, int cutoff, int norm, int layout,
 
 /* ---- measurement --------------------------------------------------------- */
 
-/* When enabled, qft_execute records a HIP event pair around every kernel
- * launch it enqueues and accumulates per-pass device times.                 */
+/* When enabled, qft_execute records HIP events around every kernel launch
+ * it enqueues (one more event per launch, plus one per execute).  The events
+ * of all executes since the last qft_plan_pass_times call are kept, and
+ * reused after it: call it now and then while timing is on.  Executes of a
+ * timed plan must be ordered on one stream.                                 */
 int qft_plan_set_timing(qft_plan_t *plan, int enable);
 /* Synchronises on the recorded events and returns the mean milliseconds per
  * execute of each pass in ms[0..count) (count = min(max, num_passes)) and
