@@ -486,6 +486,25 @@ void build_pass_image(const qft_circuit_s *c, int g0, int g1, const std::vector<
       else if (!other_high) lo.push_back(r);
       else cross.push_back(r);
     }
+    // Each table entry multiplies all its table's records, and the two
+    // tables are built side by side: records on global bits and hx only fit
+    // either table, so move them to the low one until the counts balance.
+    {
+      auto movable = [&](const DevDiag<Real> &r) {
+        return (r.q1 < 0 || r.q1 == hx) && (r.q0 < 0 || r.q0 == hx);
+      };
+      std::vector<DevDiag<Real>> stay;
+      size_t nhi = hi.size();
+      for (const DevDiag<Real> &r : hi) {
+        if (movable(r) && lo.size() + 1 <= nhi - 1) {
+          lo.push_back(r);
+          --nhi;
+        } else {
+          stay.push_back(r);
+        }
+      }
+      hi.swap(stay);
+    }
     // the run rides on the pair operation just before it, if there is one
     const bool attach = !img.ops.empty() && img.ops.back().kind == kOpPair;
     if (!attach) {
