@@ -184,14 +184,18 @@ def bench_gate_schedule(torch, Q, n=24, steps=3):
 
 def bench_configs(torch, Q):
     """The small configurations: n = 10 complex128 (gate by gate and fused,
-    launch-bound, microseconds) and n = 24 in both element types."""
+    launch-bound, microseconds), n = 12, 14 and 22 complex64 and n = 24 in
+    both element types."""
     rows = []
+    # n = 12, 14 and 22 complex64 are the sizes the paper times (FP32)
     for n, dtype, schedule, steps in ((10, "c128", "gates", 200), (10, "c128", "fused", 200),
+                                      (12, "c64", "fused", 200), (14, "c64", "fused", 200),
+                                      (22, "c64", "fused", 50),
                                       (24, "c64", "fused", 20), (24, "c128", "fused", 20)):
         N = 1 << n
         x = torch.empty(N, dtype=torch.complex64 if dtype == "c64" else torch.complex128,
                         device="cuda")
-        Q.fill_random(x, "uniform" if n == 10 else "gaussian", seed=1001 if n == 10 else 1002)
+        Q.fill_random(x, "uniform" if n <= 14 else "gaussian", seed=1001 if n <= 14 else 1002)
         plan = Q.Plan(n, -1, "unitary", dtype, "natural", schedule)
         ms = time_plan(torch, Q, plan, x, steps, 5)
         info = plan.info
