@@ -27,28 +27,90 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
-def cpu_baseline(n_sample: int = 26):
-    """Time the FP64 oracle (per-target fused numpy form) on one transform."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline_and_accuracy(torch, Q, n, dtype, cutoff):
+    """The FP64 oracle timed on the host cores on the headline workload, and
+    the accuracy of the timed plan against it.
+
+    The input is the seed-1003 N(0,1) workload drawn on the host (numpy), so
+    that nothing the oracle sees comes from the device.  The GPU runs the same
+    plan and kernels as the timed steps on it; the whole output is compared
+    with the oracle's whole-vector per-target form (oracle.qft_state_c, the
+    plain C form on every host core), and 2^20 seeded bins with the FP64
+    exact DFT through the library FFT (workers = every host core), which is
+    also timed as the multi-core host FFT context."""
     import numpy as np
 
     import oracle as O
     from paper_2606_18981_amd import inputs as I
 
-    x = I.gaussian(n_sample, 1003)
+    N = 1 << n
+    k = None if cutoff < 0 else cutoff
+    x = I.gaussian(n, 1003)
+    npdt = np.complex64 if dtype == "c64" else np.complex128
+    plan = Q.Plan(n, cutoff, "unitary", dtype, "natural")
+    t = torch.from_numpy(x.astype(npdt)).cuda()
+    plan.execute(t)
+    torch.cuda.synchronize()
+    y = t.cpu().numpy()
+    del t
+    plan.close()
+    torch.cuda.empty_cache()
+
     t0 = time.perf_counter()
-    O.qft_fused_targets(x, None, "unitary", "natural")
-    dt = time.perf_counter() - t0
-    N = 1 << n_sample
-    return {
-        "value": 5.0 * N * n_sample / dt / 1e9,
+    ref = O.qft_state_c(x, k)
+    dt_oracle = time.perf_counter() - t0
+    whole = O.error_norms(y, ref)
+    del ref
+    nproc = os.cpu_count()
+    t0 = time.perf_counter()
+    exact = O.dft_library(x, workers=nproc)
+    dt_fft = time.perf_counter() - t0
+    bins = np.random.default_rng(1003).choice(N, min(N, 1 << 20), replace=False)
+    yb = y[bins].astype(np.complex128)
+    eb = exact[bins]
+    del exact
+    threads = O.c_oracle_threads()
+    flops = 5.0 * N * n
+    baseline = {
+        "value": flops / dt_oracle / 1e9,
         "unit": "GFLOP/s-equiv (5N log2 N / t)",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"one exact n={n_sample} complex128 transform (oracle per-target fused form, "
-                  f"numpy FP64, single thread), {dt:.2f} s",
-        "seconds": dt,
-        "nproc": os.cpu_count(),
+        "sample": f"one n={n} {'exact' if k is None else f'k={k}'} transform of the seed-1003 "
+                  f"N(0,1) input: the oracle's whole-vector per-target form in FP64 "
+                  f"(plain C, {threads} OpenMP threads), {dt_oracle:.2f} s",
+        "seconds": dt_oracle,
+        "nproc": nproc,
+        "cpu_model": _cpu_model(),
+        "host_fft_context": {
+            "what": f"FP64 library FFT (scipy.fft, workers={nproc}) of the same input, "
+                    "the exact DFT only",
+            "seconds": dt_fft,
+            "gflops_equiv": flops / dt_fft / 1e9,
+        },
     }
+    accuracy = {
+        "input": f"seed-1003 N(0,1) re/im, n={n}, drawn on the host; the timed plan "
+                 f"({dtype}) run once on it",
+        "vs_oracle_whole_vector": {"rel_l2": whole["rel_l2"], "max_err": whole["max_err"],
+                                   "elements": N},
+        "vs_exact_dft_2^20_bins": {"rel_l2": O.rel_l2(yb, eb), "max_err": O.max_err(yb, eb),
+                                   "bins": int(bins.size)},
+        "max_err_definition": "max |y - ref| over the RMS amplitude of ref",
+    }
+    if k is not None:
+        accuracy["expected_aqft_rel_l2_vs_exact"] = O.aqft_expected_relerr_gaussian(n, k)
+    return baseline, accuracy
 
 
 def profile_name(n, dtype, cutoff):
@@ -357,9 +419,6 @@ def main():
     gflops = flops / (ms_per_step * 1e-3) / 1e9
     state_bytes = info.state_bytes
     per_launch_bytes = 2 * state_bytes  # one read and one write of the state
-    # dominant kernel: every pass launches the fused-pass kernel; the
-    # roofline uses its mean launch time over the timed region
-    mean_pass_ms = sum(pass_ms) / len(pass_ms)
     real = "float" if args.dtype == "c64" else "double"
     names = []
     for p in range(info.num_passes):
@@ -370,8 +429,16 @@ def main():
             names.append(f"k_fused_pass2<{real}, 5, {(sh - 1) % 5 + 1}, {ext}, {st}>")
         else:
             names.append(f"k_fused_pass<{real}, {info.config.radix_log2}>")
-    kernel = "; ".join(names)
-    achieved = per_launch_bytes / (mean_pass_ms * 1e-3) / 1e9
+    # every pass is one launch of a pass kernel instance; the dominant kernel
+    # is the slowest pass (HIP events on the launch stream, timed region)
+    per_pass = [{"pass": p, "kernel": names[p], "qubits": info.pass_bits[p],
+                 "ms": pass_ms[p],
+                 "gbs": per_launch_bytes / (pass_ms[p] * 1e-3) / 1e9,
+                 "frac": per_launch_bytes / (pass_ms[p] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                for p in range(info.num_passes)]
+    dom = max(range(info.num_passes), key=lambda p: pass_ms[p])
+    achieved = per_pass[dom]["gbs"]
+    mean_pass_ms = sum(pass_ms) / len(pass_ms)
     hbm_gbs = info.hbm_bytes / (ms_per_step * 1e-3) / 1e9
 
     out = {
@@ -405,27 +472,33 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": f"fused pass kernels, mean over the plan's {info.num_passes} passes: {kernel}",
+            "kernel": names[dom],
+            "dominant": f"pass {dom} ({info.pass_bits[dom]} qubits), the slowest of the plan's "
+                        f"{info.num_passes} pass launches",
             "algorithmic_bytes_per_launch": per_launch_bytes,
+            "per_pass": per_pass,
+            "mean_pass_frac": per_launch_bytes / (mean_pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
     }
-    # HBM traffic from the committed rocprofv3 counter summary of this same
-    # workload and kernel sources (FETCH_SIZE and WRITE_SIZE, each scaled by
-    # what it reads for a plain device copy of known size); null otherwise
+    # HBM traffic of the dominant kernel from the committed rocprofv3 counter
+    # summary of this same workload and kernel sources (FETCH_SIZE and
+    # WRITE_SIZE, each scaled by what it reads for a plain device copy of
+    # known size); null otherwise
     from paper_2606_18981_amd import profile_summary as PS
     prof = os.path.join(ROOT, "profiles", profile_name(n, args.dtype, args.cutoff))
-    out["roofline"]["traffic"] = PS.load_traffic(prof, out["config"])
+    tr = PS.load_traffic(prof, out["config"], names[dom])
+    out["roofline"]["traffic"] = tr
     out["roofline"]["traffic_source"] = os.path.relpath(prof, ROOT)
     # HBM bytes per gate of the circuit (H, controlled phases, swaps): the
     # fused plan's passes shared over its gates, from the algorithmic bytes
     # and from the counters; a gate-by-gate sweep moves 2*N*S per gate
     gates = info.gates_h + info.gates_cr + info.gates_swap
-    traffic = out["roofline"]["traffic"]
+    plan_traffic = PS.load_plan_traffic(prof, out["config"])
     out["bytes_per_gate"] = {
         "gates": {"h": info.gates_h, "controlled_phase": info.gates_cr,
                   "swap": info.gates_swap},
         "algorithmic": info.hbm_bytes / gates,
-        "counters": traffic * info.num_passes / gates if traffic else None,
+        "counters": plan_traffic / gates if plan_traffic else None,
         "gate_by_gate_sweep": per_launch_bytes,
     }
     if args.copy_ref:
@@ -476,8 +549,9 @@ def main():
         out["p50_ms"] = out["serve"]["continuous"].get("p50_ms")
         out["p99_ms"] = out["serve"]["continuous"].get("p99_ms")
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline()
+        print("[bench] cpu baseline and accuracy of the timed plan", file=sys.stderr, flush=True)
+        out["cpu_baseline"], out["accuracy"] = cpu_baseline_and_accuracy(
+            torch, Q, n, args.dtype, args.cutoff)
     print(json.dumps(out), flush=True)
 
 

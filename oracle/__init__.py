@@ -10,6 +10,8 @@ Contents
                  per-target fused (DIF) form, metrics and AQFT error formulas.
   dft_bins.c     plain C per-output-bin sums (exact DFT and closed-form AQFT)
                  used to check sampled outputs of large transforms.
+  qft_state.c    plain C (OpenMP) whole-vector per-target form, the same
+                 steps as qft_fused_targets, for full outputs at n = 28-31.
 """
 
 from .qft_oracle import *  # noqa: F401,F403

@@ -1,4 +1,5 @@
-"""Build the oracle's C helper (liboracle_bins.so) with gcc.
+"""Build the oracle's C helpers (liboracle_bins.so: per-bin sums and the
+whole-vector per-target form) with gcc.
 
 Part of the test infrastructure; called by the repository's build entry point.
 """
@@ -11,9 +12,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def build() -> str:
-    src = os.path.join(HERE, "dft_bins.c")
+    srcs = [os.path.join(HERE, f) for f in ("dft_bins.c", "qft_state.c")]
     out = os.path.join(HERE, "liboracle_bins.so")
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", src, "-o", out + ".tmp", "-lm"]
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared"] + srcs + ["-o", out + ".tmp", "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)
     return out

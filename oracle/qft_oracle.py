@@ -66,16 +66,19 @@ __all__ = [
     "dft_bins",
     "dft_library",
     "qft_fused_targets",
+    "qft_state_c",
     "qft_padded",
     "apply_gates",
     "qft_as_gates",
     "rel_l2",
     "max_err",
+    "error_norms",
     "fidelity",
     "top_bin_leakage",
     "aqft_error_bound",
     "aqft_expected_relerr_gaussian",
     "c_oracle_available",
+    "c_oracle_threads",
 ]
 
 NORMS = ("unitary", "none", "inv_n")
@@ -452,6 +455,36 @@ def qft_fused_targets(x, cutoff=None, norm: str = "unitary",
     return psi
 
 
+def qft_state_c(x, cutoff=None, norm: str = "unitary", order: str = "natural",
+                inverse: bool = False) -> np.ndarray:
+    """``qft_fused_targets`` computed by the plain C helper (qft_state.c):
+    the same per-target steps (H on qubit t, then the collapsed controlled
+    phases of target t), with the pairs of each target split over OpenMP
+    threads, for whole outputs at n = 28-31 in seconds.  Needs the built C
+    helper (oracle/build_oracle.py); raises if it is missing."""
+    lib = _c_lib()
+    if lib is None:
+        raise RuntimeError("the oracle's C helper is not built (python -m oracle.build_oracle)")
+    if order not in ORDERS:
+        raise ValueError(f"unknown order {order!r}")
+    psi = np.array(x, dtype=np.complex128, copy=True, order="C")
+    N = psi.shape[0]
+    n = N.bit_length() - 1
+    if N != 1 << n:
+        raise ValueError("N must be a power of two")
+    k = effective_cutoff(n, cutoff)
+    out = np.empty_like(psi) if order == "natural" else None
+    lib.oracle_qft_state(
+        psi.ctypes.data_as(ctypes.c_void_p),
+        out.ctypes.data_as(ctypes.c_void_p) if out is not None else None,
+        ctypes.c_int(n), ctypes.c_int(k), ctypes.c_int(1 if inverse else 0),
+        ctypes.c_double(norm_factor(n, norm)))
+    if out is None:
+        return psi
+    del psi
+    return out
+
+
 def qft_padded(x, cutoff=None, norm: str = "unitary", order: str = "natural",
                inverse: bool = False) -> np.ndarray:
     """Sec. 3 step 1 for a length N that is not a power of two: n = ceil(log2 N)
@@ -544,6 +577,31 @@ def max_err(y, ref) -> float:
     return m / rms if rms > 0 else m
 
 
+def error_norms(y, ref, chunk: int = 1 << 24) -> dict:
+    """``rel_l2`` and ``max_err`` of y against ref in one pass over chunks of
+    both arrays (for 2^28-2^31-element outputs, without full-size FP64
+    temporaries).  Sums of squares are accumulated in FP64."""
+    y = np.asarray(y)
+    ref = np.asarray(ref)
+    if y.shape != ref.shape:
+        raise ValueError("shape mismatch")
+    d2 = 0.0
+    r2 = 0.0
+    m = 0.0
+    for i in range(0, ref.size, chunk):
+        a = y[i:i + chunk].astype(np.complex128)
+        b = ref[i:i + chunk].astype(np.complex128)
+        e = np.abs(a - b)
+        d2 += float(np.dot(e, e))
+        r2 += float(np.vdot(b, b).real)
+        if e.size:
+            m = max(m, float(np.max(e)))
+    rn = math.sqrt(r2)
+    rms = rn / math.sqrt(max(1, ref.size))
+    return {"rel_l2": math.sqrt(d2) / rn if rn > 0 else math.sqrt(d2),
+            "max_err": m / rms if rms > 0 else m}
+
+
 def fidelity(y, ref) -> float:
     """Squared normalised inner product |<ref, y>|^2 / (|ref|^2 |y|^2) (Sec. 4)."""
     y = np.asarray(y, dtype=np.complex128)
@@ -616,9 +674,17 @@ def _c_lib():
         lib = ctypes.CDLL(path)
         lib.oracle_dft_bins.restype = None
         lib.oracle_aqft_bins.restype = None
+        lib.oracle_qft_state.restype = None
+        lib.oracle_threads.restype = ctypes.c_int
         _LIB = lib
     return _LIB
 
 
 def c_oracle_available() -> bool:
     return _c_lib() is not None
+
+
+def c_oracle_threads() -> int:
+    """Threads the C helper's parallel loops use (OpenMP maximum)."""
+    lib = _c_lib()
+    return int(lib.oracle_threads()) if lib is not None else 0

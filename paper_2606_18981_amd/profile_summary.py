@@ -132,12 +132,29 @@ def summarize(a):
     pass_trace = [t for t in trace if is_pass(t["name"])]
     calls = sum(t["calls"] for t in pass_trace)
     avg_ns = sum(t["total_ns"] for t in pass_trace) / calls if calls else None
+    # per pass-kernel instance: duration and scaled counter bytes per launch;
+    # the dominant kernel is the one with the longest average launch
+    per_kernel = {}
+    for t in pass_trace:
+        fk = [v for (k, _g), v in fetch.items() if k == t["name"]]
+        wk = [v for (k, _g), v in write.items() if k == t["name"]]
+        fm = sum(m * c for m, c in fk) / max(1, sum(c for _m, c in fk)) if fk else None
+        wm = sum(m * c for m, c in wk) / max(1, sum(c for _m, c in wk)) if wk else None
+        tb = None
+        if None not in (fm, wm, f_factor, w_factor):
+            tb = (fm * f_factor + wm * w_factor) * 1024.0
+        per_kernel[t["name"]] = {"avg_ns": t["avg_ns"], "calls": t["calls"], "fetch_kib": fm,
+                                 "write_kib": wm, "traffic_bytes_per_launch": tb}
+    dominant = max(per_kernel, key=lambda k: per_kernel[k]["avg_ns"]) if per_kernel else None
     bench = None
     if a.bench_json and os.path.exists(a.bench_json):
         for line in open(a.bench_json):
             line = line.strip()
             if line.startswith("{") and '"metric"' in line:
                 bench = json.loads(line)
+    alg = None
+    if bench:
+        alg = bench.get("roofline", {}).get("algorithmic_bytes_per_launch")
     block = {
         "source_digest": source_digest(),
         "workload": bench["config"] if bench else None,
@@ -150,6 +167,14 @@ def summarize(a):
         "fetch_factor": f_factor,
         "write_factor": w_factor,
         "pass_traffic_bytes_per_launch": traffic,
+        "kernels": per_kernel,
+        "dominant_kernel": dominant,
+        "dominant_avg_ns": per_kernel[dominant]["avg_ns"] if dominant else None,
+        "dominant_traffic_bytes_per_launch":
+            per_kernel[dominant]["traffic_bytes_per_launch"] if dominant else None,
+        "algorithmic_bytes_per_launch": alg,
+        "dominant_frac_of_8tbs": (alg / per_kernel[dominant]["avg_ns"] / 8000.0
+                                  if (alg and dominant) else None),
     }
     out = []
     out.append(f"# {a.title}\n")
@@ -183,12 +208,27 @@ def summarize(a):
     if traffic:
         out.append(f"Pass kernel, scaled: {traffic / 2**30:.4f} GiB per launch "
                    f"({nf} / {nw} dispatches counted).")
+    if dominant:
+        d = per_kernel[dominant]
+        line = (f"Dominant kernel (longest average launch): `{dominant[:90]}`, "
+                f"{d['avg_ns'] / 1e3:.1f} µs")
+        if alg:
+            line += (f"; {alg} algorithmic bytes per launch, {alg / d['avg_ns']:.1f} GB/s, "
+                     f"{alg / d['avg_ns'] / 8000.0:.3f} of 8 TB/s")
+        if d["traffic_bytes_per_launch"]:
+            line += f"; counters {d['traffic_bytes_per_launch'] / 2**30:.4f} GiB per launch"
+        out.append(line + ".")
     if bench:
         r = bench.get("roofline", {})
+        pm = bench.get("pass_ms") or []
         out.append("")
-        out.append(f"Bench line of the traced run: {bench['ms_per_step']:.4f} ms per step, "
-                   f"pass mean from HIP events {1e3 * r.get('algorithmic_bytes_per_launch', 0) / max(r.get('achieved', 1), 1e-9) / 1e9:.4f} ms "
-                   f"per launch; rocprofv3 average {avg_ns / 1e6 if avg_ns else float('nan'):.4f} ms.")
+        out.append(f"Bench line of the traced run: {bench['ms_per_step']:.4f} ms per step; "
+                   f"HIP-event pass times {', '.join(f'{m:.4f}' for m in pm)} ms; "
+                   f"roofline frac {r.get('frac', float('nan')):.3f} ({r.get('kernel', '')}).")
+    out.append("")
+    out.append("VGPR and AGPR as rocprofv3 reports them: on gfx950 the figure is half the "
+               "registers the compiler allocates (its resource report: 157 for a 'VGPR 80' "
+               "here).")
     if getattr(a, "sq", None):
         sq = sq_per_wave(a.sq)
         cols = [c for c in SQ_COUNTERS if c != "SQ_WAVES"]
@@ -215,9 +255,9 @@ def summarize(a):
     return "\n".join(out) + "\n"
 
 
-def load_traffic(md_path, config):
-    """Scaled HBM bytes per pass launch from a summary, or None when the
-    summary is missing, was taken on other sources, or on another workload."""
+def _load_block(md_path, config):
+    """The summary's JSON block, or None when the summary is missing, was
+    taken on other sources, or on another workload."""
     try:
         text = open(md_path).read()
     except OSError:
@@ -236,7 +276,32 @@ def load_traffic(md_path, config):
     for key in ("n", "cutoff", "pass_bits", "kernel_config", "workload"):
         if w.get(key) != config.get(key):
             return None
-    return block.get("pass_traffic_bytes_per_launch")
+    return block
+
+
+def load_traffic(md_path, config, kernel=None):
+    """Scaled HBM bytes per launch of one pass kernel instance (`kernel`, a
+    name such as "k_fused_pass2<float, 5, 4, true, true>"), or pooled over
+    every pass launch when kernel is None; None when the summary does not
+    apply (see _load_block) or lacks that kernel."""
+    block = _load_block(md_path, config)
+    if block is None:
+        return None
+    if kernel is None:
+        return block.get("pass_traffic_bytes_per_launch")
+    for name, v in (block.get("kernels") or {}).items():
+        if ("qft::" + kernel + "(") in name:
+            return v.get("traffic_bytes_per_launch")
+    return None
+
+
+def load_plan_traffic(md_path, config):
+    """Scaled HBM bytes of one whole transform (mean per pass launch times
+    the plan's passes), or None."""
+    block = _load_block(md_path, config)
+    if block is None or not block.get("pass_traffic_bytes_per_launch"):
+        return None
+    return block["pass_traffic_bytes_per_launch"] * config.get("passes", 0)
 
 
 def main():

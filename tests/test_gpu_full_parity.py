@@ -1,0 +1,162 @@
+"""Whole-vector parity at the full sizes of the AQFT workload (n = 28 and
+n = 30), and the accuracy of every cutoff against the FP64 exact DFT.
+
+Parity: every output element of the GPU transform against the oracle's
+whole-vector per-target form (oracle.qft_state_c, the circuit of Fig. 1 with
+the controlled phases of each target collapsed, Sec. 2), in FP64.  Bars:
+relative L2 and max error over the RMS amplitude, each <= 1e-5 (complex64)
+or <= 1e-12 (complex128).  The max-error bar is the stronger of the two (it
+bounds the relative L2 from above).
+
+Accuracy (Sec. 4 metrics; Sec. 2 "Approximate QFT"): the relative L2 of each
+GPU AQFT output against the FP64 exact DFT (library FFT of the whole input)
+on 2^20 seeded output bins must match the closed-form expectation for
+i.i.d. complex Gaussian inputs within 5 %, and shrink as the cutoff grows.
+
+Host cost on a 16-core host: the oracle takes about 10 s per cutoff at n = 28
+and 40 s at n = 30; the whole module about 4 minutes.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_18981_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": 1e-5, "c128": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2606_18981_amd import qft
+    return qft
+
+
+def gpu_full(torch, Q, xdev, n, k, dtype, inverse=False):
+    """One transform of a copy of the device input; the whole output on the
+    host."""
+    print(f"[gpu] n={n} cutoff={k} dtype={dtype} inverse={inverse}", flush=True)
+    plan = Q.Plan(n, k, "unitary", dtype, "natural", inverse=inverse)
+    t = xdev.clone()
+    plan.execute(t)
+    torch.cuda.synchronize()
+    y = t.cpu().numpy()
+    del t
+    plan.close()
+    return y
+
+
+def check_parity(y, ref, dtype, what):
+    e = O.error_norms(y, ref)
+    print(f"[parity] {what}: rel_l2={e['rel_l2']:.3e} max_err={e['max_err']:.3e}", flush=True)
+    assert e["rel_l2"] <= TOL[dtype], (what, e)
+    assert e["max_err"] <= TOL[dtype], (what, e)
+    return e
+
+
+def aqft_run(torch, Q, n, parity_cutoffs, seed=1003):
+    N = 1 << n
+    print(f"[gpu] n={n} input (seed {seed})", flush=True)
+    x = I.gaussian(n, seed)
+    print(f"[gpu] n={n} exact FP64 reference (library FFT)", flush=True)
+    exact = O.dft_library(x, workers=-1)
+    bins = np.random.default_rng(seed).choice(N, 1 << 20, replace=False)
+    exact_b = exact[bins]
+    del exact
+    xd = torch.from_numpy(x.astype(np.complex64)).cuda()
+    rows = []
+    for k in (-1, 6, 10, 14, 18):
+        y = gpu_full(torch, Q, xd, n, k, "c64")
+        row = {"n": n, "cutoff": k, "vs_exact_dft_2^20_bins": O.rel_l2(y[bins], exact_b),
+               "max_err_vs_exact_dft_2^20_bins": O.max_err(y[bins], exact_b),
+               "predicted": O.aqft_expected_relerr_gaussian(n, k)}
+        if k in parity_cutoffs:
+            print(f"[oracle] n={n} cutoff={k} whole vector", flush=True)
+            ref = O.qft_state_c(x, None if k < 0 else k)
+            e = check_parity(y, ref, "c64", f"n={n} k={k} c64")
+            row.update({"vs_oracle_rel_l2": e["rel_l2"], "vs_oracle_max_err": e["max_err"]})
+            del ref
+        del y
+        rows.append(row)
+    del xd, x
+    torch.cuda.empty_cache()
+    out_dir = os.environ.get("QFT_RESULTS_DIR")  # optional copy of the table
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, f"aqft_full_n{n}.json"), "w") as f:
+            json.dump(rows, f, indent=1)
+    print(json.dumps(rows), flush=True)
+    # accuracy against the exact DFT: the closed-form expectation
+    for r in rows:
+        if r["cutoff"] < 0:
+            assert r["vs_exact_dft_2^20_bins"] <= TOL["c64"]
+        else:
+            assert r["vs_exact_dft_2^20_bins"] == pytest.approx(r["predicted"], rel=0.05)
+    errs = [r["vs_exact_dft_2^20_bins"] for r in rows[1:]]
+    assert all(b < a for a, b in zip(errs, errs[1:]))  # shrinks as k grows
+    return rows
+
+
+@pytest.mark.timeout(600)
+def test_n28_c64_aqft_whole_vector(torch_cuda, Q):
+    """Config 3 at n = 28: the exact transform and every cutoff 6, 10, 14,
+    18, whole vector against the oracle."""
+    aqft_run(torch_cuda, Q, 28, (-1, 6, 10, 14, 18))
+
+
+@pytest.mark.timeout(900)
+def test_n30_c64_aqft_whole_vector(torch_cuda, Q):
+    """Config 3 at n = 30 (8 GiB state): exact, k = 6 and k = 18 whole vector
+    against the oracle; all cutoffs against the exact DFT."""
+    aqft_run(torch_cuda, Q, 30, (-1, 6, 18))
+
+
+@pytest.mark.timeout(600)
+def test_n28_c128_and_inverse_whole_vector(torch_cuda, Q):
+    """n = 28 complex128 (exact and k = 10) and the complex64 inverse, whole
+    vector against the oracle."""
+    torch = torch_cuda
+    n = 28
+    x = I.gaussian(n, 1003)
+    xd = torch.from_numpy(x).cuda()
+    for k in (-1, 10):
+        y = gpu_full(torch, Q, xd, n, k, "c128")
+        check_parity(y, O.qft_state_c(x, None if k < 0 else k), "c128", f"n=28 k={k} c128")
+        del y
+    del xd
+    xd = torch.from_numpy(x.astype(np.complex64)).cuda()
+    y = gpu_full(torch, Q, xd, n, -1, "c64", inverse=True)
+    check_parity(y, O.qft_state_c(x, None, inverse=True), "c64", "n=28 inverse c64")
+    del xd, y
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("n", [25, 26, 27, 29])
+def test_default_splits_whole_vector(torch_cuda, Q, n):
+    """Every default three-pass split between n = 25 and 29 (the planner's
+    last-pass and first-pass rules pick them), both element types, whole
+    vector against the oracle."""
+    torch = torch_cuda
+    x = I.gaussian(n, 2500 + n)
+    print(f"[oracle] n={n} whole vector", flush=True)
+    ref = O.qft_state_c(x)
+    for dtype in ("c64", "c128"):
+        xd = torch.from_numpy(x.astype(np.complex64 if dtype == "c64" else np.complex128)).cuda()
+        y = gpu_full(torch, Q, xd, n, -1, dtype)
+        del xd
+        check_parity(y, ref, dtype, f"n={n} {dtype} default split")
+        del y
+    torch.cuda.empty_cache()

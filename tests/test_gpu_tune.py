@@ -9,6 +9,12 @@ from paper_2606_18981_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
+def within(y, ref, tol):
+    """Relative L2 and max error over the RMS amplitude both <= tol."""
+    e = O.error_norms(y, ref)
+    return e["rel_l2"] <= tol and e["max_err"] <= tol
+
+
 
 @pytest.fixture(scope="module")
 def env():
@@ -35,7 +41,7 @@ def test_tune_shape_and_reuse(env, tmp_path):
     t = torch.from_numpy(x.astype(np.complex64)).cuda()
     plan.execute(t)
     torch.cuda.synchronize()
-    assert O.rel_l2(t.cpu().numpy().astype(np.complex128), O.qft_fused_targets(x)) <= 1e-5
+    assert within(t.cpu().numpy(), O.qft_fused_targets(x), 1e-5)
     plan.close()
     path = tmp_path / "wisdom.jsonl"
     Q.tune_save(path)

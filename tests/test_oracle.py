@@ -382,6 +382,18 @@ def test_metrics_definitions():
     assert O.max_err(y, ref) == pytest.approx(0.5 / (5.0 / 2.0))
     assert O.fidelity(ref, ref) == pytest.approx(1.0)
     assert O.top_bin_leakage(y, ref) == pytest.approx(1 - 16.0 / 25.25)
+    e = O.error_norms(y, ref, chunk=3)
+    assert e["rel_l2"] == pytest.approx(0.1) and e["max_err"] == pytest.approx(0.2)
+
+
+def test_chunked_error_norms_equal_the_plain_metrics():
+    rng = np.random.default_rng(5)
+    ref = rng.standard_normal(1000) + 1j * rng.standard_normal(1000)
+    y = (ref + 1e-3 * rng.standard_normal(1000)).astype(np.complex64)
+    for chunk in (1, 7, 256, 4096):
+        e = O.error_norms(y, ref, chunk)
+        assert e["rel_l2"] == pytest.approx(O.rel_l2(y, ref), rel=1e-12)
+        assert e["max_err"] == pytest.approx(O.max_err(y, ref), rel=1e-12)
 
 
 # --------------------------------------------------------------------------
@@ -537,3 +549,68 @@ def test_qft_as_general_gates_is_the_circuit(n, k):
     for order in O.ORDERS:
         y = O.apply_gates(x, O.qft_as_gates(n, k, order))
         assert O.rel_l2(y, O.qft_circuit(x, k, "unitary", order, encode=False)) < TOL
+
+
+# --------------------------------------------------------------------------
+# the C whole-vector form (qft_state.c), used for full outputs at n = 28-31
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c_oracle():
+    import oracle.qft_oracle as OQ
+    if not O.c_oracle_available():
+        from oracle.build_oracle import build
+        build()
+        OQ._LIB_TRIED = False  # look for the freshly built helper again
+    assert O.c_oracle_available()
+    return O
+
+
+@pytest.mark.parametrize("n", list(range(1, 11)))
+@pytest.mark.parametrize("inverse", [False, True])
+def test_c_state_exact_is_dft_definition(c_oracle, n, inverse):
+    x = I.gaussian(n, 700 + n)
+    for norm in O.NORMS:
+        for order in O.ORDERS:
+            y = O.qft_state_c(x, None, norm, order, inverse)
+            assert O.rel_l2(y, O.dft_naive(x, norm, order, inverse)) < TOL
+            assert O.max_err(y, O.dft_naive(x, norm, order, inverse)) < 10 * TOL
+
+
+@pytest.mark.parametrize("n", list(range(2, 8)))
+def test_c_state_aqft_is_closed_form(c_oracle, n):
+    """Every cutoff against the closed-form AQFT matrix (a different
+    formulation: bits of input and output index, no butterflies)."""
+    x = I.gaussian(n, 710 + n)
+    for k in range(0, n):
+        A = O.aqft_matrix(n, k)
+        assert O.rel_l2(O.qft_state_c(x, k), A @ x) < TOL
+        assert O.rel_l2(O.qft_state_c(x, k, inverse=True), np.conj(A) @ x) < TOL
+
+
+def test_c_state_large_vs_library_and_bins(c_oracle):
+    """n = 20: exact against the library FFT of the whole vector; the AQFT
+    k = 5 and the exact inverse against the per-bin closed-form sums."""
+    n = 20
+    x = I.gaussian(n, 720)
+    y = O.qft_state_c(x)
+    ref = O.dft_library(x)
+    assert O.rel_l2(y, ref) < TOL and O.max_err(y, ref) < 10 * TOL
+    bins = np.random.default_rng(720).choice(1 << n, 48, replace=False)
+    ya = O.qft_state_c(x, 5)
+    assert O.rel_l2(ya[bins], O.aqft_bins(x, bins, 5)) < TOL
+    yi = O.qft_state_c(x, None, "inv_n", "natural", inverse=True)
+    assert O.rel_l2(yi[bins], O.dft_bins(x, bins, "inv_n", inverse=True)) < TOL
+    # Parseval for the AQFT (a product of unitary gates)
+    assert np.linalg.norm(ya) == pytest.approx(np.linalg.norm(x), rel=1e-13)
+
+
+def test_c_state_delta_and_tone(c_oracle):
+    n = 16
+    N = 1 << n
+    y = O.qft_state_c(I.delta(n, 0))
+    assert np.max(np.abs(y - 1.0 / math.sqrt(N))) < 1e-15
+    y = O.qft_state_c(I.tone(n, 37))
+    spike = np.zeros(N, complex)
+    spike[37] = math.sqrt(N)
+    assert np.max(np.abs(y - spike)) < 1e-11

@@ -59,6 +59,13 @@ def test_summary_scales_counters_by_the_copy_and_round_trips(tmp_path):
     path.write_text(md)
     traffic = PS.load_traffic(str(path), config)
     assert abs(traffic - (1.01 * GIB + GIB)) < 1.0
+    # the one pass kernel instance is the dominant one
+    assert abs(PS.load_traffic(str(path), config, "k_fused_pass<float, 5>")
+               - (1.01 * GIB + GIB)) < 1.0
+    assert PS.load_traffic(str(path), config, "k_fused_pass2<float, 5, 4, true, true>") is None
+    assert abs(PS.load_plan_traffic(str(path), dict(config, passes=3))
+               - 3 * (1.01 * GIB + GIB)) < 4.0
+    assert "Dominant kernel (longest average launch)" in md
     # another workload or other kernel sources: no traffic figure
     assert PS.load_traffic(str(path), dict(config, pass_bits=[10, 9, 9])) is None
     assert PS.load_traffic(str(path).replace("s.md", "none.md"), config) is None
