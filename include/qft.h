@@ -177,6 +177,23 @@ int qft_execute_ws(qft_plan_t *plan, void *dev_ptr, void *workspace,
 int qft_execute_norm(qft_plan_t *plan, void *dev_ptr, void *workspace,
                      double *norm_dev, qft_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * qft_execute_norm, but the partial sums live in a static device array of
+ * QFT_NORM_SCRATCH_DOUBLES doubles (8 MiB, one per GPU, held until the
+ * process ends) instead of a plan-owned buffer, so this call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine; it records
+ * no per-launch timing events).  The plan (tables, workspace) is built
+ * beforehand as usual.  Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU race and must be ordered by the
+ * caller (one stream, or events).  Every partial is rewritten before it is
+ * read, so no clearing is needed.  Returns QFT_ERR_UNSUPPORTED when the plan
+ * needs more partial sums than the array holds (not the case for any
+ * default plan up to n = 31), else as qft_execute_norm.                   */
+#define QFT_NORM_SCRATCH_DOUBLES (1u << 20)
+int qft_execute_norm_static(qft_plan_t *plan, void *dev_ptr, void *workspace,
+                            double *norm_dev, qft_stream_t stream);
+
 /* Free the plan and its device memory (NULL-safe).  The caller must ensure
  * no enqueued execute of the plan is still pending.                         */
 void qft_destroy(qft_plan_t *plan);

@@ -15,8 +15,41 @@
 #include "qft_planner.h"
 #include "qft_runtime.h"
 
+// Partial sums of |x|^2 for qft_execute_norm_static: file-scope device
+// memory instead of a plan-owned hipMalloc'd buffer, so that entry point
+// allocates nothing.  Each GPU the library runs on holds its own copy
+// (QFT_NORM_SCRATCH_DOUBLES doubles, 8 MiB) until the process ends.  In host
+// code the name `scratch` is only a host-side stand-in: the device address
+// comes from hipGetSymbolAddress, once per device, and only that address is
+// passed to kernels.
+static __device__ __align__(256) double scratch[QFT_NORM_SCRATCH_DOUBLES];
+
 namespace {
 thread_local std::string g_last_error;
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of this device's scratch array (resolved on the first call
+// on the device, with the device current).
+int scratch_address(int dev, double **out) {
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return qft::set_error(QFT_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return qft::hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                            "hipGetSymbolAddress(scratch)");
+    }
+    g_scratch_ptr[dev] = (double *)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return QFT_OK;
+}
 }
 
 namespace qft {
@@ -34,18 +67,22 @@ int hip_error(hipError_t e, const char *what) {
 void clear_error() { g_last_error.clear(); }
 
 // Enqueue the kernels of a plan.  `ws` may be NULL when the plan needs none.
-int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm_out) {
+// With norm_out, `part` holds the plan's norm_parts_for() partial sums.
+int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm_out,
+                 double *part, bool allow_timing) {
   const HostPlan &hp = p->hp;
   hipError_t e = hipSuccess;
   size_t li = 0;
+  const bool timing = p->timing && allow_timing;
   auto mark = [&](size_t i) {
-    if (p->timing) hipEventRecord(p->timer.slot(i), s);
+    if (timing) hipEventRecord(p->timer.slot(i), s);
   };
+  const uint32_t nparts = norm_out ? norm_parts_for(p) : 0;
   if (norm_out && hp.schedule == Schedule::Gates) {
-    e = launch_norm_sweep(dev, hp.n, hp.c128, p->d_norm, p->norm_parts, s);
+    e = launch_norm_sweep(dev, hp.n, hp.c128, part, nparts, s);
     if (e != hipSuccess) return hip_error(e, "norm sweep launch");
   }
-  if (p->timing) p->timer.begin(p->num_launches());
+  if (timing) p->timer.begin(p->num_launches());
   if (hp.schedule == Schedule::Fused) {
     for (size_t i = 0; i < p->launches.size(); ++i) {
       const PassLaunch &L = p->launches[i];
@@ -55,7 +92,7 @@ int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm
       if (i == 0 && norm_out) {
         // the first pass also sums |x|^2 of the tiles it loads
         PassLaunch Ln = L;
-        Ln.d.norm_part = p->d_norm;
+        Ln.d.norm_part = part;
         e = launch_fused_pass(Ln, hp.c128, in, out, s);
       } else {
         e = launch_fused_pass(L, hp.c128, in, out, s);
@@ -80,12 +117,22 @@ int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm
     }
   }
   mark(li);
-  if (p->timing) p->timer.end();
+  if (timing) p->timer.end();
   if (norm_out) {
-    e = launch_norm_finish(p->d_norm, p->norm_parts, norm_out, s);
+    e = launch_norm_finish(part, nparts, norm_out, s);
     if (e != hipSuccess) return hip_error(e, "norm launch");
   }
   return QFT_OK;
+}
+
+uint32_t norm_parts_for(const qft_plan_s *p) {
+  const HostPlan &hp = p->hp;
+  if (hp.schedule == Schedule::Fused) {
+    const PassLaunch &L = p->launches[0];
+    return L.d.ntiles * (uint32_t)norm_parts_per_tile(L.threads);
+  }
+  const uint32_t N = 1u << hp.n;
+  return std::max(1u, std::min(1024u, N / 4096u));
 }
 
 // ---- per-launch timing ---------------------------------------------------
@@ -212,7 +259,7 @@ int qft_execute_ws(qft_plan_t *plan, void *dev_ptr, void *workspace, qft_stream_
   clear_error();
   int rc = check_execute(plan, dev_ptr, workspace);
   if (rc != QFT_OK) return rc;
-  return enqueue_plan(plan, dev_ptr, workspace, (hipStream_t)stream);
+  return enqueue_plan(plan, dev_ptr, workspace, (hipStream_t)stream, nullptr, nullptr, true);
 }
 
 int qft_execute_norm(qft_plan_t *plan, void *dev_ptr, void *workspace, double *norm_dev,
@@ -225,15 +272,7 @@ int qft_execute_norm(qft_plan_t *plan, void *dev_ptr, void *workspace, double *n
   if ((uintptr_t)norm_dev % sizeof(double))
     return set_error(QFT_ERR_POINTER, "norm pointer is not aligned to 8 bytes");
   if (!plan->d_norm) {
-    const HostPlan &hp = plan->hp;
-    uint32_t parts;
-    if (hp.schedule == Schedule::Fused) {
-      const PassLaunch &L = plan->launches[0];
-      parts = L.d.ntiles * (uint32_t)norm_parts_per_tile(L.threads);
-    } else {
-      const uint32_t N = 1u << hp.n;
-      parts = std::max(1u, std::min(1024u, N / 4096u));
-    }
+    const uint32_t parts = norm_parts_for(plan);
     hipError_t e = hipMalloc(&plan->d_norm, (size_t)parts * sizeof(double));
     if (e != hipSuccess) {
       plan->d_norm = nullptr;
@@ -242,7 +281,30 @@ int qft_execute_norm(qft_plan_t *plan, void *dev_ptr, void *workspace, double *n
     }
     plan->norm_parts = parts;
   }
-  return enqueue_plan(plan, dev_ptr, workspace, (hipStream_t)stream, norm_dev);
+  return enqueue_plan(plan, dev_ptr, workspace, (hipStream_t)stream, norm_dev, plan->d_norm,
+                      true);
+}
+
+int qft_execute_norm_static(qft_plan_t *plan, void *dev_ptr, void *workspace, double *norm_dev,
+                            qft_stream_t stream) {
+  clear_error();
+  if (plan && !workspace) workspace = plan->d_ws;
+  int rc = check_execute(plan, dev_ptr, workspace);
+  if (rc != QFT_OK) return rc;
+  if (!norm_dev) return set_error(QFT_ERR_POINTER, "norm pointer is NULL");
+  if ((uintptr_t)norm_dev % sizeof(double))
+    return set_error(QFT_ERR_POINTER, "norm pointer is not aligned to 8 bytes");
+  const uint32_t parts = norm_parts_for(plan);
+  if (parts > QFT_NORM_SCRATCH_DOUBLES)
+    return set_error(QFT_ERR_UNSUPPORTED,
+                     "this plan needs more norm partial sums than the static scratch holds "
+                     "(QFT_NORM_SCRATCH_DOUBLES); use qft_execute_norm");
+  double *part = nullptr;
+  rc = scratch_address(plan->device, &part);
+  if (rc != QFT_OK) return rc;
+  // every partial is written by the first pass (or the norm sweep) before the
+  // final sum reads it, so the scratch needs no clearing between calls
+  return enqueue_plan(plan, dev_ptr, workspace, (hipStream_t)stream, norm_dev, part, false);
 }
 
 int qft_execute(qft_plan_t *plan, void *dev_ptr, qft_stream_t stream) {

@@ -46,8 +46,13 @@ struct qft_plan_s {
 };
 
 namespace qft {
-// norm_out: device double receiving ||x||_2 of the input, or nullptr
-int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm_out = nullptr);
+// norm_out: device double receiving ||x||_2 of the input, or nullptr; part:
+// device buffer of norm_parts_for(p) partial sums (used when norm_out is set);
+// allow_timing: record the plan's per-launch timing events if it has them on
+int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm_out,
+                 double *part, bool allow_timing);
+// partial sums of |x|^2 an execute with the input norm needs for this plan
+uint32_t norm_parts_for(const qft_plan_s *p);
 // drop cached batch launches that use this plan
 void batch_forget_plan(qft_plan_s *plan);
 // tuned configuration for a plan shape, if the tuning table has one

@@ -111,6 +111,7 @@ def _load():
         "qft_execute": (I, [P, P, P]),
         "qft_execute_ws": (I, [P, P, P, P]),
         "qft_execute_norm": (I, [P, P, P, P, P]),
+        "qft_execute_norm_static": (I, [P, P, P, P, P]),
         "qft_destroy": (None, [P]),
         "qft_last_error": (ctypes.c_char_p, []),
         "qft_plan_info": (I, [P, ctypes.POINTER(PlanInfo)]),
