@@ -218,6 +218,7 @@ static qft_plan_t *make_plan(int n, int cutoff, int norm, int layout, const qft_
     L.d.tw_lo = t + hp.off_lo;
     L.d.tw_hi = t + hp.off_hi;
     L.d.gtab = hp.off_gtab[i] ? t + hp.off_gtab[i] : nullptr;
+    L.d.gtab1 = hp.off_gtab1[i] ? t + hp.off_gtab1[i] : nullptr;
   }
   return p;
 }

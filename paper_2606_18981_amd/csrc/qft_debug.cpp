@@ -24,8 +24,9 @@ int qft_debug_pass(int n, int cutoff, int norm, int layout, const qft_config_t *
   if (!out_desc || desc_bytes < sizeof(PassDesc)) return QFT_ERR_INVALID;
   PassLaunch L = hp.passes[pass];
   L.d.tw_int = L.d.tw_lo = L.d.tw_hi = nullptr;
-  // the group-factor table: its byte offset in the table image (0: none)
+  // the group-factor tables: their byte offsets in the table image (0: none)
   L.d.gtab = reinterpret_cast<const void *>((uintptr_t)hp.off_gtab[pass]);
+  L.d.gtab1 = reinterpret_cast<const void *>((uintptr_t)hp.off_gtab1[pass]);
   memcpy(out_desc, &L.d, sizeof(PassDesc));
   if (launch) {
     launch[0] = L.threads;

@@ -71,6 +71,9 @@ struct PassDesc {
   int32_t conj_in;  // 1: conjugate the loaded elements (first pass, inverse)
   int32_t conj_out; // 1: conjugate the stored elements (last pass, inverse)
   int32_t nt;       // 1: non-temporal (streaming) loads and stores
+  int32_t lane_swap;// s > 0: three register groups, the last one taking pass
+                    // bits 0..s-1 from lane bits 5..6-s of the middle group
+                    // by cross-lane swaps (no LDS); 0 otherwise
   uint32_t ntiles;
   uint32_t gpos_w[4];   // global index bit of e-position q (packed)
   uint32_t free_w[8];   // global positions of the non-tile bits, ascending
@@ -87,6 +90,7 @@ struct PassDesc {
   const void *tw_hi;          // w_N^(x 2^L), x < 2^(n-L)
   const void *gtab;           // per-thread factors of group 0, [q][tid]
                               // (entries of tw_int), or null
+  const void *gtab1;          // the same for group 1 of a three-group pass
   double *norm_part;          // non-null: per-wave sums of |x|^2 of the
                               // loaded tile at [tile * parts_per_tile + w]
 };
@@ -116,6 +120,29 @@ inline int pass2_shape(const PassLaunch &L) {
                    d.grp[1].jbase == 0 && d.grp[1].nst >= 1 && d.grp[1].nst <= d.r &&
                    L.threads == (1 << (d.T - d.r));
   return two ? 1 + (d.ext_tw ? 5 : 0) + (d.grp[1].nst - 1) : 0;
+}
+
+// 0, or 1 + 3 * ext + (s - 1) for a pass of 10 + s bits (s = 1..3) with the
+// three-group shape of the compile-time kernel: radix 32, groups 0 and 1
+// full and carrying per-thread factors, group 2 holding pass bits 0..s-1,
+// which reach its registers by cross-lane swaps with lane bits 5, 4, 3.
+inline int pass3_shape(const PassLaunch &L) {
+  const PassDesc &d = L.d;
+  const int s = d.lane_swap;
+  const bool three = s >= 1 && s <= 3 && d.r == 5 && d.ngroups == 3 && d.m == 10 + s &&
+                     d.grp[0].nst == 5 && d.grp[0].jbase == s + 5 && d.grp[1].nst == 5 &&
+                     d.grp[1].jbase == s && d.grp[2].jbase == 0 && d.grp[2].nst == s &&
+                     d.T - d.r >= 6 && L.threads == (1 << (d.T - d.r));
+  return three ? 1 + (d.ext_tw ? 3 : 0) + (s - 1) : 0;
+}
+
+// Kernel of a pass: 0 generic, 1..10 the two-group kernel (pass2_shape),
+// 11..16 the three-group kernel (10 + pass3_shape).
+inline int pass_kernel_shape(const PassLaunch &L) {
+  const int two = pass2_shape(L);
+  if (two) return two;
+  const int three = pass3_shape(L);
+  return three ? 10 + three : 0;
 }
 
 }  // namespace qft

@@ -42,9 +42,10 @@ struct BatchGroup {
 };
 hipError_t launch_batch_group(bool c128, const BatchGroup &g, hipStream_t s);
 
-// 0 for the generic pass kernel; 1 + 5 * ext + (nst - 1) for a pass with the
-// two-group shape of the compile-time specialised kernel (radix 32, the
-// first group full, the last group holding pass bit 0 with nst stages).
+// Kernel of a pass (pass_kernel_shape): 0 for the generic pass kernel;
+// 1..10 for the compile-time two-group kernel (radix 32, the first group
+// full, the last holding pass bit 0); 11..16 for the compile-time
+// three-group kernel (the last group reached by cross-lane swaps).
 int fused_pass_shape(const PassLaunch &L);
 
 // Gate-by-gate sweeps (unfused circuit, Fig. 1).

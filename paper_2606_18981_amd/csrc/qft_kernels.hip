@@ -571,15 +571,179 @@ k_fused_pass2(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
                                       reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x);
 }
 
-int fused_pass_shape(const PassLaunch &L) { return pass2_shape(L); }
+// Cross-lane exchange of register bit q with lane bit LB of one 32-bit
+// component, between the register pair (a: register bit q clear, b: set).
+// Afterwards register bit q carries what lane bit LB carried and lane bit LB
+// what register bit q carried: a lane whose bit LB is clear keeps a and takes
+// its partner's a into b; a lane whose bit LB is set keeps b and takes its
+// partner's b into a (partner = lane ^ 2^LB).
+template <int LB>
+__device__ __forceinline__ void lane_swap_u32(uint32_t &a, uint32_t &b, uint32_t lane) {
+  if constexpr (LB == 5) {
+    // v_permlane32_swap: the upper 32 lanes of a trade places with the lower
+    // 32 lanes of b
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  } else if constexpr (LB == 4) {
+    // v_permlane16_swap: the odd 16-lane rows of a trade places with the
+    // even rows of b
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  } else {
+    static_assert(LB == 3, "lane bits 3..5 only");
+    // rotating a 16-lane row by 8 (DPP row_ror:8) pairs lane l with l ^ 8
+    const bool up = (lane >> 3) & 1u;
+    const uint32_t send = up ? a : b;
+    const uint32_t recv = (uint32_t)__builtin_amdgcn_mov_dpp((int)send, 0x128, 0xf, 0xf, false);
+    if (up) a = recv;
+    else b = recv;
+  }
+}
+
+template <int LB>
+__device__ __forceinline__ void lane_swap(cplx<float> &a, cplx<float> &b, uint32_t lane) {
+  uint32_t ax = __float_as_uint(a.x), bx = __float_as_uint(b.x);
+  uint32_t ay = __float_as_uint(a.y), by = __float_as_uint(b.y);
+  lane_swap_u32<LB>(ax, bx, lane);
+  lane_swap_u32<LB>(ay, by, lane);
+  a = cplx<float>{__uint_as_float(ax), __uint_as_float(ay)};
+  b = cplx<float>{__uint_as_float(bx), __uint_as_float(by)};
+}
+
+template <int LB>
+__device__ __forceinline__ void lane_swap(cplx<double> &a, cplx<double> &b, uint32_t lane) {
+  uint64_t w[4] = {(uint64_t)__double_as_longlong(a.x), (uint64_t)__double_as_longlong(a.y),
+                   (uint64_t)__double_as_longlong(b.x), (uint64_t)__double_as_longlong(b.y)};
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    uint32_t alo = (uint32_t)w[c], ahi = (uint32_t)(w[c] >> 32);
+    uint32_t blo = (uint32_t)w[c + 2], bhi = (uint32_t)(w[c + 2] >> 32);
+    lane_swap_u32<LB>(alo, blo, lane);
+    lane_swap_u32<LB>(ahi, bhi, lane);
+    w[c] = ((uint64_t)ahi << 32) | alo;
+    w[c + 2] = ((uint64_t)bhi << 32) | blo;
+  }
+  a = cplx<double>{__longlong_as_double((long long)w[0]), __longlong_as_double((long long)w[1])};
+  b = cplx<double>{__longlong_as_double((long long)w[2]), __longlong_as_double((long long)w[3])};
+}
+
+// Register bits 0..S-1 trade places with lane bits 5, 4, 3 (register bit q
+// with lane bit 5 - q): the last group of a three-group pass takes the pass
+// bits that the middle group held on those lanes.
+template <typename Real, int RB, int S>
+__device__ __forceinline__ void lane_swaps(cplx<Real> (&v)[1 << RB], uint32_t lane) {
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+#pragma unroll
+    for (int rho = 0; rho < (1 << RB); ++rho) {
+      if (rho & (1 << q)) continue;
+      if (q == 0) lane_swap<5>(v[rho], v[rho | 1], lane);
+      else if (q == 1) lane_swap<4>(v[rho], v[rho | 2], lane);
+      else lane_swap<3>(v[rho], v[rho | 4], lane);
+    }
+  }
+}
+
+// A pass of 10 + S bits with its structure fixed at compile time: groups 0
+// and 1 full (RB stages each, per-thread factors of the lower pass bits from
+// the planner's tables), one LDS exchange between them, then the S lowest
+// pass bits brought into registers by cross-lane swaps (they sit on lane
+// bits 5, 4, 3 of group 1's thread map) and applied by a radix-2^S network,
+// and (EXT) the diagonal of the controls below the pass.  Wider middle
+// passes let the first and last passes keep long contiguous rows.
+template <typename Real, int RB, int S, bool EXT, bool NT>
+__device__ __forceinline__ void pass3_tile(const PassDesc &d, uint32_t tile, const cplx<Real> *in,
+                                           cplx<Real> *out, cplx<Real> *lds, uint32_t tid) {
+  using C = cplx<Real>;
+  constexpr int R = 1 << RB;
+  const int TR = d.T - RB;
+  const uint32_t base = tile_base(d, tile);
+  const uint32_t st_thr = deposit_tid(tid, d.st_thr_w, TR);
+
+  C gf[RB];
+  {
+    const C *__restrict__ gt = (const C *)d.gtab;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) gf[q] = gt[(uint32_t)q * blockDim.x + tid];
+  }
+  ExtRaw<Real, RB> raw;
+  if (EXT) ext_loads<Real, RB>(d, base | st_thr, raw);
+
+  C v[R];
+  {
+    const C *src = in + (base | deposit_tid(tid, d.ld_thr_w, TR));
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) v[rho] = ld_elem<NT>(src + deposit_reg<RB>(rho, d.ld_reg_w));
+  }
+  conj_if<RB>(v, d.conj_in != 0);
+  if (d.norm_part) norm_partial<Real, RB>(v, d.norm_part, tile, tid);
+
+  radix_network<Real, RB>(v, RB);
+  apply_factors<Real, RB>(v, gf, C{(Real)1, (Real)0}, false);
+  {
+    // group 1's factors: their reads are in flight during the exchange
+    const C *__restrict__ gt = (const C *)d.gtab1;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) gf[q] = gt[(uint32_t)q * blockDim.x + tid];
+  }
+  if constexpr (sizeof(Real) == 4) {
+    exchange_split<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR);  // half-tile LDS
+  } else {
+    exchange<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR, true);
+  }
+  radix_network<Real, RB>(v, RB);
+  apply_factors<Real, RB>(v, gf, C{(Real)1, (Real)0}, false);
+  lane_swaps<Real, RB, S>(v, tid & 63u);
+  radix_network<Real, RB>(v, S);
+
+  if (EXT) {
+    C f[RB], f0;
+    ext_finish<Real, RB>(d, raw, f, f0);
+    apply_factors<Real, RB>(v, f, f0, true);
+  } else {
+    const Real scale = (Real)d.scale;
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) {
+      v[rho].x *= scale;
+      v[rho].y *= scale;
+    }
+  }
+  conj_if<RB>(v, d.conj_out != 0);
+  const uint32_t obase = d.reverse ? rev_bits(base, d.n) : base;
+  store_tile_raw<Real, RB, NT>(d, v, out + (obase | st_thr));
+}
+
+template <typename Real, int S, bool EXT, bool NT>
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? 256 : 512)
+k_fused_pass3(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  uint32_t tile = blockIdx.x;
+  if (d.xcd_remap) {
+    const uint32_t per = gridDim.x >> 3;
+    tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  }
+  pass3_tile<Real, 5, S, EXT, NT>(d, tile, in, out, reinterpret_cast<cplx<Real> *>(qft_smem),
+                                  threadIdx.x);
+}
+
+int fused_pass_shape(const PassLaunch &L) { return pass_kernel_shape(L); }
 
 template <typename Real, int RB>
 static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, hipStream_t s) {
   auto fn = k_fused_pass<Real, RB>;
-  // which kernel instance: bit in `raised` below
-  const int inst = fused_pass_shape(L) + (fused_pass_shape(L) && L.d.nt ? 10 : 0);
   if constexpr (RB == 5) {
-    if (inst) {
+    const int shape = fused_pass_shape(L);
+    if (shape > 10) {
+      using K = void (*)(const PassDesc, const cplx<Real> *, cplx<Real> *);
+#define QFT_P3(E, N) \
+  {k_fused_pass3<Real, 1, E, N>, k_fused_pass3<Real, 2, E, N>, k_fused_pass3<Real, 3, E, N>}
+      static const K tab3[2][2][3] = {{QFT_P3(false, false), QFT_P3(true, false)},
+                                      {QFT_P3(false, true), QFT_P3(true, true)}};
+#undef QFT_P3
+      fn = tab3[L.d.nt ? 1 : 0][L.d.ext_tw ? 1 : 0][L.d.lane_swap - 1];
+    } else if (shape) {
       using K = void (*)(const PassDesc, const cplx<Real> *, cplx<Real> *);
 #define QFT_P2(E, N)                                                                         \
   {k_fused_pass2<Real, 5, 1, E, N>, k_fused_pass2<Real, 5, 2, E, N>,                        \
@@ -674,11 +838,37 @@ k_batch_group2(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__re
                                  threadIdx.x);
 }
 
+// The same for groups of three-group passes.
+template <typename Real, int S, bool EXT>
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? 256 : 512)
+k_batch_group3(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__restrict__ descs,
+               const BatchIO *__restrict__ io) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  const uint32_t item = blockIdx.x;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].first <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchSeg sg = segs[lo];
+  const BatchIO b = io[sg.desc];
+  pass3_tile<Real, 5, S, EXT, false>(descs[sg.desc], item - sg.first, (const cplx<Real> *)b.in,
+                                     (cplx<Real> *)b.out, reinterpret_cast<cplx<Real> *>(qft_smem),
+                                     threadIdx.x);
+}
+
 template <typename Real, int RB>
 static hipError_t launch_group_t(const BatchGroup &g, hipStream_t s) {
   auto fn = k_batch_group<Real, RB>;
   if constexpr (RB == 5) {
-    if (g.shape) {
+    if (g.shape > 10) {
+      using K = void (*)(const BatchSeg *, int, const PassDesc *, const BatchIO *);
+      static const K tab3[6] = {k_batch_group3<Real, 1, false>, k_batch_group3<Real, 2, false>,
+                                k_batch_group3<Real, 3, false>, k_batch_group3<Real, 1, true>,
+                                k_batch_group3<Real, 2, true>,  k_batch_group3<Real, 3, true>};
+      fn = tab3[g.shape - 11];
+    } else if (g.shape) {
       using K = void (*)(const BatchSeg *, int, const PassDesc *, const BatchIO *);
       static const K tab[10] = {
           k_batch_group2<Real, 1, false>, k_batch_group2<Real, 2, false>,

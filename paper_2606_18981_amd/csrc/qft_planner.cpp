@@ -122,6 +122,42 @@ void build_groups(PassLaunch &L, const PassGeom &g, int r, int n) {
     groups.push_back(gm);
     thr_orders.push_back(thr);
   }
+  // Three radix-32 groups whose last group holds s = 1..3 pass bits: the
+  // middle group keeps pass bits 0..s-1 on lane bits 5, 4, 3 of its thread
+  // map, so that the last group takes them into its low register bits by
+  // cross-lane swaps with the middle group's register bits 0..s-1 instead of
+  // an LDS exchange.  The remaining thread bits are ordered by output
+  // address: after the swaps they are the store map, whose low lanes then
+  // run along contiguous output memory.
+  const int s_lane = m - 2 * r;
+  if (r == 5 && ng == 3 && s_lane >= 1 && s_lane <= 3 && T - r >= 6 && nspec + s_lane <= 6) {
+    std::vector<int> reg1(r), rest;
+    for (int q = 0; q < r; ++q) reg1[q] = nspec + s_lane + q;
+    for (int q = 0; q < T; ++q) {
+      const bool low = q >= nspec && q < nspec + s_lane;
+      if (!low && std::find(reg1.begin(), reg1.end(), q) == reg1.end()) rest.push_back(q);
+    }
+    std::stable_sort(rest.begin(), rest.end(), [&](int a, int b) { return outpos[a] < outpos[b]; });
+    std::vector<int> thr1(T - r, -1);
+    for (int q = 0; q < s_lane; ++q) thr1[5 - q] = nspec + q;
+    size_t next = 0;
+    for (int b = 0; b < T - r; ++b)
+      if (thr1[b] < 0) thr1[b] = rest[next++];
+    std::vector<int> reg2(r), thr2 = thr1;
+    for (int q = 0; q < r; ++q) reg2[q] = q < s_lane ? nspec + q : reg1[q];
+    for (int q = 0; q < s_lane; ++q) thr2[5 - q] = reg1[q];
+    for (int q = 0; q < r; ++q) {
+      pos_set(groups[1].reg_w, q, reg1[q]);
+      pos_set(groups[2].reg_w, q, reg2[q]);
+    }
+    for (int b = 0; b < T - r; ++b) {
+      pos_set(groups[1].thr_w, b, thr1[b]);
+      pos_set(groups[2].thr_w, b, thr2[b]);
+    }
+    thr_orders[1] = thr1;
+    thr_orders[2] = thr2;
+    d.lane_swap = s_lane;
+  }
   // A single group loads in input order; if the output order differs, add an
   // exchange-only group that stores in output order.
   if (ng == 1) {
@@ -158,44 +194,54 @@ int max_thread_bits(int r, bool c128) {
   return r >= 5 ? 9 : 10;
 }
 
-// Per-thread factors of the first register group of every pass that the
-// compile-time two-group kernel runs: entry [q][tid] is the internal-table
-// entry w_{2^MI}^{x << (MI - 1 - jl)} that the group's factor for register
-// bit q of thread tid reads (jl = jbase + q, x = the thread's lower pass bits
-// with those below jl - k cleared for an AQFT).  Copying the table entry
-// keeps the result bitwise the same as reading the table, while the kernel
-// reads 64 consecutive entries per wave instead of 64 scattered ones.
-void build_group_tables(HostPlan &p) {
+// Per-thread factors of a register group of a pass that a compile-time
+// kernel runs (group 0 of the two-group shape, groups 0 and 1 of the
+// three-group shape): entry [q][tid] is the internal-table entry
+// w_{2^MI}^{x << (MI - 1 - jl)} that the group's factor for register bit q of
+// thread tid reads (jl = jbase + q, x = the thread's lower pass bits with
+// those below jl - k cleared for an AQFT).  Copying the table entry keeps the
+// result bitwise the same as reading the table, while the kernel reads 64
+// consecutive entries per wave instead of 64 scattered ones.  Returns the
+// byte offset of the new table in the image.
+size_t add_group_table(HostPlan &p, const PassLaunch &L, const GroupMap &G) {
   const size_t es = p.elem_bytes;
+  const PassDesc &d = L.d;
+  const int TR = d.T - d.r;
+  const int threads = L.threads;
+  const size_t off = p.tables.size();
+  p.tables.resize(align_up(off + (size_t)d.r * threads * es, 256), 0);
+  const int MI1 = d.MI - 1;
+  for (int tid = 0; tid < threads; ++tid) {
+    uint32_t e_thr = 0;
+    for (int b = 0; b < TR; ++b) e_thr |= (uint32_t)((tid >> b) & 1) << pos_get(G.thr_w, b);
+    const uint32_t u = (e_thr >> d.pbase) & ((1u << G.jbase) - 1u);
+    for (int q = 0; q < d.r; ++q) {
+      const size_t dst = off + ((size_t)q * threads + tid) * es;
+      if (q >= G.nst) {
+        put_cplx(p.tables, dst, 0, p.c128, 1.0, 0.0);
+        continue;
+      }
+      const int jl = G.jbase + q;
+      int clear = d.aqft ? jl - d.k : 0;
+      clear = clear < 0 ? 0 : clear;
+      const uint32_t x = clear >= G.jbase ? 0u : ((u >> clear) << clear);
+      const size_t src = p.off_int + ((size_t)x << (MI1 - jl)) * es;
+      memcpy(&p.tables[dst], &p.tables[src], es);
+    }
+  }
+  return off;
+}
+
+void build_group_tables(HostPlan &p) {
   p.off_gtab.assign(p.passes.size(), 0);
+  p.off_gtab1.assign(p.passes.size(), 0);
   for (size_t i = 0; i < p.passes.size(); ++i) {
     const PassLaunch &L = p.passes[i];
-    if (!pass2_shape(L)) continue;
-    const PassDesc &d = L.d;
-    const GroupMap &G = d.grp[0];
-    const int TR = d.T - d.r;
-    const int threads = L.threads;
-    const size_t off = p.tables.size();
-    p.off_gtab[i] = off;
-    p.tables.resize(align_up(off + (size_t)d.r * threads * es, 256), 0);
-    const int MI1 = d.MI - 1;
-    for (int tid = 0; tid < threads; ++tid) {
-      uint32_t e_thr = 0;
-      for (int b = 0; b < TR; ++b) e_thr |= (uint32_t)((tid >> b) & 1) << pos_get(G.thr_w, b);
-      const uint32_t u = (e_thr >> d.pbase) & ((1u << G.jbase) - 1u);
-      for (int q = 0; q < d.r; ++q) {
-        const size_t dst = off + ((size_t)q * threads + tid) * es;
-        if (q >= G.nst) {
-          put_cplx(p.tables, dst, 0, p.c128, 1.0, 0.0);
-          continue;
-        }
-        const int jl = G.jbase + q;
-        int clear = d.aqft ? jl - d.k : 0;
-        clear = clear < 0 ? 0 : clear;
-        const uint32_t x = clear >= G.jbase ? 0u : ((u >> clear) << clear);
-        const size_t src = p.off_int + ((size_t)x << (MI1 - jl)) * es;
-        memcpy(&p.tables[dst], &p.tables[src], es);
-      }
+    if (pass2_shape(L)) {
+      p.off_gtab[i] = add_group_table(p, L, L.d.grp[0]);
+    } else if (pass3_shape(L)) {
+      p.off_gtab[i] = add_group_table(p, L, L.d.grp[0]);
+      p.off_gtab1[i] = add_group_table(p, L, L.d.grp[1]);
     }
   }
 }
@@ -296,8 +342,21 @@ int plan_fused(HostPlan &p, std::string &err) {
         const size_t rows = p.elem_bytes << std::max(0, spec0);
         if (a4 != a && f4 >= 6 && f4 <= hmax && rows >= (wide ? 128u : 256u)) a = a4;
       }
-      widths.push_back(rem - a);
-      for (int i = 0; i < P - 2; ++i) widths.push_back(hmax);
+      // A complex64 first pass that would still hold T - 3 bits or more
+      // (n = 29, 30) gives one bit to an 11-bit middle pass of the
+      // three-group kernel: n = 29 [9, 11, 9] 5.82 ms against [10, 10, 9]
+      // 6.00 ms, n = 30 [10, 11, 9] 12.97 ms against [10, 10, 10] 13.40 ms.
+      // At n = 28 [8, 11, 9] was slower (2.70 against 2.64 ms): the middle
+      // pass then reads 32-byte rows, and four tiles share each 128-byte
+      // line, which L2 evicts between them (1.22x fetched, 1.32x written).
+      int mid = hmax;
+      if (P == 3 && !p.c128 && !p.bitrev && r_cfg == 5 && T - r_cfg >= 6 && rem - a >= T - 3 &&
+          hmax + 1 == 2 * r_cfg + 1 && hmax + 1 <= T) {
+        mid = hmax + 1;
+        a = std::min(amax, T - 4);
+      }
+      widths.push_back(n - (P - 2) * mid - a);
+      for (int i = 0; i < P - 2; ++i) widths.push_back(mid);
       widths.push_back(a);
     } else {
       // Four or more passes leave slack.  A bit-reversing last pass keeps
@@ -453,7 +512,7 @@ int plan_fused(HostPlan &p, std::string &err) {
     L.lds_bytes = d.ngroups > 1 ? (int)(((size_t)1 << Te) * es) : 0;
     // the complex64 two-group kernel exchanges real and imaginary parts in
     // turn through half the tile's LDS (three workgroups per CU at 2^13)
-    if (!p.c128 && pass2_shape(L)) L.lds_bytes /= 2;
+    if (!p.c128 && (pass2_shape(L) || pass3_shape(L))) L.lds_bytes /= 2;
     L.grid = d.ntiles;
     // Streaming loads and stores pay off where a tile reads whole 128-byte
     // lines: where it reads half lines, the neighbouring tile (run at the
@@ -466,9 +525,9 @@ int plan_fused(HostPlan &p, std::string &err) {
       while (run < n && in_tile[run]) ++run;
       const bool lines = (es << run) >= 128;
       const bool big = p.state_bytes >= ((size_t)256 << 20);
-      // (only the compile-time two-group kernel has a streaming form)
+      // (only the compile-time kernels have a streaming form)
       const bool want = (c.nontemporal == 2 && lines) || (c.nontemporal == 0 && lines && big);
-      d.nt = want && pass2_shape(L) ? 1 : 0;
+      d.nt = want && (pass2_shape(L) || pass3_shape(L)) ? 1 : 0;
     }
     d.xcd_remap = (L.grid >= 8 && L.grid % 8 == 0) ? 1 : 0;
     if (natural_multi) {
@@ -643,7 +702,7 @@ void describe_plan(const HostPlan &p, qft_plan_info_t *o) {
       o->pass_bits[i] = d.m;
       o->pass_spec[i] = d.pbase;
       o->pass_reverse[i] = d.reverse;
-      o->pass_kernel[i] = pass2_shape(p.passes[i]);
+      o->pass_kernel[i] = pass_kernel_shape(p.passes[i]);
       o->pass_streaming[i] = d.nt;
     }
   } else {

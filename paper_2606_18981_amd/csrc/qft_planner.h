@@ -47,6 +47,8 @@ struct HostPlan {
   size_t off_int = 0, off_lo = 0, off_hi = 0;
   // per pass: byte offset of its per-thread group-0 factor table, or 0 (none)
   std::vector<size_t> off_gtab;
+  // per pass: the same for group 1 (three-group passes), or 0
+  std::vector<size_t> off_gtab1;
   size_t end_hi = 0;  // end of the high table (the group tables follow)
 
   // gate schedule

@@ -34,7 +34,7 @@ class PassDesc(ctypes.Structure):
         ("n", i32), ("T", i32), ("r", i32), ("m", i32), ("pbase", i32), ("lo", i32),
         ("ngroups", i32), ("reverse", i32), ("ext_tw", i32), ("aqft", i32), ("k", i32),
         ("nfree", i32), ("MI", i32), ("L", i32), ("xcd_remap", i32),
-        ("conj_in", i32), ("conj_out", i32), ("nt", i32), ("ntiles", u32),
+        ("conj_in", i32), ("conj_out", i32), ("nt", i32), ("lane_swap", i32), ("ntiles", u32),
         ("gpos_w", u32 * 4), ("free_w", u32 * 8),
         ("ld_thr_w", u32 * 4), ("ld_reg_w", u32 * 2),
         ("st_thr_w", u32 * 4), ("st_reg_w", u32 * 2),
@@ -42,6 +42,7 @@ class PassDesc(ctypes.Structure):
         ("scale", ctypes.c_double),
         ("tw_int", ctypes.c_void_p), ("tw_lo", ctypes.c_void_p), ("tw_hi", ctypes.c_void_p),
         ("gtab", ctypes.c_void_p),
+        ("gtab1", ctypes.c_void_p),
         ("norm_part", ctypes.c_void_p),
     ]
 
@@ -99,17 +100,19 @@ def get_table_image(n, cutoff, norm, layout, config):
     return np.frombuffer(bytes(buf), dtype=np.uint8), dt
 
 
-def check_group_table(d, launch, image, dt, W):
-    """The planner's per-thread factor table of group 0 (d.gtab is its byte
-    offset in the image) must hold, bit for bit, the internal-table entries
-    that the group's factors read."""
-    if not d.gtab:
+def check_group_table(d, launch, image, dt, W, group=0):
+    """The planner's per-thread factor table of register group `group`
+    (d.gtab for group 0, d.gtab1 for group 1; each a byte offset in the
+    image) must hold, bit for bit, the internal-table entries that the
+    group's factors read."""
+    off = d.gtab if group == 0 else d.gtab1
+    if not off:
         return False
     threads = launch[0]
     RB, TR = d.r, d.T - d.r
-    G = d.grp[0]
+    G = d.grp[group]
     es = np.dtype(dt).itemsize
-    got = image[d.gtab:d.gtab + RB * threads * es].view(dt).reshape(RB, threads)
+    got = image[off:off + RB * threads * es].view(dt).reshape(RB, threads)
     tid = np.arange(threads, dtype=np.int64)
     e = np.zeros_like(tid)
     for b in range(TR):
@@ -123,7 +126,30 @@ def check_group_table(d, launch, image, dt, W):
         clear = max(0, jl - d.k) if d.aqft else 0
         x = np.zeros_like(u) if clear >= G.jbase else (u >> clear) << clear
         want = W[x << (d.MI - 1 - jl)].astype(dt)
-        assert np.array_equal(got[q], want), f"group table row {q} differs"
+        assert np.array_equal(got[q], want), f"group {group} table row {q} differs"
+    return True
+
+
+def check_lane_swap(d, launch):
+    """A three-group pass's last map must be the middle map with register bit
+    q and lane bit 5 - q traded (q < s), as the kernel's cross-lane swaps do,
+    and register bits 0..s-1 of the last map must hold pass bits 0..s-1."""
+    s = d.lane_swap
+    if not s:
+        return False
+    TR = d.T - d.r
+    assert TR >= 6 and d.ngroups == 3 and d.m == 10 + s
+    g1, g2 = d.grp[1], d.grp[2]
+    r1, t1 = P(g1.reg_w)[:d.r], P(g1.thr_w)[:TR]
+    r2, t2 = P(g2.reg_w)[:d.r], P(g2.thr_w)[:TR]
+    for q in range(d.r):
+        want = t1[5 - q] if q < s else r1[q]
+        assert r2[q] == want, "last group's register map is not the swapped middle map"
+    for b in range(TR):
+        want = r1[5 - b] if 5 - s < b <= 5 else t1[b]
+        assert t2[b] == want, "last group's thread map is not the swapped middle map"
+    for q in range(s):
+        assert r2[q] == d.pbase + q, "register bit q of the last group must be pass bit q"
     return True
 
 

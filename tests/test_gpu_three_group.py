@@ -1,0 +1,132 @@
+"""GPU parity of the three-group pass kernel (passes of 11-13 qubits whose
+last register group is reached by cross-lane swaps) against the FP64
+oracle, on the whole output vector.
+
+Explicit pass splits place such a pass first (below-pass diagonal, input
+norm, inverse conjugation on load), in the middle, and last (bit-reversed
+stores, conjugation on store), in complex64 (2^13-element tiles) and
+complex128 (2^12).  Bars as everywhere: relative L2 and max error over the
+RMS amplitude, each <= 1e-5 (complex64) or <= 1e-12 (complex128).  Batched
+runs of the same plans must equal the lone runs bit for bit.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_18981_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": 1e-5, "c128": 1e-12}
+NPDT = {"c64": np.complex64, "c128": np.complex128}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2606_18981_amd import qft
+    return qft
+
+
+def cfg(dtype, split, **kw):
+    c64 = dtype == "c64"
+    c = dict(tile_log2=13 if c64 else 12, radix_log2=5, spec_log2=3 if c64 else 2,
+             rev_spec_log2=3 if c64 else 2, pass_bits=split)
+    c.update(kw)
+    return c
+
+
+def check(y, ref, dtype, what):
+    e = O.error_norms(y, ref)
+    print(f"[parity] {what}: rel_l2={e['rel_l2']:.3e} max_err={e['max_err']:.3e}", flush=True)
+    assert e["rel_l2"] <= TOL[dtype] and e["max_err"] <= TOL[dtype], (what, e)
+
+
+def run(torch, Q, x, n, k, norm, dtype, order, config, inverse=False, norm_out=False):
+    print(f"[gpu] n={n} k={k} norm={norm} {dtype} {order} {config} inverse={inverse}",
+          flush=True)
+    plan = Q.Plan(n, k, norm, dtype, order, "fused", config, inverse=inverse)
+    assert any(plan.info.pass_kernel[p] > 10 for p in range(plan.info.num_passes))
+    t = torch.from_numpy(x.astype(NPDT[dtype])).cuda()
+    nrm = torch.zeros(1, dtype=torch.float64, device="cuda") if norm_out else None
+    plan.execute(t, norm_out=nrm)
+    torch.cuda.synchronize()
+    y = t.cpu().numpy().astype(np.complex128)
+    plan.close()
+    return (y, float(nrm.item())) if norm_out else y
+
+
+SPLITS = [
+    ("c64", [6, 11, 7]), ("c64", [5, 12, 7]), ("c64", [4, 13, 7]), ("c64", [11, 6, 7]),
+    ("c64", [7, 6, 11]), ("c64", [11, 13]), ("c128", [5, 11, 6]), ("c128", [5, 12, 5]),
+    ("c128", [6, 5, 11]),
+]
+
+
+@pytest.mark.parametrize("dtype,split", SPLITS)
+def test_three_group_splits(torch_cuda, Q, dtype, split):
+    n = sum(split)
+    x = I.gaussian(n, 5100 + n)
+    c = cfg(dtype, split)
+    for k, order, norm in ((-1, "natural", "unitary"), (6, "natural", "unitary"),
+                           (10, "bitrev", "none")):
+        y = run(torch_cuda, Q, x, n, k, norm, dtype, order, c)
+        ref = O.qft_fused_targets(x, None if k < 0 else k, norm, order)
+        check(y, ref, dtype, f"n={n} {split} k={k} {order} {norm}")
+
+
+@pytest.mark.parametrize("dtype,split", [("c64", [11, 6, 7]), ("c64", [5, 12, 7]),
+                                         ("c128", [6, 5, 11])])
+def test_three_group_inverse_and_norm(torch_cuda, Q, dtype, split):
+    n = sum(split)
+    x = I.gaussian(n, 5200 + n) * 3.0
+    c = cfg(dtype, split)
+    y = run(torch_cuda, Q, x, n, -1, "inv_n", dtype, "natural", c, inverse=True)
+    check(y, O.qft_fused_targets(x, None, "inv_n", "natural", inverse=True), dtype,
+          f"inverse n={n} {split}")
+    y, nrm = run(torch_cuda, Q, x, n, 8, "unitary", dtype, "natural", c, norm_out=True)
+    check(y, O.qft_fused_targets(x, 8), dtype, f"norm n={n} {split}")
+    assert nrm == pytest.approx(float(np.linalg.norm(x)), rel=1e-6 if dtype == "c64" else 1e-12)
+
+
+def test_three_group_streaming(torch_cuda, Q):
+    # non-temporal loads and stores on a three-group pass that reads whole
+    # lines: the bit-reversing last pass loads 2^11-element contiguous runs
+    n = 24
+    x = I.gaussian(n, 5300)
+    for dtype, split in (("c64", [7, 6, 11]), ("c128", [7, 6, 11])):
+        c = cfg(dtype, split, nontemporal=2)
+        info = Q.describe(n, -1, "unitary", dtype, "natural", "fused", c)
+        assert info.pass_kernel[2] > 10 and info.pass_streaming[2] == 1
+        y = run(torch_cuda, Q, x, n, -1, "unitary", dtype, "natural", c)
+        check(y, O.qft_fused_targets(x, None), dtype, f"streaming {dtype} {split}")
+
+
+def test_three_group_batch_bitwise(torch_cuda, Q):
+    torch = torch_cuda
+    specs = [(20, -1, [4, 11, 5]), (21, 8, [4, 12, 5]), (22, -1, [4, 13, 5]),
+             (20, 6, [5, 4, 11]), (18, -1, [7, 11])]
+    plans, xs, alone = [], [], []
+    for i, (n, k, split) in enumerate(specs):
+        p = Q.Plan(n, k, "unitary", "c64", "natural", "fused", cfg("c64", split))
+        plans.append(p)
+        x = I.uniform_pm1(n, 5400 + i)
+        t = torch.from_numpy(x.astype(np.complex64)).cuda()
+        xs.append(t)
+        a = t.clone()
+        p.execute(a)
+        alone.append(a)
+    print("[gpu] batch of three-group plans", flush=True)
+    Q.execute_batch(plans, xs, graph=True)
+    torch.cuda.synchronize()
+    for (n, k, split), t, a in zip(specs, xs, alone):
+        assert torch.equal(t, a), f"batched n={n} {split} differs from the lone run"
+    for p in plans:
+        p.close()

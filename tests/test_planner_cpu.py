@@ -308,9 +308,9 @@ def test_wide_first_pass():
     rows) takes one more tile bit: n = 30 at the default tiles, and a small
     plan with 2^10 tiles, checked by emulation."""
     info = Q.describe(30, dtype="c64")
-    assert list(info.pass_bits)[:3] == [10, 10, 10]
-    assert list(info.pass_spec)[:3] == [4, 3, 3]
-    for n, spec in ((28, [4, 3, 4]), (29, [4, 3, 4])):
+    assert list(info.pass_bits)[:3] == [10, 11, 9]
+    assert list(info.pass_spec)[:3] == [4, 2, 4]
+    for n, spec in ((28, [4, 3, 4]), (29, [4, 2, 4])):
         assert list(Q.describe(n, dtype="c64").pass_spec)[:3] == spec
     assert list(Q.describe(29, dtype="c128").pass_spec)[:3] == [3, 2, 2]  # complex64 only
     cfg = dict(tile_log2=10, radix_log2=4, spec_log2=3, rev_spec_log2=3)
@@ -348,7 +348,7 @@ def test_three_pass_last_pass_rule():
     the wider complex64 first-pass tile), and otherwise split the outer
     passes evenly."""
     expect = {("c64", 24): [7, 10, 7], ("c64", 25): [6, 10, 9], ("c64", 26): [7, 10, 9],
-              ("c64", 27): [8, 10, 9], ("c64", 28): [9, 10, 9], ("c64", 29): [10, 10, 9],
+              ("c64", 27): [8, 10, 9], ("c64", 28): [9, 10, 9], ("c64", 29): [9, 11, 9],
               ("c128", 24): [6, 10, 8], ("c128", 26): [8, 10, 8], ("c128", 27): [8, 10, 9],
               ("c128", 28): [9, 10, 9]}
     for (dtype, n), bits in expect.items():
@@ -356,6 +356,23 @@ def test_three_pass_last_pass_rule():
         assert list(info.pass_bits)[:info.num_passes] == bits, (dtype, n)
     # bit-reversed plans have no reversing pass: the even split stays
     assert list(Q.describe(26, dtype="c64", order="bitrev").pass_bits)[:3] != [7, 10, 9]
+
+
+def test_three_group_middle_pass_rule():
+    """Complex64 three-pass plans whose first pass would hold T - 3 bits or
+    more (n = 29, 30) run an 11-bit middle pass on the three-group kernel;
+    smaller sizes, complex128 and bit-reversed plans keep 10-bit middles."""
+    for n, bits in ((29, [9, 11, 9]), (30, [10, 11, 9])):
+        info = Q.describe(n, dtype="c64")
+        assert list(info.pass_bits)[:3] == bits
+        assert info.pass_kernel[1] == 10 + 1 + 3 + 0  # below-pass diagonal, s = 1
+    for n in range(21, 29):
+        info = Q.describe(n, dtype="c64")
+        assert max(info.pass_kernel[p] for p in range(info.num_passes)) <= 10
+    assert max(Q.describe(29, dtype="c128").pass_bits) == 10
+    assert list(Q.describe(29, dtype="c64", order="bitrev").pass_bits)[:3] == [9, 10, 10]
+    # an AQFT whose radix drops below 32 keeps the two-group split
+    assert list(Q.describe(30, 3, dtype="c64").pass_bits)[:3] == [10, 10, 10]
 
 
 def test_one_pass_radix():
@@ -366,3 +383,59 @@ def test_one_pass_radix():
         got = {n: E.get_pass(n, -1, "unitary", lay, None, 0)[0].r for n in (9, 10, 11, 12, 13)}
         assert got == {9: 5, 10: 5, 11: 4, 12: 4, 13: 5}, (dtype, got)
         assert E.get_pass(12, -1, "unitary", lay, dict(radix_log2=5), 0)[0].r == 5
+
+
+# Three-group passes (10 + s qubits, s = 1..3): groups 0 and 1 of radix 32,
+# the last group reached by cross-lane swaps.  Splits put such a pass first
+# (below-pass diagonal, input norm), in the middle, and last (bit-reversed
+# stores); complex64 tiles of 2^13 and complex128 tiles of 2^12.
+THREE_GROUP = [
+    ("c64", [3, 11, 4]), ("c64", [2, 12, 4]), ("c64", [2, 13, 3]), ("c64", [11, 4, 3]),
+    ("c64", [4, 3, 11]), ("c64", [5, 13]), ("c128", [4, 11, 3]), ("c128", [3, 12, 3]),
+    ("c128", [3, 3, 12]),
+]
+
+
+def _three_group_cfg(dtype, split):
+    c64 = dtype == "c64"
+    return dict(tile_log2=13 if c64 else 12, radix_log2=5, spec_log2=3 if c64 else 2,
+                rev_spec_log2=3 if c64 else 2, pass_bits=split)
+
+
+@pytest.mark.parametrize("dtype,split", THREE_GROUP)
+def test_three_group_pass_maps_and_tables(dtype, split):
+    n = sum(split)
+    cfg = _three_group_cfg(dtype, split)
+    lay = Q.layout_flags(dtype)
+    info = Q.describe(n, -1, "unitary", dtype, "natural", "fused", cfg)
+    W = E.get_tables(n, -1, "unitary", lay, cfg)[0]
+    image, dt = E.get_table_image(n, -1, "unitary", lay, cfg)
+    for p in range(info.num_passes):
+        d, launch = E.get_pass(n, -1, "unitary", lay, cfg, p)
+        m = split[p]
+        if m > 10:
+            s = m - 10
+            assert d.lane_swap == s
+            assert info.pass_kernel[p] == 10 + 1 + (3 if d.ext_tw else 0) + (s - 1)
+            assert E.check_lane_swap(d, launch)
+            assert E.check_group_table(d, launch, image, dt, W, group=0)
+            assert E.check_group_table(d, launch, image, dt, W, group=1)
+            # the exchange between groups 0 and 1 still uses the half-tile
+            # LDS area in complex64
+            assert launch[1] == (1 << d.T) * (4 if dtype == "c64" else 16)
+        else:
+            assert d.lane_swap == 0 and not d.gtab1
+
+
+@pytest.mark.parametrize("dtype,split", THREE_GROUP)
+def test_emulated_three_group_passes(dtype, split):
+    n = sum(split)
+    cfg = _three_group_cfg(dtype, split)
+    x = I.gaussian(n, 2200 + n)
+    tol = 1e-12 if dtype == "c128" else 2e-6
+    y = E.emulate(x, n, -1, "unitary", dtype, "natural", cfg)
+    assert O.rel_l2(y, O.qft_fused_targets(x, None, "unitary", "natural")) < tol
+    y = E.emulate(x, n, 6, "unitary", dtype, "bitrev", cfg)
+    assert O.rel_l2(y, O.qft_fused_targets(x, 6, "unitary", "bitrev")) < tol
+    y = E.emulate(x, n, -1, "none", dtype, "natural", cfg, inverse=True)
+    assert O.rel_l2(y, O.qft_fused_targets(x, None, "none", "natural", inverse=True)) < tol
