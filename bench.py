@@ -113,6 +113,26 @@ def cpu_baseline_and_accuracy(torch, Q, n, dtype, cutoff):
     return baseline, accuracy
 
 
+def pass_kernel_name(info, p, dtype):
+    """Name of the kernel instance that runs pass p of a plan, as the kernel
+    trace prints it (without the argument list)."""
+    real = "float" if dtype == "c64" else "double"
+    sh = info.pass_kernel[p]
+    st = "true" if info.pass_streaming[p] else "false"
+    r = info.config.radix_log2
+    threads = 1 << (info.pass_bits[p] + info.pass_spec[p] - r)
+    wide = dtype == "c64" and threads == 512  # the four-wave form
+    if 1 <= sh <= 10:
+        nst, ext = (sh - 1) % 5 + 1, "true" if sh > 5 else "false"
+        return (f"k_fused_pass2w<5, {nst}, {ext}, {st}>" if wide
+                else f"k_fused_pass2<{real}, 5, {nst}, {ext}, {st}>")
+    if sh >= 11:
+        s, ext = (sh - 11) % 3 + 1, "true" if sh >= 14 else "false"
+        return (f"k_fused_pass3w<{s}, {ext}, {st}>" if wide
+                else f"k_fused_pass3<{real}, {s}, {ext}, {st}>")
+    return f"k_fused_pass<{real}, {r}>"
+
+
 def profile_name(n, dtype, cutoff):
     tag = "exact" if cutoff < 0 else f"k{cutoff}"
     return f"fused_pass_n{n}_{dtype}_{tag}.md"
@@ -419,16 +439,7 @@ def main():
     gflops = flops / (ms_per_step * 1e-3) / 1e9
     state_bytes = info.state_bytes
     per_launch_bytes = 2 * state_bytes  # one read and one write of the state
-    real = "float" if args.dtype == "c64" else "double"
-    names = []
-    for p in range(info.num_passes):
-        sh = info.pass_kernel[p]
-        st = "true" if info.pass_streaming[p] else "false"
-        if sh:
-            ext = "true" if sh > 5 else "false"
-            names.append(f"k_fused_pass2<{real}, 5, {(sh - 1) % 5 + 1}, {ext}, {st}>")
-        else:
-            names.append(f"k_fused_pass<{real}, {info.config.radix_log2}>")
+    names = [pass_kernel_name(info, p, args.dtype) for p in range(info.num_passes)]
     # every pass is one launch of a pass kernel instance; the dominant kernel
     # is the slowest pass (HIP events on the launch stream, timed region)
     per_pass = [{"pass": p, "kernel": names[p], "qubits": info.pass_bits[p],

@@ -104,7 +104,14 @@ typedef void *qft_stream_t; /* hipStream_t */
  *              summing to n (all zero = planner's choice: the fewest passes,
  *              middle passes as wide as the tile allows, the rest split
  *              between the first and the last pass, whose rows lie furthest
- *              apart in memory)                                             */
+ *              apart in memory)
+ * pass_tile_log2: tile bits of each pass, most significant pass first (0 =
+ *              planner's choice: tile_log2, or tile_log2 + 1 for the passes
+ *              below which other qubits lie, in complex64 plans of at least
+ *              2^26 elements, so that their rows hold 2^(tile - bits)
+ *              contiguous elements; such 512-thread workgroups run the
+ *              four-wave form of the kernels, two per CU).  A pass's
+ *              spectator bits are its tile bits minus its qubits.          */
 typedef struct qft_config {
   int tile_log2;
   int radix_log2;
@@ -112,6 +119,7 @@ typedef struct qft_config {
   int rev_spec_log2;
   int nontemporal;
   int pass_bits[QFT_MAX_PASSES];
+  int pass_tile_log2[QFT_MAX_PASSES];
 } qft_config_t;
 
 /* Description of a plan.  Gate counts are those of the circuit before any
@@ -126,10 +134,13 @@ typedef struct qft_plan_info {
   int pass_bits[QFT_MAX_PASSES]; /* qubits applied by pass p                 */
   int pass_spec[QFT_MAX_PASSES]; /* spectator (coalescing) bits of pass p    */
   int pass_reverse[QFT_MAX_PASSES]; /* pass p writes bit-reversed addresses  */
-  int pass_kernel[QFT_MAX_PASSES];  /* 0: the generic pass kernel; else the
-                                       compile-time two-group kernel, shape
+  int pass_kernel[QFT_MAX_PASSES];  /* 0: the generic pass kernel; 1..10:
+                                       the compile-time two-group kernel,
                                        1 + 5 * (below-pass diagonal) +
-                                       (stages of the last group - 1)        */
+                                       (stages of the last group - 1);
+                                       11..16: the compile-time three-group
+                                       kernel, 11 + 3 * (below-pass
+                                       diagonal) + (qubits - 11)             */
   int pass_streaming[QFT_MAX_PASSES]; /* pass p uses non-temporal access    */
   qft_config_t config;
   long long gates_h, gates_cr, gates_swap;

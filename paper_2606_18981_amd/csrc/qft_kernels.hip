@@ -176,6 +176,56 @@ __device__ __forceinline__ void apply_factors(cplx<Real> (&v)[1 << RB], const cp
   }
 }
 
+// The same product in two steps: every element is multiplied by its
+// low-half subset factor, then by its high-half one.  Two complex multiplies
+// per element, as in apply_factors, but only one subset table is live at a
+// time: the four-wave kernels (128 VGPRs per lane) need the registers.
+template <typename Real, int RB>
+__device__ __forceinline__ void apply_factors_lean(cplx<Real> (&v)[1 << RB],
+                                                   const cplx<Real> (&f)[RB], cplx<Real> f0,
+                                                   bool apply0) {
+  constexpr int R = 1 << RB;
+  constexpr int SL = RB / 2;
+  constexpr int NL = 1 << SL;
+  constexpr int NH = 1 << (RB - SL);
+  {
+    cplx<Real> Fl[NL];
+    Fl[0] = f0;
+#pragma unroll
+    for (int a = 1; a < NL; ++a) {
+      const int top = 31 - __builtin_clz(a);
+      const int rest = a & ~(1 << top);
+      Fl[a] = (rest == 0 && !apply0) ? f[top] : cmul(Fl[rest], f[top]);
+    }
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) {
+      const int a = rho & (NL - 1);
+      if (a != 0 || apply0) v[rho] = cmul(v[rho], Fl[a]);
+    }
+  }
+  cplx<Real> Fh[NH];
+  Fh[0] = cplx<Real>{(Real)1, (Real)0};
+#pragma unroll
+  for (int b = 1; b < NH; ++b) {
+    const int top = 31 - __builtin_clz(b);
+    const int rest = b & ~(1 << top);
+    Fh[b] = rest == 0 ? f[SL + top] : cmul(Fh[rest], f[SL + top]);
+  }
+#pragma unroll
+  for (int rho = 0; rho < R; ++rho) {
+    const int b = rho >> SL;
+    if (b != 0) v[rho] = cmul(v[rho], Fh[b]);
+  }
+}
+
+// Subset-product factors: the four-wave kernels (W4) take the two-step form.
+template <typename Real, int RB, bool W4>
+__device__ __forceinline__ void apply_factors_k(cplx<Real> (&v)[1 << RB], const cplx<Real> (&f)[RB],
+                                                cplx<Real> f0, bool apply0) {
+  if constexpr (W4) apply_factors_lean<Real, RB>(v, f, f0, apply0);
+  else apply_factors<Real, RB>(v, f, f0, apply0);
+}
+
 // Index of the tile's first element: the tile number deposited into the
 // non-tile bit positions.
 __device__ __forceinline__ uint32_t tile_base(const PassDesc &d, uint32_t tile) {
@@ -501,7 +551,12 @@ k_fused_pass(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
 // registers, no path merges are needed: the generic kernel spends about a
 // third of its vector instructions on register moves that reconcile its
 // run-time branches.
-template <typename Real, int RB, int NSTL, bool EXT, bool NT>
+//
+// W4: the four-wave form for 512-thread workgroups of 2^14 complex64
+// elements (two workgroups per CU at 128 VGPRs per lane): the reads of the
+// below-pass diagonal's table entries are issued after the exchange and the
+// factors are applied in two steps, so that fewer registers are live.
+template <typename Real, int RB, int NSTL, bool EXT, bool NT, bool W4 = false>
 __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, const cplx<Real> *in,
                                            cplx<Real> *out, cplx<Real> *lds, uint32_t tid) {
   using C = cplx<Real>;
@@ -520,7 +575,7 @@ __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, con
     for (int q = 0; q < RB; ++q) gf[q] = gt[(uint32_t)q * blockDim.x + tid];
   }
   ExtRaw<Real, RB> raw;
-  if (EXT) ext_loads<Real, RB>(d, base | st_thr, raw);
+  if (EXT && !W4) ext_loads<Real, RB>(d, base | st_thr, raw);
 
   C v[R];
   {
@@ -532,18 +587,22 @@ __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, con
   if (d.norm_part) norm_partial<Real, RB>(v, d.norm_part, tile, tid);
 
   radix_network<Real, RB>(v, RB);
-  apply_factors<Real, RB>(v, gf, C{(Real)1, (Real)0}, false);
+  apply_factors_k<Real, RB, W4>(v, gf, C{(Real)1, (Real)0}, false);
+  // (four-wave form: keep the exchange's LDS addresses from being computed
+  // early, where they would be live across the network and spill)
+  if constexpr (W4) __builtin_amdgcn_sched_barrier(0);
   if constexpr (sizeof(Real) == 4) {
     exchange_split<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR);  // half-tile LDS
   } else {
     exchange<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR, true);
   }
+  if (EXT && W4) ext_loads<Real, RB>(d, base | st_thr, raw);
   radix_network<Real, RB>(v, NSTL);
 
   if (EXT) {
     C f[RB], f0;
     ext_finish<Real, RB>(d, raw, f, f0);
-    apply_factors<Real, RB>(v, f, f0, true);
+    apply_factors_k<Real, RB, W4>(v, f, f0, true);
   } else {
     const Real scale = (Real)d.scale;
 #pragma unroll
@@ -653,7 +712,8 @@ __device__ __forceinline__ void lane_swaps(cplx<Real> (&v)[1 << RB], uint32_t la
 // bits 5, 4, 3 of group 1's thread map) and applied by a radix-2^S network,
 // and (EXT) the diagonal of the controls below the pass.  Wider middle
 // passes let the first and last passes keep long contiguous rows.
-template <typename Real, int RB, int S, bool EXT, bool NT>
+// W4 as for pass2_tile.
+template <typename Real, int RB, int S, bool EXT, bool NT, bool W4 = false>
 __device__ __forceinline__ void pass3_tile(const PassDesc &d, uint32_t tile, const cplx<Real> *in,
                                            cplx<Real> *out, cplx<Real> *lds, uint32_t tid) {
   using C = cplx<Real>;
@@ -669,7 +729,7 @@ __device__ __forceinline__ void pass3_tile(const PassDesc &d, uint32_t tile, con
     for (int q = 0; q < RB; ++q) gf[q] = gt[(uint32_t)q * blockDim.x + tid];
   }
   ExtRaw<Real, RB> raw;
-  if (EXT) ext_loads<Real, RB>(d, base | st_thr, raw);
+  if (EXT && !W4) ext_loads<Real, RB>(d, base | st_thr, raw);
 
   C v[R];
   {
@@ -681,27 +741,29 @@ __device__ __forceinline__ void pass3_tile(const PassDesc &d, uint32_t tile, con
   if (d.norm_part) norm_partial<Real, RB>(v, d.norm_part, tile, tid);
 
   radix_network<Real, RB>(v, RB);
-  apply_factors<Real, RB>(v, gf, C{(Real)1, (Real)0}, false);
+  apply_factors_k<Real, RB, W4>(v, gf, C{(Real)1, (Real)0}, false);
   {
     // group 1's factors: their reads are in flight during the exchange
     const C *__restrict__ gt = (const C *)d.gtab1;
 #pragma unroll
     for (int q = 0; q < RB; ++q) gf[q] = gt[(uint32_t)q * blockDim.x + tid];
   }
+  if constexpr (W4) __builtin_amdgcn_sched_barrier(0);  // as in pass2_tile
   if constexpr (sizeof(Real) == 4) {
     exchange_split<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR);  // half-tile LDS
   } else {
     exchange<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR, true);
   }
+  if (EXT && W4) ext_loads<Real, RB>(d, base | st_thr, raw);
   radix_network<Real, RB>(v, RB);
-  apply_factors<Real, RB>(v, gf, C{(Real)1, (Real)0}, false);
+  apply_factors_k<Real, RB, W4>(v, gf, C{(Real)1, (Real)0}, false);
   lane_swaps<Real, RB, S>(v, tid & 63u);
   radix_network<Real, RB>(v, S);
 
   if (EXT) {
     C f[RB], f0;
     ext_finish<Real, RB>(d, raw, f, f0);
-    apply_factors<Real, RB>(v, f, f0, true);
+    apply_factors_k<Real, RB, W4>(v, f, f0, true);
   } else {
     const Real scale = (Real)d.scale;
 #pragma unroll
@@ -728,6 +790,38 @@ k_fused_pass3(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
                                   threadIdx.x);
 }
 
+// The four-wave forms of the compile-time kernels, for 512-thread
+// complex64 workgroups (2^14-element tiles): 128 VGPRs per lane, so that two
+// workgroups share a CU.
+template <int RB, int NSTL, bool EXT, bool NT>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+k_fused_pass2w(const PassDesc d, const cplx<float> *in, cplx<float> *out) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  uint32_t tile = blockIdx.x;
+  if (d.xcd_remap) {
+    const uint32_t per = gridDim.x >> 3;
+    tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  }
+  pass2_tile<float, RB, NSTL, EXT, NT, true>(d, tile, in, out,
+                                            reinterpret_cast<cplx<float> *>(qft_smem), threadIdx.x);
+}
+
+template <int S, bool EXT, bool NT>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+k_fused_pass3w(const PassDesc d, const cplx<float> *in, cplx<float> *out) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  uint32_t tile = blockIdx.x;
+  if (d.xcd_remap) {
+    const uint32_t per = gridDim.x >> 3;
+    tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  }
+  pass3_tile<float, 5, S, EXT, NT, true>(d, tile, in, out,
+                                         reinterpret_cast<cplx<float> *>(qft_smem), threadIdx.x);
+}
+
+// The four-wave form runs every complex64 compile-time pass of 512 threads.
+inline bool four_wave(const PassLaunch &L, bool c128) { return !c128 && L.threads == 512; }
+
 int fused_pass_shape(const PassLaunch &L) { return pass_kernel_shape(L); }
 
 template <typename Real, int RB>
@@ -743,6 +837,15 @@ static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, 
                                       {QFT_P3(false, true), QFT_P3(true, true)}};
 #undef QFT_P3
       fn = tab3[L.d.nt ? 1 : 0][L.d.ext_tw ? 1 : 0][L.d.lane_swap - 1];
+      if constexpr (sizeof(Real) == 4) {
+        if (four_wave(L, false)) {
+#define QFT_P3W(E, N) {k_fused_pass3w<1, E, N>, k_fused_pass3w<2, E, N>, k_fused_pass3w<3, E, N>}
+          static const K tab3w[2][2][3] = {{QFT_P3W(false, false), QFT_P3W(true, false)},
+                                           {QFT_P3W(false, true), QFT_P3W(true, true)}};
+#undef QFT_P3W
+          fn = tab3w[L.d.nt ? 1 : 0][L.d.ext_tw ? 1 : 0][L.d.lane_swap - 1];
+        }
+      }
     } else if (shape) {
       using K = void (*)(const PassDesc, const cplx<Real> *, cplx<Real> *);
 #define QFT_P2(E, N)                                                                         \
@@ -753,6 +856,17 @@ static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, 
                                      {QFT_P2(false, true), QFT_P2(true, true)}};
 #undef QFT_P2
       fn = tab[L.d.nt ? 1 : 0][L.d.ext_tw ? 1 : 0][L.d.grp[1].nst - 1];
+      if constexpr (sizeof(Real) == 4) {
+        if (four_wave(L, false)) {
+#define QFT_P2W(E, N)                                                                        \
+  {k_fused_pass2w<5, 1, E, N>, k_fused_pass2w<5, 2, E, N>, k_fused_pass2w<5, 3, E, N>,       \
+   k_fused_pass2w<5, 4, E, N>, k_fused_pass2w<5, 5, E, N>}
+          static const K tabw[2][2][5] = {{QFT_P2W(false, false), QFT_P2W(true, false)},
+                                          {QFT_P2W(false, true), QFT_P2W(true, true)}};
+#undef QFT_P2W
+          fn = tabw[L.d.nt ? 1 : 0][L.d.ext_tw ? 1 : 0][L.d.grp[1].nst - 1];
+        }
+      }
     }
   }
   if (L.lds_bytes > 65536) {
@@ -858,6 +972,47 @@ k_batch_group3(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__re
                                      threadIdx.x);
 }
 
+// Four-wave batch forms (512-thread complex64 groups), so that a transform
+// gives bit-identical results alone and in a batch.
+template <int NSTL, bool EXT>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+k_batch_group2w(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__restrict__ descs,
+                const BatchIO *__restrict__ io) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  const uint32_t item = blockIdx.x;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].first <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchSeg sg = segs[lo];
+  const BatchIO b = io[sg.desc];
+  pass2_tile<float, 5, NSTL, EXT, false, true>(descs[sg.desc], item - sg.first,
+                                               (const cplx<float> *)b.in, (cplx<float> *)b.out,
+                                               reinterpret_cast<cplx<float> *>(qft_smem),
+                                               threadIdx.x);
+}
+
+template <int S, bool EXT>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+k_batch_group3w(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__restrict__ descs,
+                const BatchIO *__restrict__ io) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  const uint32_t item = blockIdx.x;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].first <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchSeg sg = segs[lo];
+  const BatchIO b = io[sg.desc];
+  pass3_tile<float, 5, S, EXT, false, true>(descs[sg.desc], item - sg.first,
+                                            (const cplx<float> *)b.in, (cplx<float> *)b.out,
+                                            reinterpret_cast<cplx<float> *>(qft_smem), threadIdx.x);
+}
+
 template <typename Real, int RB>
 static hipError_t launch_group_t(const BatchGroup &g, hipStream_t s) {
   auto fn = k_batch_group<Real, RB>;
@@ -868,6 +1023,14 @@ static hipError_t launch_group_t(const BatchGroup &g, hipStream_t s) {
                                 k_batch_group3<Real, 3, false>, k_batch_group3<Real, 1, true>,
                                 k_batch_group3<Real, 2, true>,  k_batch_group3<Real, 3, true>};
       fn = tab3[g.shape - 11];
+      if constexpr (sizeof(Real) == 4) {
+        if (g.threads == 512) {
+          static const K tab3w[6] = {k_batch_group3w<1, false>, k_batch_group3w<2, false>,
+                                     k_batch_group3w<3, false>, k_batch_group3w<1, true>,
+                                     k_batch_group3w<2, true>,  k_batch_group3w<3, true>};
+          fn = tab3w[g.shape - 11];
+        }
+      }
     } else if (g.shape) {
       using K = void (*)(const BatchSeg *, int, const PassDesc *, const BatchIO *);
       static const K tab[10] = {
@@ -877,6 +1040,16 @@ static hipError_t launch_group_t(const BatchGroup &g, hipStream_t s) {
           k_batch_group2<Real, 2, true>,  k_batch_group2<Real, 3, true>,
           k_batch_group2<Real, 4, true>,  k_batch_group2<Real, 5, true>};
       fn = tab[g.shape - 1];
+      if constexpr (sizeof(Real) == 4) {
+        if (g.threads == 512) {
+          static const K tabw[10] = {
+              k_batch_group2w<1, false>, k_batch_group2w<2, false>, k_batch_group2w<3, false>,
+              k_batch_group2w<4, false>, k_batch_group2w<5, false>, k_batch_group2w<1, true>,
+              k_batch_group2w<2, true>,  k_batch_group2w<3, true>,  k_batch_group2w<4, true>,
+              k_batch_group2w<5, true>};
+          fn = tabw[g.shape - 1];
+        }
+      }
     }
   }
   if (g.lds_bytes > 65536) {

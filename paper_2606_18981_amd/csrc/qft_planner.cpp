@@ -63,6 +63,12 @@ int check_config(const qft_config_t &c, std::string &err) {
     err = "spec_log2 and rev_spec_log2 must be in [0, tile_log2)";
     return QFT_ERR_INVALID;
   }
+  for (int i = 0; i < QFT_MAX_PASSES; ++i) {
+    if (c.pass_tile_log2[i] < 0 || c.pass_tile_log2[i] > kMaxTile) {
+      err = "pass_tile_log2 entries must be 0 (planner's choice) or at most 15";
+      return QFT_ERR_INVALID;
+    }
+  }
   if ((1 << (c.tile_log2 - c.radix_log2)) > (c.radix_log2 >= 5 ? 512 : 1024)) {
     err = "too many threads per workgroup (2^(tile_log2 - radix_log2) must be <= 1024, "
           "or <= 512 for radix_log2 = 5)";
@@ -292,7 +298,7 @@ int plan_fused(HostPlan &p, std::string &err) {
       return QFT_ERR_INVALID;
     }
     for (int i = 0; i < nexplicit; ++i) {
-      if (c.pass_bits[i] > T) {
+      if (c.pass_bits[i] > std::max(T, c.pass_tile_log2[i])) {
         err = "a pass cannot apply more qubits than the tile holds";
         return QFT_ERR_INVALID;
       }
@@ -342,16 +348,20 @@ int plan_fused(HostPlan &p, std::string &err) {
         const size_t rows = p.elem_bytes << std::max(0, spec0);
         if (a4 != a && f4 >= 6 && f4 <= hmax && rows >= (wide ? 128u : 256u)) a = a4;
       }
-      // A complex64 first pass that would still hold T - 3 bits or more
-      // (n = 29, 30) gives one bit to an 11-bit middle pass of the
-      // three-group kernel: n = 29 [9, 11, 9] 5.82 ms against [10, 10, 9]
-      // 6.00 ms, n = 30 [10, 11, 9] 12.97 ms against [10, 10, 10] 13.40 ms.
-      // At n = 28 [8, 11, 9] was slower (2.70 against 2.64 ms): the middle
-      // pass then reads 32-byte rows, and four tiles share each 128-byte
-      // line, which L2 evicts between them (1.22x fetched, 1.32x written).
+      // A complex64 first pass that would hold T - 3 bits gives one bit to
+      // an 11-bit middle pass of the three-group kernel, so that it keeps
+      // T - 4 bits (n = 29: [9, 11, 9]).  With 2^13 tiles everywhere that
+      // split took 5.82 ms against 6.00 for [10, 10, 9]; with the wider
+      // high-pass tiles below all three measured 5.22 ms.  Not at n = 30:
+      // [10, 11, 9] 11.23 ms against [10, 10, 10] 10.89 ms; nor at n = 28:
+      // [8, 11, 9] 2.57 against [9, 10, 9] 2.45 ms.  (With 2^13 tiles the
+      // 11-bit middle pass reads 32-byte rows, four tiles share each
+      // 128-byte line, and L2 evicts it between them: 1.22x fetched, 1.32x
+      // written.)
       int mid = hmax;
-      if (P == 3 && !p.c128 && !p.bitrev && r_cfg == 5 && T - r_cfg >= 6 && rem - a >= T - 3 &&
-          hmax + 1 == 2 * r_cfg + 1 && hmax + 1 <= T) {
+      if (P == 3 && !p.c128 && !p.bitrev && r_cfg == 5 && T - r_cfg >= 6 && rem - a == T - 3 &&
+          n - (hmax + 1) - std::min(amax, T - 4) == T - 4 && hmax + 1 == 2 * r_cfg + 1 &&
+          hmax + 1 <= T) {
         mid = hmax + 1;
         a = std::min(amax, T - 4);
       }
@@ -383,25 +393,49 @@ int plan_fused(HostPlan &p, std::string &err) {
   {
     int top = n;
     const int P = (int)widths.size();
+    // Complex64 passes below which other qubits lie take one more tile bit
+    // in three-pass plans of 2^28 to 2^30 elements: 2^14-element tiles of
+    // 512 threads, run by the four-wave form of the kernels (128 VGPRs, two
+    // workgroups per CU), whose rows of 2^(tile - bits) contiguous elements
+    // are twice as long.  n = 28: first pass 1.006 -> 0.856 ms (256-byte
+    // rows), middle 0.800 -> 0.769 ms, 2.63 -> 2.45 ms in all; the
+    // bit-reversing last pass keeps 2^13 (0.83 against 0.99 ms) unless its
+    // rows would be shorter than 128 bytes (n = 30 [10, 10, 10]: 10.89 ms
+    // with every pass at 2^14, 11.62 with the last at 2^13, 13.40 before).
+    // n = 26, 27 and 31 measured 1-3 % slower with the wider tiles.
+    const bool wide_high = !p.c128 && !p.bitrev && P == 3 && n >= 28 && n <= 30 && r_cfg == 5 &&
+                           T + 1 <= r_cfg + max_thread_bits(r_cfg, p.c128) && T + 1 <= kMaxTile;
     for (int i = 0; i < P; ++i) {
       PassGeom g;
       g.m = widths[i];
       g.lo = top - g.m;
       top = g.lo;
+      int Tq = T;
+      if (i < kMaxPasses && c.pass_tile_log2[i] > 0) {
+        Tq = c.pass_tile_log2[i];
+        if (Tq < g.m || Tq > kMaxTile) {
+          err = "pass_tile_log2 must lie between the pass's qubits and 15";
+          return QFT_ERR_INVALID;
+        }
+      } else if (wide_high && (i + 1 < P || ((size_t)p.elem_bytes << (T - g.m)) < 128)) {
+        Tq = T + 1;
+      } else if (i == 0 && !p.c128 && P >= 3 && T - g.m < 4) {
+        // The first pass reads rows 2^lo elements apart; with fewer than 4
+        // row bits (64-byte complex64 rows, at n = 30) one more tile bit is
+        // worth the lower occupancy: measured 5.25 against 6.17 ms at n = 30.
+        Tq = T + 1;
+      }
       if (i + 1 < P) {
         // a high pass applies the diagonal of lower controls per register
         // group, which needs every register bit to be a pass bit (r <= m)
         const int r = std::min(r_cfg, g.m);
-        // The first pass reads rows 2^lo elements apart; with fewer than 4
-        // row bits (64-byte complex64 rows, at n = 30) one more tile bit is
-        // worth the lower occupancy: measured 5.25 against 6.17 ms at n = 30.
-        const int Tw = (i == 0 && !p.c128 && P >= 3 && T - g.m < 4) ? T + 1 : T;
-        const int Tp = std::min(Tw, r + max_thread_bits(r, p.c128));
+        const int Tp = std::min(Tq, r + max_thread_bits(r, p.c128));
         const int nspec = std::min(Tp - g.m, g.lo);
         for (int q = 0; q < nspec; ++q) g.spec_g.push_back(q);
       } else {
         g.reverse = !p.bitrev;
-        const int nspec = std::min(T - g.m, n - g.m);
+        const int Tp = std::min(Tq, std::min(r_cfg, Tq) + max_thread_bits(std::min(r_cfg, Tq), p.c128));
+        const int nspec = std::min(std::max(Tp, g.m) - g.m, n - g.m);
         if (p.bitrev) {
           for (int q = 0; q < nspec; ++q) g.spec_g.push_back(g.m + q);
         } else {
@@ -670,6 +704,7 @@ int build_host_plan(int n, int cutoff, int norm, int layout, const qft_config_t 
     c.spec_log2 = std::min(c.spec_log2, c.tile_log2 - 1);
     c.rev_spec_log2 = std::min(c.rev_spec_log2, c.tile_log2 - 1);
     for (int i = 0; i < QFT_MAX_PASSES; ++i) c.pass_bits[i] = cfg->pass_bits[i];
+    for (int i = 0; i < QFT_MAX_PASSES; ++i) c.pass_tile_log2[i] = cfg->pass_tile_log2[i];
   }
   p.cfg = c;
   p.auto_radix = !cfg || cfg->radix_log2 == 0;

@@ -296,16 +296,18 @@ int qft_tune_save(const char *path) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (const auto &kv : g_table) {
     const Entry &e = kv.second;
-    std::string split;
+    std::string split, tiles;
     for (int i = 0; i < QFT_MAX_PASSES && e.cfg.pass_bits[i] > 0; ++i)
       split += (i ? "," : "") + std::to_string(e.cfg.pass_bits[i]);
+    for (int i = 0; i < QFT_MAX_PASSES; ++i)
+      tiles += (i ? "," : "") + std::to_string(e.cfg.pass_tile_log2[i]);
     fprintf(f,
             "{\"arch\":\"%s\",\"n\":%d,\"cutoff\":%d,\"layout\":%d,\"tile_log2\":%d,"
             "\"radix_log2\":%d,\"spec_log2\":%d,\"rev_spec_log2\":%d,\"nontemporal\":%d,"
-            "\"pass_bits\":\"%s\",\"ms\":%.6g}\n",
+            "\"pass_bits\":\"%s\",\"pass_tile_log2\":\"%s\",\"ms\":%.6g}\n",
             arch.c_str(), std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
             e.cfg.tile_log2, e.cfg.radix_log2, e.cfg.spec_log2, e.cfg.rev_spec_log2,
-            e.cfg.nontemporal, split.c_str(), e.ms);
+            e.cfg.nontemporal, split.c_str(), tiles.c_str(), e.ms);
   }
   fclose(f);
   return QFT_OK;
@@ -343,6 +345,16 @@ int qft_tune_load(const char *path) {
       for (int i = 0; i < QFT_MAX_PASSES && *q; ++i) {
         char *end = nullptr;
         cfg.pass_bits[i] = (int)strtol(q, &end, 10);
+        if (end == q) break;
+        q = *end == ',' ? end + 1 : end;
+      }
+    }
+    std::string tiles;
+    if (get_str(line, "pass_tile_log2", &tiles) && !tiles.empty()) {
+      const char *q = tiles.c_str();
+      for (int i = 0; i < QFT_MAX_PASSES && *q; ++i) {
+        char *end = nullptr;
+        cfg.pass_tile_log2[i] = (int)strtol(q, &end, 10);
         if (end == q) break;
         q = *end == ',' ? end + 1 : end;
       }

@@ -52,7 +52,8 @@ class Config(ctypes.Structure):
     _fields_ = [("tile_log2", ctypes.c_int), ("radix_log2", ctypes.c_int),
                 ("spec_log2", ctypes.c_int), ("rev_spec_log2", ctypes.c_int),
                 ("nontemporal", ctypes.c_int),
-                ("pass_bits", ctypes.c_int * QFT_MAX_PASSES)]
+                ("pass_bits", ctypes.c_int * QFT_MAX_PASSES),
+                ("pass_tile_log2", ctypes.c_int * QFT_MAX_PASSES)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -201,9 +202,10 @@ def _config(config) -> Optional[Config]:
         return config
     c = Config()
     for k, v in dict(config).items():
-        if k == "pass_bits":
+        if k in ("pass_bits", "pass_tile_log2"):
+            arr = getattr(c, k)
             for i, b in enumerate(list(v)[:QFT_MAX_PASSES]):
-                c.pass_bits[i] = int(b)
+                arr[i] = int(b)
         else:
             setattr(c, k, int(v))
     return c
@@ -360,12 +362,16 @@ def fill_random(x, dist="gaussian", seed: int = 0, stream_id: int = 0, stream=No
 # ---- autotuner ------------------------------------------------------------
 
 def _cfg_dict(c: Config) -> dict:
-    d = {f: getattr(c, f) for f, _ in Config._fields_ if f not in ("pass_bits", "nontemporal")}
+    d = {f: getattr(c, f) for f, _ in Config._fields_
+         if f not in ("pass_bits", "pass_tile_log2", "nontemporal")}
     if c.nontemporal:
         d["nontemporal"] = c.nontemporal
     pb = [int(x) for x in c.pass_bits if int(x) > 0]
     if pb:
         d["pass_bits"] = pb
+    pt = [int(x) for x in c.pass_tile_log2]
+    if any(pt):
+        d["pass_tile_log2"] = pt[:max(i + 1 for i, x in enumerate(pt) if x)]
     return d
 
 

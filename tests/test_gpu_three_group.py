@@ -49,11 +49,13 @@ def check(y, ref, dtype, what):
     assert e["rel_l2"] <= TOL[dtype] and e["max_err"] <= TOL[dtype], (what, e)
 
 
-def run(torch, Q, x, n, k, norm, dtype, order, config, inverse=False, norm_out=False):
+def run(torch, Q, x, n, k, norm, dtype, order, config, inverse=False, norm_out=False,
+        three=True):
     print(f"[gpu] n={n} k={k} norm={norm} {dtype} {order} {config} inverse={inverse}",
           flush=True)
     plan = Q.Plan(n, k, norm, dtype, order, "fused", config, inverse=inverse)
-    assert any(plan.info.pass_kernel[p] > 10 for p in range(plan.info.num_passes))
+    if three:
+        assert any(plan.info.pass_kernel[p] > 10 for p in range(plan.info.num_passes))
     t = torch.from_numpy(x.astype(NPDT[dtype])).cuda()
     nrm = torch.zeros(1, dtype=torch.float64, device="cuda") if norm_out else None
     plan.execute(t, norm_out=nrm)
@@ -128,5 +130,57 @@ def test_three_group_batch_bitwise(torch_cuda, Q):
     torch.cuda.synchronize()
     for (n, k, split), t, a in zip(specs, xs, alone):
         assert torch.equal(t, a), f"batched n={n} {split} differs from the lone run"
+    for p in plans:
+        p.close()
+
+
+# ---- the four-wave forms: 2^14-element complex64 tiles of 512 threads ------
+
+WIDE = [
+    ([6, 10, 6], [14, 14, 13]), ([7, 11, 6], [14, 14, 13]), ([6, 10, 8], [14, 14, 14]),
+    ([5, 12, 7], [13, 14, 14]),
+]
+
+
+@pytest.mark.parametrize("split,tiles", WIDE)
+def test_four_wave_wide_tiles(torch_cuda, Q, split, tiles):
+    n = sum(split)
+    x = I.gaussian(n, 5500 + n)
+    c = cfg("c64", split, pass_tile_log2=tiles)
+    info = Q.describe(n, -1, "unitary", "c64", "natural", "fused", c)
+    for p, t in enumerate(tiles):
+        assert info.pass_spec[p] == t - split[p]
+    for k, order, norm in ((-1, "natural", "unitary"), (6, "bitrev", "inv_n")):
+        y = run(torch_cuda, Q, x, n, k, norm, "c64", order, c, three=False)
+        ref = O.qft_fused_targets(x, None if k < 0 else k, norm, order)
+        check(y, ref, "c64", f"wide n={n} {split} {tiles} k={k} {order}")
+    y = run(torch_cuda, Q, x, n, -1, "none", "c64", "natural", c, inverse=True, three=False)
+    check(y, O.qft_fused_targets(x, None, "none", "natural", inverse=True), "c64",
+          f"wide inverse n={n} {split}")
+    y, nrm = run(torch_cuda, Q, x, n, 8, "unitary", "c64", "natural", c, norm_out=True,
+                 three=False)
+    check(y, O.qft_fused_targets(x, 8), "c64", f"wide norm n={n} {split}")
+    assert nrm == pytest.approx(float(np.linalg.norm(x)), rel=1e-6)
+
+
+def test_four_wave_batch_bitwise(torch_cuda, Q):
+    torch = torch_cuda
+    specs = [(20, -1, [5, 10, 5], [14, 14, 13]), (21, 8, [5, 11, 5], [14, 14, 14]),
+             (22, -1, [6, 10, 6], [14, 13, 14])]
+    plans, xs, alone = [], [], []
+    for i, (n, k, split, tiles) in enumerate(specs):
+        p = Q.Plan(n, k, "unitary", "c64", "natural", "fused",
+                   cfg("c64", split, pass_tile_log2=tiles))
+        plans.append(p)
+        t = torch.from_numpy(I.uniform_pm1(n, 5600 + i).astype(np.complex64)).cuda()
+        xs.append(t)
+        a = t.clone()
+        p.execute(a)
+        alone.append(a)
+    print("[gpu] batch of four-wave plans", flush=True)
+    Q.execute_batch(plans, xs, graph=True)
+    torch.cuda.synchronize()
+    for (n, k, split, tiles), t, a in zip(specs, xs, alone):
+        assert torch.equal(t, a), f"batched n={n} {split} {tiles} differs from the lone run"
     for p in plans:
         p.close()

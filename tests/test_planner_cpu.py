@@ -261,7 +261,8 @@ def test_nontemporal_rule():
         lay = Q.layout_flags(dtype)
         P = Q.describe(n, dtype=dtype, config=cfg).num_passes
         return [E.get_pass(n, -1, "unitary", lay, cfg, p)[0].nt for p in range(P)]
-    assert nts(28) == [1, 0, 1]        # 128 B rows, 64 B rows, contiguous
+    assert nts(28) == [1, 1, 1]        # 256 B rows, 128 B rows (2^14 tiles), contiguous
+    assert nts(27) == [1, 0, 1]        # 256 B rows, 64 B rows, contiguous
     assert nts(27, "c128") == [1, 0, 1]
     assert nts(24) == [0, 0, 0]        # 128 MiB state: stays cached
     assert nts(25) == [1, 0, 1]        # 256 MiB
@@ -307,10 +308,12 @@ def test_wide_first_pass():
     """A first pass that would hold fewer than 4 row bits (64-byte complex64
     rows) takes one more tile bit: n = 30 at the default tiles, and a small
     plan with 2^10 tiles, checked by emulation."""
-    info = Q.describe(30, dtype="c64")
-    assert list(info.pass_bits)[:3] == [10, 11, 9]
-    assert list(info.pass_spec)[:3] == [4, 2, 4]
-    for n, spec in ((28, [4, 3, 4]), (29, [4, 2, 4])):
+    # n = 28..30 complex64 passes get 2^14 tiles anyway (wide high passes);
+    # the rule shows with those turned off by explicit 2^13 pass tiles
+    info = Q.describe(30, dtype="c64", config=dict(pass_tile_log2=[0, 13, 13]))
+    assert list(info.pass_bits)[:3] == [10, 10, 10]
+    assert list(info.pass_spec)[:3] == [4, 3, 3]
+    for n, spec in ((28, [5, 4, 4]), (29, [5, 3, 4]), (30, [4, 4, 4])):
         assert list(Q.describe(n, dtype="c64").pass_spec)[:3] == spec
     assert list(Q.describe(29, dtype="c128").pass_spec)[:3] == [3, 2, 2]  # complex64 only
     cfg = dict(tile_log2=10, radix_log2=4, spec_log2=3, rev_spec_log2=3)
@@ -359,20 +362,64 @@ def test_three_pass_last_pass_rule():
 
 
 def test_three_group_middle_pass_rule():
-    """Complex64 three-pass plans whose first pass would hold T - 3 bits or
-    more (n = 29, 30) run an 11-bit middle pass on the three-group kernel;
-    smaller sizes, complex128 and bit-reversed plans keep 10-bit middles."""
-    for n, bits in ((29, [9, 11, 9]), (30, [10, 11, 9])):
-        info = Q.describe(n, dtype="c64")
-        assert list(info.pass_bits)[:3] == bits
-        assert info.pass_kernel[1] == 10 + 1 + 3 + 0  # below-pass diagonal, s = 1
-    for n in range(21, 29):
+    """A complex64 three-pass plan whose first pass would hold T - 3 bits and
+    T - 4 after giving one to the middle pass (n = 29) runs an 11-bit middle
+    pass on the three-group kernel; other sizes, complex128 and bit-reversed
+    plans keep 10-bit middles."""
+    info = Q.describe(29, dtype="c64")
+    assert list(info.pass_bits)[:3] == [9, 11, 9]
+    assert info.pass_kernel[1] == 10 + 1 + 3 + 0  # below-pass diagonal, s = 1
+    assert list(Q.describe(30, dtype="c64").pass_bits)[:3] == [10, 10, 10]
+    for n in list(range(21, 29)) + [30]:
         info = Q.describe(n, dtype="c64")
         assert max(info.pass_kernel[p] for p in range(info.num_passes)) <= 10
     assert max(Q.describe(29, dtype="c128").pass_bits) == 10
     assert list(Q.describe(29, dtype="c64", order="bitrev").pass_bits)[:3] == [9, 10, 10]
     # an AQFT whose radix drops below 32 keeps the two-group split
     assert list(Q.describe(30, 3, dtype="c64").pass_bits)[:3] == [10, 10, 10]
+
+
+def test_wide_high_pass_tiles():
+    """Complex64 three-pass plans of 2^28..2^30 elements give every pass
+    below which other qubits lie a 2^14-element tile of 512 threads (the
+    four-wave kernels), and the last pass too where its rows would otherwise
+    be shorter than 128 bytes; other sizes, complex128 and bit-reversed plans
+    keep 2^13 (complex128 2^12)."""
+    lay = Q.layout_flags("c64")
+    expect = {28: [14, 14, 13], 29: [14, 14, 13], 30: [14, 14, 14]}
+    for n, tiles in expect.items():
+        info = Q.describe(n, dtype="c64")
+        for p in range(3):
+            d, launch = E.get_pass(n, -1, "unitary", lay, None, p)
+            assert d.T == tiles[p] and launch[0] == 1 << (tiles[p] - 5), (n, p)
+            assert info.pass_spec[p] == tiles[p] - info.pass_bits[p]
+    for n in (24, 25, 26, 27, 31):
+        info = Q.describe(n, dtype="c64")
+        for p in range(info.num_passes):
+            d, _ = E.get_pass(n, -1, "unitary", lay, None, p)
+            assert d.T <= 13 or (n == 31 and p == 0), (n, p, d.T)
+    for p in range(3):
+        d, _ = E.get_pass(28, -1, "unitary", Q.layout_flags("c128"), None, p)
+        assert d.T == 12
+        d, _ = E.get_pass(28, -1, "unitary", Q.layout_flags("c64", "bitrev"), None, p)
+        assert d.T == 13
+
+
+def test_pass_tile_config():
+    """pass_tile_log2 sets each pass's tile (its spectators are tile minus
+    qubits); out-of-range entries are refused; the plan still computes the
+    transform (emulated)."""
+    cfg = dict(tile_log2=10, radix_log2=4, spec_log2=2, rev_spec_log2=2, pass_bits=[6, 7, 5],
+               pass_tile_log2=[11, 9, 12])
+    info = Q.describe(18, -1, "unitary", "c128", "natural", "fused", cfg)
+    assert list(info.pass_spec)[:3] == [5, 2, 7]
+    x = I.gaussian(18, 18)
+    for k in (None, 5):
+        y = E.emulate(x, 18, -1 if k is None else k, "unitary", "c128", "natural", cfg)
+        assert O.rel_l2(y, O.qft_fused_targets(x, k)) < 1e-12
+    for bad in ([5, 13, 13], [16, 13, 13], [-1, 0, 0]):
+        with pytest.raises(Q.QftError):
+            Q.describe(18, config=dict(pass_bits=[6, 7, 5], pass_tile_log2=bad))
 
 
 def test_one_pass_radix():
