@@ -124,11 +124,11 @@ def pass_kernel_name(info, p, dtype):
     wide = dtype == "c64" and threads == 512  # the four-wave form
     if 1 <= sh <= 10:
         nst, ext = (sh - 1) % 5 + 1, "true" if sh > 5 else "false"
-        return (f"k_fused_pass2w<5, {nst}, {ext}, {st}>" if wide
+        return (f"k_fused_pass2w<float, 5, {nst}, {ext}, {st}>" if wide
                 else f"k_fused_pass2<{real}, 5, {nst}, {ext}, {st}>")
     if sh >= 11:
         s, ext = (sh - 11) % 3 + 1, "true" if sh >= 14 else "false"
-        return (f"k_fused_pass3w<{s}, {ext}, {st}>" if wide
+        return (f"k_fused_pass3w<float, {s}, {ext}, {st}>" if wide
                 else f"k_fused_pass3<{real}, {s}, {ext}, {st}>")
     return f"k_fused_pass<{real}, {r}>"
 

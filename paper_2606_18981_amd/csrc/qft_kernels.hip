@@ -340,7 +340,11 @@ __device__ __forceinline__ void exchange(cplx<Real> (&v)[1 << RB], cplx<Real> *l
 // fit a CU's 160 KiB instead of two.  Slots are the tile positions
 // themselves: with 4-byte slots the XOR fold measured slower (2.64-2.67 ms
 // against 2.61 ms at 2^28).
-template <typename Real, int RB>
+//
+// FENCE: the four-wave kernels keep the compiler from computing the LDS
+// addresses of all four phases up front (64 of them would be live at once,
+// and with the 64 data registers the 128-VGPR budget spills).
+template <typename Real, int RB, bool FENCE = false>
 __device__ __forceinline__ void exchange_split(cplx<Real> (&v)[1 << RB], cplx<Real> *lds_c,
                                                const GroupMap &P, const GroupMap &G,
                                                uint32_t tid, int TR) {
@@ -352,14 +356,17 @@ __device__ __forceinline__ void exchange_split(cplx<Real> (&v)[1 << RB], cplx<Re
   for (int rho = 0; rho < R; ++rho)
     lds[sp | deposit_reg<RB>(rho, P.reg_w)] = v[rho].x;
   __syncthreads();
+  if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int rho = 0; rho < R; ++rho)
     v[rho].x = lds[sg | deposit_reg<RB>(rho, G.reg_w)];
   __syncthreads();
+  if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int rho = 0; rho < R; ++rho)
     lds[sp | deposit_reg<RB>(rho, P.reg_w)] = v[rho].y;
   __syncthreads();
+  if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int rho = 0; rho < R; ++rho)
     v[rho].y = lds[sg | deposit_reg<RB>(rho, G.reg_w)];
@@ -586,13 +593,18 @@ __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, con
   conj_if<RB>(v, d.conj_in != 0);
   if (d.norm_part) norm_partial<Real, RB>(v, d.norm_part, tile, tid);
 
+  // (four-wave form: scheduling fences around the first network keep the
+  // loads, the network and the factors from being interleaved into a
+  // register peak above the 128-VGPR budget)
+  if constexpr (W4) __builtin_amdgcn_sched_barrier(0);
   radix_network<Real, RB>(v, RB);
+  if constexpr (W4) __builtin_amdgcn_sched_barrier(0);
   apply_factors_k<Real, RB, W4>(v, gf, C{(Real)1, (Real)0}, false);
   // (four-wave form: keep the exchange's LDS addresses from being computed
   // early, where they would be live across the network and spill)
   if constexpr (W4) __builtin_amdgcn_sched_barrier(0);
   if constexpr (sizeof(Real) == 4) {
-    exchange_split<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR);  // half-tile LDS
+    exchange_split<Real, RB, W4>(v, lds, d.grp[0], d.grp[1], tid, TR);  // half-tile LDS
   } else {
     exchange<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR, true);
   }
@@ -740,7 +752,12 @@ __device__ __forceinline__ void pass3_tile(const PassDesc &d, uint32_t tile, con
   conj_if<RB>(v, d.conj_in != 0);
   if (d.norm_part) norm_partial<Real, RB>(v, d.norm_part, tile, tid);
 
+  // (four-wave form: scheduling fences around the first network keep the
+  // loads, the network and the factors from being interleaved into a
+  // register peak above the 128-VGPR budget)
+  if constexpr (W4) __builtin_amdgcn_sched_barrier(0);
   radix_network<Real, RB>(v, RB);
+  if constexpr (W4) __builtin_amdgcn_sched_barrier(0);
   apply_factors_k<Real, RB, W4>(v, gf, C{(Real)1, (Real)0}, false);
   {
     // group 1's factors: their reads are in flight during the exchange
@@ -750,7 +767,7 @@ __device__ __forceinline__ void pass3_tile(const PassDesc &d, uint32_t tile, con
   }
   if constexpr (W4) __builtin_amdgcn_sched_barrier(0);  // as in pass2_tile
   if constexpr (sizeof(Real) == 4) {
-    exchange_split<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR);  // half-tile LDS
+    exchange_split<Real, RB, W4>(v, lds, d.grp[0], d.grp[1], tid, TR);  // half-tile LDS
   } else {
     exchange<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR, true);
   }
@@ -790,37 +807,45 @@ k_fused_pass3(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
                                   threadIdx.x);
 }
 
-// The four-wave forms of the compile-time kernels, for 512-thread
-// complex64 workgroups (2^14-element tiles): 128 VGPRs per lane, so that two
-// workgroups share a CU.
-template <int RB, int NSTL, bool EXT, bool NT>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
-k_fused_pass2w(const PassDesc d, const cplx<float> *in, cplx<float> *out) {
+// The lean (four-wave) forms of the compile-time kernels, for 512-thread
+// complex64 workgroups of 2^14-element tiles: the W4 code path (table reads
+// of the below-pass diagonal after the exchange, two-step factors,
+// scheduling fences) at 128 VGPRs, four waves per SIMD, two workgroups per
+// CU.  (The same path for complex128 at 256 VGPRs, two waves per SIMD
+// instead of one, measured slower: 5.98 against 5.50 ms at n = 28, the
+// late table reads costing more than the second workgroup gains.)
+#define QFT_LEAN_BOUNDS(Real) \
+  __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+
+template <typename Real, int RB, int NSTL, bool EXT, bool NT>
+__global__ void QFT_LEAN_BOUNDS(Real)
+k_fused_pass2w(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
   extern __shared__ __align__(16) unsigned char qft_smem[];
   uint32_t tile = blockIdx.x;
   if (d.xcd_remap) {
     const uint32_t per = gridDim.x >> 3;
     tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
   }
-  pass2_tile<float, RB, NSTL, EXT, NT, true>(d, tile, in, out,
-                                            reinterpret_cast<cplx<float> *>(qft_smem), threadIdx.x);
+  pass2_tile<Real, RB, NSTL, EXT, NT, true>(d, tile, in, out,
+                                           reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x);
 }
 
-template <int S, bool EXT, bool NT>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
-k_fused_pass3w(const PassDesc d, const cplx<float> *in, cplx<float> *out) {
+template <typename Real, int S, bool EXT, bool NT>
+__global__ void QFT_LEAN_BOUNDS(Real)
+k_fused_pass3w(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
   extern __shared__ __align__(16) unsigned char qft_smem[];
   uint32_t tile = blockIdx.x;
   if (d.xcd_remap) {
     const uint32_t per = gridDim.x >> 3;
     tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
   }
-  pass3_tile<float, 5, S, EXT, NT, true>(d, tile, in, out,
-                                         reinterpret_cast<cplx<float> *>(qft_smem), threadIdx.x);
+  pass3_tile<Real, 5, S, EXT, NT, true>(d, tile, in, out,
+                                        reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x);
 }
 
-// The four-wave form runs every complex64 compile-time pass of 512 threads.
-inline bool four_wave(const PassLaunch &L, bool c128) { return !c128 && L.threads == 512; }
+// The lean form runs every complex64 compile-time pass of 512 threads.
+inline bool lean_form(const PassLaunch &L) { return L.threads == 512; }
+inline bool lean_group(const BatchGroup &g) { return g.threads == 512; }
 
 int fused_pass_shape(const PassLaunch &L) { return pass_kernel_shape(L); }
 
@@ -838,8 +863,9 @@ static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, 
 #undef QFT_P3
       fn = tab3[L.d.nt ? 1 : 0][L.d.ext_tw ? 1 : 0][L.d.lane_swap - 1];
       if constexpr (sizeof(Real) == 4) {
-        if (four_wave(L, false)) {
-#define QFT_P3W(E, N) {k_fused_pass3w<1, E, N>, k_fused_pass3w<2, E, N>, k_fused_pass3w<3, E, N>}
+        if (lean_form(L)) {
+#define QFT_P3W(E, N) \
+  {k_fused_pass3w<Real, 1, E, N>, k_fused_pass3w<Real, 2, E, N>, k_fused_pass3w<Real, 3, E, N>}
           static const K tab3w[2][2][3] = {{QFT_P3W(false, false), QFT_P3W(true, false)},
                                            {QFT_P3W(false, true), QFT_P3W(true, true)}};
 #undef QFT_P3W
@@ -857,10 +883,11 @@ static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, 
 #undef QFT_P2
       fn = tab[L.d.nt ? 1 : 0][L.d.ext_tw ? 1 : 0][L.d.grp[1].nst - 1];
       if constexpr (sizeof(Real) == 4) {
-        if (four_wave(L, false)) {
+        if (lean_form(L)) {
 #define QFT_P2W(E, N)                                                                        \
-  {k_fused_pass2w<5, 1, E, N>, k_fused_pass2w<5, 2, E, N>, k_fused_pass2w<5, 3, E, N>,       \
-   k_fused_pass2w<5, 4, E, N>, k_fused_pass2w<5, 5, E, N>}
+  {k_fused_pass2w<Real, 5, 1, E, N>, k_fused_pass2w<Real, 5, 2, E, N>,                       \
+   k_fused_pass2w<Real, 5, 3, E, N>, k_fused_pass2w<Real, 5, 4, E, N>,                       \
+   k_fused_pass2w<Real, 5, 5, E, N>}
           static const K tabw[2][2][5] = {{QFT_P2W(false, false), QFT_P2W(true, false)},
                                           {QFT_P2W(false, true), QFT_P2W(true, true)}};
 #undef QFT_P2W
@@ -972,10 +999,10 @@ k_batch_group3(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__re
                                      threadIdx.x);
 }
 
-// Four-wave batch forms (512-thread complex64 groups), so that a transform
-// gives bit-identical results alone and in a batch.
-template <int NSTL, bool EXT>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+// Lean batch forms (see k_fused_pass2w), so that a transform gives
+// bit-identical results alone and in a batch.
+template <typename Real, int NSTL, bool EXT>
+__global__ void QFT_LEAN_BOUNDS(Real)
 k_batch_group2w(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__restrict__ descs,
                 const BatchIO *__restrict__ io) {
   extern __shared__ __align__(16) unsigned char qft_smem[];
@@ -988,14 +1015,14 @@ k_batch_group2w(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__r
   }
   const BatchSeg sg = segs[lo];
   const BatchIO b = io[sg.desc];
-  pass2_tile<float, 5, NSTL, EXT, false, true>(descs[sg.desc], item - sg.first,
-                                               (const cplx<float> *)b.in, (cplx<float> *)b.out,
-                                               reinterpret_cast<cplx<float> *>(qft_smem),
-                                               threadIdx.x);
+  pass2_tile<Real, 5, NSTL, EXT, false, true>(descs[sg.desc], item - sg.first,
+                                              (const cplx<Real> *)b.in, (cplx<Real> *)b.out,
+                                              reinterpret_cast<cplx<Real> *>(qft_smem),
+                                              threadIdx.x);
 }
 
-template <int S, bool EXT>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+template <typename Real, int S, bool EXT>
+__global__ void QFT_LEAN_BOUNDS(Real)
 k_batch_group3w(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__restrict__ descs,
                 const BatchIO *__restrict__ io) {
   extern __shared__ __align__(16) unsigned char qft_smem[];
@@ -1008,9 +1035,9 @@ k_batch_group3w(const BatchSeg *__restrict__ segs, int nseg, const PassDesc *__r
   }
   const BatchSeg sg = segs[lo];
   const BatchIO b = io[sg.desc];
-  pass3_tile<float, 5, S, EXT, false, true>(descs[sg.desc], item - sg.first,
-                                            (const cplx<float> *)b.in, (cplx<float> *)b.out,
-                                            reinterpret_cast<cplx<float> *>(qft_smem), threadIdx.x);
+  pass3_tile<Real, 5, S, EXT, false, true>(descs[sg.desc], item - sg.first,
+                                           (const cplx<Real> *)b.in, (cplx<Real> *)b.out,
+                                           reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x);
 }
 
 template <typename Real, int RB>
@@ -1024,10 +1051,11 @@ static hipError_t launch_group_t(const BatchGroup &g, hipStream_t s) {
                                 k_batch_group3<Real, 2, true>,  k_batch_group3<Real, 3, true>};
       fn = tab3[g.shape - 11];
       if constexpr (sizeof(Real) == 4) {
-        if (g.threads == 512) {
-          static const K tab3w[6] = {k_batch_group3w<1, false>, k_batch_group3w<2, false>,
-                                     k_batch_group3w<3, false>, k_batch_group3w<1, true>,
-                                     k_batch_group3w<2, true>,  k_batch_group3w<3, true>};
+        if (lean_group(g)) {
+          static const K tab3w[6] = {
+              k_batch_group3w<Real, 1, false>, k_batch_group3w<Real, 2, false>,
+              k_batch_group3w<Real, 3, false>, k_batch_group3w<Real, 1, true>,
+              k_batch_group3w<Real, 2, true>,  k_batch_group3w<Real, 3, true>};
           fn = tab3w[g.shape - 11];
         }
       }
@@ -1041,12 +1069,13 @@ static hipError_t launch_group_t(const BatchGroup &g, hipStream_t s) {
           k_batch_group2<Real, 4, true>,  k_batch_group2<Real, 5, true>};
       fn = tab[g.shape - 1];
       if constexpr (sizeof(Real) == 4) {
-        if (g.threads == 512) {
+        if (lean_group(g)) {
           static const K tabw[10] = {
-              k_batch_group2w<1, false>, k_batch_group2w<2, false>, k_batch_group2w<3, false>,
-              k_batch_group2w<4, false>, k_batch_group2w<5, false>, k_batch_group2w<1, true>,
-              k_batch_group2w<2, true>,  k_batch_group2w<3, true>,  k_batch_group2w<4, true>,
-              k_batch_group2w<5, true>};
+              k_batch_group2w<Real, 1, false>, k_batch_group2w<Real, 2, false>,
+              k_batch_group2w<Real, 3, false>, k_batch_group2w<Real, 4, false>,
+              k_batch_group2w<Real, 5, false>, k_batch_group2w<Real, 1, true>,
+              k_batch_group2w<Real, 2, true>,  k_batch_group2w<Real, 3, true>,
+              k_batch_group2w<Real, 4, true>,  k_batch_group2w<Real, 5, true>};
           fn = tabw[g.shape - 1];
         }
       }
