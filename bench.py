@@ -293,23 +293,84 @@ def bench_configs(torch, Q):
     return rows
 
 
+def bench_sizes(torch, Q, sizes=range(24, 31), reps=5):
+    """Exact transforms across sizes in both element types: the sum of the
+    per-pass HIP-event times (mean over `reps` executes, best of three), as
+    a fraction of 8 TB/s both for the plan's own passes and for the
+    three-pass floor 2*3*N*S (a plan with an extra pass moves more)."""
+    rows = []
+    for dtype in ("c64", "c128"):
+        for n in sizes:
+            N = 1 << n
+            x = torch.empty(N, dtype=torch.complex64 if dtype == "c64" else torch.complex128,
+                            device="cuda")
+            Q.fill_random(x, "gaussian", seed=1002)
+            plan = Q.Plan(n, -1, "unitary", dtype, "natural")
+            info = plan.info
+            for _ in range(2):
+                plan.execute(x)
+            best = None
+            for _ in range(3):
+                torch.cuda.synchronize()
+                plan.set_timing(True)
+                for _ in range(reps):
+                    plan.execute(x)
+                torch.cuda.synchronize()
+                ms, _ = plan.pass_times()
+                plan.set_timing(False)
+                if best is None or sum(ms) < sum(best):
+                    best = ms
+            t = sum(best) * 1e-3
+            S = 8 if dtype == "c64" else 16
+            rows.append({"n": n, "dtype": dtype, "ms": sum(best),
+                         "pass_bits": list(info.pass_bits)[:info.num_passes],
+                         "pass_ms": best,
+                         "frac_plan": info.hbm_bytes / t / 1e9 / HBM_PEAK_GBS,
+                         "frac_three_pass_floor": 6 * N * S / t / 1e9 / HBM_PEAK_GBS,
+                         "dominant_pass_frac": 2 * N * S / (max(best) * 1e-3) / 1e9 / HBM_PEAK_GBS})
+            plan.close()
+            del x
+            torch.cuda.empty_cache()
+    return rows
+
+
 def bench_batch(torch, Q, reps=10):
     """512 uneven transforms: the batched launches in one HIP graph, the same
-    launches enqueued directly, and one plan execute per transform."""
+    launches enqueued directly, and one plan execute per transform, with the
+    default configuration; then the configuration the batch autotuner picks
+    for the whole batch (qft_tune_batch), in the graph."""
     from paper_2606_18981_amd import inputs as I
     ns, cuts = I.batch_sizes(1004, count=512, lo=8, hi=20, aqft_frac=0.25, aqft_k=8)
-    plans, xs, cache = [], [], {}
-    for n, k in zip(ns.tolist(), cuts.tolist()):
-        if (n, k) not in cache:
-            cache[(n, k)] = Q.Plan(n, k, "unitary", "c64", "natural")
-        plans.append(cache[(n, k)])
+    xs = []
+    for i, n in enumerate(ns.tolist()):
         t = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
-        Q.fill_random(t, "uniform", seed=1004 + len(xs))
+        Q.fill_random(t, "uniform", seed=1004 + i)
         xs.append(t)
-    total_bytes = sum(p.info.hbm_bytes for p in plans)
     elems = sum(1 << n for n in ns.tolist())
     s = torch.cuda.Event(enable_timing=True)
     e = torch.cuda.Event(enable_timing=True)
+
+    def make_plans(config):
+        cache, plans = {}, []
+        for n, k in zip(ns.tolist(), cuts.tolist()):
+            if (n, k) not in cache:
+                cache[(n, k)] = Q.Plan(n, k, "unitary", "c64", "natural", config=config)
+            plans.append(cache[(n, k)])
+        return cache, plans
+
+    def timed(run):
+        run()
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(reps):
+            run()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / reps
+
+    cache, plans = make_plans(None)
+    batch = Q.Batch(plans, xs)  # arguments checked and marshalled once
+    total_bytes = sum(p.info.hbm_bytes for p in plans)
     res = {"transforms": 512, "total_amplitudes": int(elems),
            "algorithmic_hbm_bytes": int(total_bytes)}
     for mode in ("graph", "eager", "per_launch"):
@@ -318,18 +379,26 @@ def bench_batch(torch, Q, reps=10):
                 for p, t in zip(plans, xs):
                     p.execute(t)
             else:
-                Q.execute_batch(plans, xs, graph=(mode == "graph"))
-        run()
-        torch.cuda.synchronize()
-        s.record()
-        for _ in range(reps):
-            run()
-        e.record()
-        torch.cuda.synchronize()
-        ms = s.elapsed_time(e) / reps
+                batch.execute(graph=(mode == "graph"))
+        ms = timed(run)
         res[mode] = {"ms": ms, "transforms_per_s": 512 / (ms * 1e-3),
                      "hbm_gbs": total_bytes / (ms * 1e-3) / 1e9}
     res["speedup_graph_vs_per_launch"] = res["per_launch"]["ms"] / res["graph"]["ms"]
+    for p in cache.values():
+        p.close()
+    # the batch autotuner: one configuration for the whole batch
+    t0 = time.perf_counter()
+    best, tune_ms = Q.tune_batch(ns.tolist(), cuts.tolist(), xs, reps=3)
+    tune_s = time.perf_counter() - t0
+    cache, plans = make_plans(best)
+    tuned_bytes = sum(p.info.hbm_bytes for p in plans)
+    batch = Q.Batch(plans, xs)
+    ms = timed(lambda: batch.execute(graph=True))
+    res["tuned"] = {"config": best, "tuner_seconds": tune_s, "tuner_ms": tune_ms,
+                    "graph": {"ms": ms, "transforms_per_s": 512 / (ms * 1e-3),
+                              "algorithmic_hbm_bytes": int(tuned_bytes),
+                              "hbm_gbs": tuned_bytes / (ms * 1e-3) / 1e9}}
+    res["speedup_tuned_vs_default_graph"] = res["graph"]["ms"] / ms
     for p in cache.values():
         p.close()
     del xs
@@ -337,32 +406,47 @@ def bench_batch(torch, Q, reps=10):
     return res
 
 
-def bench_serve(torch, Q, seconds, rate=2000.0):
-    """Poisson request stream: continuous batching vs one transform at a time."""
+def bench_serve(torch, Q, seconds, rate=2000.0, sweep_rates=(4000.0, 6000.0, 8000.0, 12000.0),
+                sweep_seconds=4.0):
+    """Poisson request streams: continuous batching (64 slots over 4 streams)
+    against one transform at a time (1 slot, 1 stream), on the config's trace
+    (2000 requests/s for `seconds`) and on shorter traces at higher rates,
+    to find where one at a time saturates."""
     from paper_2606_18981_amd import inputs as I
     from paper_2606_18981_amd import serve as S
-    trace = I.served_trace(1005, rate=rate, duration=seconds, n_lo=10, n_hi=26)
-    reqs = S.requests_from_trace(trace)
-    out = {"requests": len(reqs), "rate_per_s": rate, "seconds": seconds,
-           "budget_bytes": 200 << 30}
-    for name, slots, streams in (("continuous", 64, 4), ("one_at_a_time", 1, 1)):
-        srv = S.Server(200 << 30, slots, streams)
-        srv.prepare(reqs)
-        res, st = srv.run(reqs)
-        summ = S.latency_summary(res)
-        summ.update({"completed": st["completed"], "failed": st["failed"],
-                     "peak_inflight": st["peak_inflight"],
-                     "peak_reserved_gb": st["peak_reserved_bytes"] / 1e9,
-                     "wall_s": st["wall_seconds"],
-                     "hbm_gbs": st["hbm_bytes"] / st["wall_seconds"] / 1e9})
-        out[name] = summ
-        srv.close()
-        torch.cuda.synchronize()
-        torch.cuda.empty_cache()
+    budget = 200 << 30
+
+    def run_modes(rate, seconds):
+        trace = I.served_trace(1005, rate=rate, duration=seconds, n_lo=10, n_hi=26)
+        reqs = S.requests_from_trace(trace)
+        out = {"requests": len(reqs), "rate_per_s": rate, "seconds": seconds}
+        for name, slots, streams in (("continuous", 64, 4), ("one_at_a_time", 1, 1)):
+            srv = S.Server(budget, slots, streams)
+            srv.prepare(reqs)
+            res, st = srv.run(reqs)
+            summ = S.latency_summary(res)
+            summ.update({"completed": st["completed"], "failed": st["failed"],
+                         "peak_inflight": st["peak_inflight"],
+                         "peak_reserved_gb": st["peak_reserved_bytes"] / 1e9,
+                         "plan_tables_gb": st["plan_bytes"] / 1e9,
+                         "wall_s": st["wall_seconds"],
+                         "requests_per_s": st["completed"] / st["wall_seconds"],
+                         "hbm_gbs": st["hbm_bytes"] / st["wall_seconds"] / 1e9})
+            out[name] = summ
+            srv.close()
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            print(f"[bench] serve {rate:.0f}/s {seconds:g} s {name}: p50 "
+                  f"{summ.get('p50_ms', 0):.3f} ms p99 {summ.get('p99_ms', 0):.3f} ms",
+                  file=sys.stderr, flush=True)
+        return out
+
+    out = {"budget_bytes": budget, "trace": run_modes(rate, seconds)}
+    out["rate_sweep"] = [run_modes(r, sweep_seconds) for r in sweep_rates]
     return out
 
 
-EXTRA_LEGS = ("configs", "aqft", "budget", "c128", "gates", "circuit", "batch", "serve")
+EXTRA_LEGS = ("configs", "sizes", "aqft", "budget", "c128", "gates", "circuit", "batch", "serve")
 
 
 def main():
@@ -373,7 +457,7 @@ def main():
     ap.add_argument("--n", type=int, default=28)
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
     ap.add_argument("--cutoff", type=int, default=-1)
-    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline measurement")
@@ -535,6 +619,9 @@ def main():
     if "configs" in legs:
         print("[bench] n = 10 and n = 24", file=sys.stderr, flush=True)
         out["small_configs"] = bench_configs(torch, Q)
+    if "sizes" in legs:
+        print("[bench] sizes n = 24..30", file=sys.stderr, flush=True)
+        out["sizes"] = bench_sizes(torch, Q)
     if "aqft" in legs:
         print("[bench] aqft sweep", file=sys.stderr, flush=True)
         out["aqft_n28_c64"] = bench_aqft(torch, Q, 28, "c64", [-1, 6, 10, 14, 18], 10)
@@ -557,8 +644,8 @@ def main():
     if "serve" in legs:
         print("[bench] serve", file=sys.stderr, flush=True)
         out["serve"] = bench_serve(torch, Q, args.serve_seconds)
-        out["p50_ms"] = out["serve"]["continuous"].get("p50_ms")
-        out["p99_ms"] = out["serve"]["continuous"].get("p99_ms")
+        out["p50_ms"] = out["serve"]["trace"]["continuous"].get("p50_ms")
+        out["p99_ms"] = out["serve"]["trace"]["continuous"].get("p99_ms")
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline and accuracy of the timed plan", file=sys.stderr, flush=True)
         out["cpu_baseline"], out["accuracy"] = cpu_baseline_and_accuracy(

@@ -63,6 +63,12 @@ typedef void *qft_stream_t; /* hipStream_t */
 #define QFT_PLAN_NO_WORKSPACE 0x8 /* the plan allocates no workspace: run it
                                   with qft_execute_ws (qft_execute then fails
                                   with QFT_ERR_POINTER if one is needed)      */
+#define QFT_PLAN_TUNED 0x20    /* build the plan with the tuning table's
+                                  entry for its shape when there is one
+                                  (qft_tune.h); without this flag, and
+                                  always with an explicit configuration, the
+                                  table is not consulted, so a plan does not
+                                  depend on what was tuned before          */
 #define QFT_INVERSE 0x10       /* the inverse transform: the same circuit with
                                   every controlled phase conjugated, R_m ->
                                   R_m^*, i.e. y_k = s * sum_j x_j
@@ -243,18 +249,22 @@ int qft_plan_pass_times(qft_plan_t *plan, double *ms, int max, long long *execs)
 
 /* Transform count arrays, dev_ptrs[i] with plans[i], with one graph launch.
  * The tiles of all transforms are grouped by pass level, then by register
- * radix and workgroup size; each group is one kernel launch over the tiles
- * of many transforms (one tile per workgroup), and the launches run level by
- * level, so a transform's pass p+1 starts after every pass-p tile is done
- * and no workgroup waits on another.  The first call for a given
+ * radix, workgroup size and kernel shape; each group is one kernel launch
+ * over the tiles of many transforms (one tile per workgroup), and the
+ * launches run level by level, so a transform's pass p+1 starts after every
+ * pass-p tile is done and no workgroup waits on another.  A transform's
+ * passes take the last levels (with the largest plan having maxP passes, a
+ * plan of P passes runs pass p at level maxP - P + p): one-pass transforms
+ * run beside the last passes of the large ones.  The first call for a given
  * (plans, dev_ptrs) set builds the work list (and allocates one workspace per
  * natural-order multi-pass transform) and captures the launches into a HIP
  * graph; later calls replay the graph.  Plans must be fused-schedule plans
- * of one element type.  Destroying a plan drops the cached sets that use
- * it.  At most 64 sets stay cached: a new set beyond that synchronises the
- * device once and releases the oldest.  The graph's launches of one pass
- * level are spread over the caller's stream and three streams of the set,
- * joined before the next level.                                            */
+ * of one element type.  Results equal those of each plan's own qft_execute
+ * bit for bit.  Destroying a plan drops the cached sets that use it.  At
+ * most 64 sets stay cached: a new set beyond that synchronises the device
+ * once and releases the oldest.  The graph's launches of one pass level are
+ * spread, largest first, over the caller's stream and three streams of the
+ * set, joined before the next level.                                        */
 int qft_execute_batch(qft_plan_t *const *plans, void *const *dev_ptrs,
                       int count, qft_stream_t stream);
 

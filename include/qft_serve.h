@@ -3,8 +3,10 @@
  *
  * A server replays a stream of transform requests in real time.  Requests
  * are released at their arrival times into a FIFO queue and admitted, in
- * order, as soon as an in-flight slot is free and the HBM budget (state
- * buffer plus workspace of the request) fits; admitted requests are enqueued
+ * order, as soon as an in-flight slot is free and the HBM budget fits: the
+ * budget is charged once with the device memory of the server's resident
+ * plans (their twiddle tables) and then with the state buffer plus
+ * workspace of every request in flight.  Admitted requests are enqueued
  * on a pool of HIP streams, so that requests arriving while others run are
  * overlapped on the device.  Each request generates its input on the device
  * (Philox-4x32-10, see qft_fill_random), runs its cached plan and records a
@@ -57,6 +59,9 @@ typedef struct qft_server_stats {
   int peak_inflight;
   double wall_seconds;
   double hbm_bytes;  /* algorithmic HBM bytes of all transforms + inputs     */
+  size_t plan_bytes; /* device memory of the resident plans, charged against
+                        the budget for the whole run (peak_reserved_bytes
+                        includes it)                                         */
 } qft_server_stats_t;
 
 /* hbm_budget_bytes: admission budget; max_inflight: in-flight slots;
@@ -69,7 +74,8 @@ void qft_server_destroy(qft_server_t *server);
 int qft_server_prepare(qft_server_t *server, const qft_request_t *reqs, int count);
 
 /* Replay `count` requests (sorted by arrival) in real time and block until
- * all have completed.  results[i] describes reqs[i].                        */
+ * all have completed.  results[i] describes reqs[i].  Fails with
+ * QFT_ERR_NOMEM when the resident plans alone exceed the budget.            */
 int qft_server_run(qft_server_t *server, const qft_request_t *reqs, int count,
                    qft_request_result_t *results, qft_server_stats_t *stats);
 

@@ -4,10 +4,13 @@
  * The tuner times candidate kernel configurations (qft_config_t: tile size,
  * register radix = number of qubits fused per register group, spectator
  * widths) on the device and keeps the fastest per plan shape in an
- * in-memory table.  qft_plan() with no explicit configuration uses the table
- * entry for its shape when there is one.  The table can be saved to and
- * loaded from a text file of JSON lines; lines that do not parse, or that
- * name another GPU architecture, are skipped.
+ * in-memory table.  A plan uses the table entry for its shape only when it
+ * is built with the QFT_PLAN_TUNED layout flag and no explicit
+ * configuration; otherwise plans do not depend on the table.  The table can
+ * be saved to and loaded from a text file of JSON lines; lines that do not
+ * parse, or that name another GPU architecture, are skipped.  The radix
+ * stops at 32 (five fused qubits): a 64-element register block would hold
+ * 128 complex64 data registers per lane.
  */
 #ifndef QFT_MI355X_TUNE_H
 #define QFT_MI355X_TUNE_H
@@ -30,9 +33,11 @@ int qft_tune(int n, int cutoff, int norm, int layout, void *data, int reps,
              qft_config_t *best, double *best_ms);
 
 /* Tune one configuration shared by all transforms of a batch: for each
- * candidate, plans (n[i], cutoff[i], norm, layout) are built with it and the
- * batch on data[i] is timed through qft_execute_batch_ex (eager launch).
- * The winner is stored in the table for every shape of the batch.          */
+ * candidate of the batch grid (tile_log2 8..13, radix_log2 3..5, spectator
+ * widths 2..4), plans (n[i], cutoff[i], norm, layout) are built with it and
+ * the batch on data[i] is timed through qft_execute_batch (graph launch,
+ * after one call that captures it).  The winner and its time are returned;
+ * the per-shape table is not changed.                                       */
 int qft_tune_batch(const int *n, const int *cutoff, int count, int norm, int layout,
                    void *const *data, int reps, qft_config_t *best, double *best_ms);
 

@@ -171,7 +171,10 @@ static qft_plan_t *make_plan(int n, int cutoff, int norm, int layout, const qft_
   }
   std::string err;
   qft_config_t tuned;
-  if (!cfg && !(layout & QFT_SCHEDULE_GATES) && tune_table_lookup(n, cutoff, layout, &tuned))
+  // the tuning table only when asked for (QFT_PLAN_TUNED), so that a plan
+  // does not depend on what the process tuned before
+  if (!cfg && (layout & QFT_PLAN_TUNED) && !(layout & QFT_SCHEDULE_GATES) &&
+      tune_table_lookup(n, cutoff, layout, &tuned))
     cfg = &tuned;
   int rc = build_host_plan(n, cutoff, norm, layout, cfg, p->hp, err);
   if (rc != QFT_OK) {

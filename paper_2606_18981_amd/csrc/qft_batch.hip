@@ -1,7 +1,11 @@
 // Batched uneven-size execution: the tiles of all transforms, launched pass
-// level by pass level (one launch per level, radix and workgroup size),
-// captured once per (plans, pointers) set into a HIP graph and replayed.
-// See include/qft.h.
+// level by pass level (one launch per level, radix, workgroup size and
+// kernel shape), captured once per (plans, pointers) set into a HIP graph
+// and replayed.  Transforms of one pass depend on nothing: their launches go
+// to a stream of their own, forked at the start and joined at the end, and
+// run beside the others.  The passes of multi-pass transforms are aligned to
+// the last levels (a transform of P passes runs its pass p at level
+// maxP - P + p).  See include/qft.h.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -20,9 +24,16 @@ namespace qft {
 namespace {
 
 // The groups of one pass level touch different transforms, so they may run
-// at the same time: up to this many streams (the caller's and the side
-// streams of the batch entry), joined again before the next level.
+// at the same time: on up to kLevelStreams streams (the caller's and side
+// streams of the batch entry), joined again before the next level; one more
+// side stream runs the one-pass transforms.  (Four streams: the hardware
+// queues a process gets by default.)
 constexpr int kForkStreams = 4;
+constexpr int kLevelStreams = kForkStreams - 1;
+// launch cost model for dealing a level's groups to streams: bytes moved at
+// this rate, but at least this latency per launch
+constexpr double kGroupBytesPerUs = 4.0e6;
+constexpr double kLaunchFloorUs = 10.0;
 
 // Cached (plans, pointers) sets, each with its graph, workspaces, streams
 // and events; beyond this many the oldest is released.
@@ -35,7 +46,8 @@ struct BatchEntry {
   std::vector<BatchGroup> groups;    // launch order: pass level by pass level
   void *d_mem = nullptr;             // segments, descriptors, io
   std::vector<void *> workspaces;    // one per natural-order multi-pass job
-  std::vector<int> levels;           // pass level of each group
+  std::vector<int> levels;           // pass level of each group; -1: one-pass
+  std::vector<double> cost;          // modelled time of each group (us)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int device = 0;
@@ -98,12 +110,17 @@ int build_entry(BatchEntry *e) {
     uint32_t items = 0;
   };
   std::vector<GroupBuild> gb;
-  for (int level = 0; level < maxP; ++level) {
+  // level -1: the one-pass transforms; then the pass levels of the others
+  for (int level = -1; level < maxP; ++level) {
     std::map<std::tuple<int, int, int>, size_t> index;  // (r, threads, shape) -> group
     for (int j = 0; j < njobs; ++j) {
       qft_plan_t *p = e->plans[j];
-      if (level >= (int)p->launches.size()) continue;
-      const PassLaunch &L = p->launches[level];
+      const int P = (int)p->launches.size();
+      int pass;
+      if (level < 0) pass = P == 1 ? 0 : -1;
+      else pass = P == 1 ? -1 : level - (maxP - P);  // right-aligned: the last pass at the last level
+      if (pass < 0) continue;
+      const PassLaunch &L = p->launches[pass];
       const int shape = fused_pass_shape(L);
       const auto key = std::make_tuple((int)L.d.r, L.threads, shape);
       auto it = index.find(key);
@@ -170,6 +187,9 @@ int build_entry(BatchEntry *e) {
     g.shape = gb[i].shape;
     e->groups.push_back(g);
     e->levels.push_back(gb[i].level);
+    const double bytes = 2.0 * (double)g.items * (double)g.threads * (double)(1 << g.r) *
+                         (e->c128 ? 16.0 : 8.0);
+    e->cost.push_back(std::max(kLaunchFloorUs, bytes / kGroupBytesPerUs));
   }
   for (hipStream_t &st : e->side) {
     he = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -194,40 +214,68 @@ int build_entry(BatchEntry *e) {
 }
 
 // Level by level: a level with one group runs on `s`; the groups of a wider
-// level are dealt round-robin, largest first, over `s` and the side streams,
-// which wait for `s` before and are waited for by `s` after.  Under graph
-// capture the same calls record the fork and join as graph edges.
+// level are dealt, largest modelled cost first, each to the stream of the
+// level with the least cost so far (`s` and the first side streams), which
+// wait for `s` before and are waited for by `s` after.  The one-pass groups
+// (level -1) run on the last side stream, forked from `s` at the start and
+// joined at the end; they are enqueued after the first level's launches (a
+// graph dispatches its kernels in the order they were captured, and the
+// large first passes should start first).  Under graph capture the same
+// calls record the forks and joins as graph edges.
 hipError_t launch_entry(BatchEntry *e, hipStream_t s) {
   const size_t ng = e->groups.size();
-  size_t i = 0;
+  hipError_t he;
+  hipStream_t free_st = e->side[kForkStreams - 2];
+  size_t nfree = 0;
+  while (nfree < ng && e->levels[nfree] < 0) ++nfree;
+  bool free_done = nfree == 0;
+  if (!free_done) {
+    he = hipEventRecord(e->fork_ev, s);
+    if (he != hipSuccess) return he;
+    he = hipStreamWaitEvent(free_st, e->fork_ev, 0);
+    if (he != hipSuccess) return he;
+  }
+  auto launch_free = [&]() -> hipError_t {
+    for (size_t k = 0; k < nfree; ++k) {
+      hipError_t h = launch_batch_group(e->c128, e->groups[k], free_st);
+      if (h != hipSuccess) return h;
+    }
+    free_done = true;
+    return hipSuccess;
+  };
+  size_t i = nfree;
   while (i < ng) {
     size_t j = i;
     while (j < ng && e->levels[j] == e->levels[i]) ++j;
     if (j - i == 1) {
-      hipError_t he = launch_batch_group(e->c128, e->groups[i], s);
+      he = launch_batch_group(e->c128, e->groups[i], s);
       if (he != hipSuccess) return he;
+      if (!free_done && (he = launch_free()) != hipSuccess) return he;
       i = j;
       continue;
     }
     std::vector<size_t> order;
     for (size_t k = i; k < j; ++k) order.push_back(k);
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
-      return (uint64_t)e->groups[a].items * e->groups[a].threads >
-             (uint64_t)e->groups[b].items * e->groups[b].threads;
-    });
-    const int used = (int)std::min<size_t>(order.size(), kForkStreams);
-    hipError_t he = hipEventRecord(e->fork_ev, s);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return e->cost[a] > e->cost[b]; });
+    const int used = (int)std::min<size_t>(order.size(), kLevelStreams);
+    he = hipEventRecord(e->fork_ev, s);
     if (he != hipSuccess) return he;
     for (int k = 1; k < used; ++k) {
       he = hipStreamWaitEvent(e->side[k - 1], e->fork_ev, 0);
       if (he != hipSuccess) return he;
     }
+    double load[kLevelStreams] = {};
     for (size_t k = 0; k < order.size(); ++k) {
-      const int lane = (int)(k % (size_t)used);
+      int lane = 0;
+      for (int q = 1; q < used; ++q)
+        if (load[q] < load[lane]) lane = q;
+      load[lane] += e->cost[order[k]];
       hipStream_t st = lane == 0 ? s : e->side[lane - 1];
       he = launch_batch_group(e->c128, e->groups[order[k]], st);
       if (he != hipSuccess) return he;
     }
+    if (!free_done && (he = launch_free()) != hipSuccess) return he;
     for (int k = 1; k < used; ++k) {
       he = hipEventRecord(e->join_ev[k - 1], e->side[k - 1]);
       if (he != hipSuccess) return he;
@@ -235,6 +283,13 @@ hipError_t launch_entry(BatchEntry *e, hipStream_t s) {
       if (he != hipSuccess) return he;
     }
     i = j;
+  }
+  if (nfree > 0) {
+    if (!free_done && (he = launch_free()) != hipSuccess) return he;
+    he = hipEventRecord(e->join_ev[kForkStreams - 2], free_st);
+    if (he != hipSuccess) return he;
+    he = hipStreamWaitEvent(s, e->join_ev[kForkStreams - 2], 0);
+    if (he != hipSuccess) return he;
   }
   return hipSuccess;
 }

@@ -675,7 +675,7 @@ int build_host_plan(int n, int cutoff, int norm, int layout, const qft_config_t 
     err = "norm must be QFT_NORM_UNITARY, QFT_NORM_NONE or QFT_NORM_INV_N";
     return QFT_ERR_INVALID;
   }
-  if (layout & ~0x1F) {
+  if (layout & ~(0x1F | QFT_PLAN_TUNED)) {
     err = "unknown layout flag bits";
     return QFT_ERR_INVALID;
   }

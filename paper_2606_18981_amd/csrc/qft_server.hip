@@ -250,6 +250,11 @@ int qft_server_run(qft_server_t *server, const qft_request_t *reqs, int count,
       return set_error(QFT_ERR_INVALID, "requests must be sorted by arrival");
   int rc = qft_server_prepare(server, reqs, count);
   if (rc != QFT_OK) return rc;
+  // the resident plans' device memory (tables) is charged once, up front
+  size_t plan_bytes = 0;
+  for (const auto &kv : server->plans) plan_bytes += qft_plan_device_bytes(kv.second);
+  if (plan_bytes >= server->budget)
+    return set_error(QFT_ERR_NOMEM, "the resident plans alone exceed the HBM budget");
   std::vector<SchedReq> sr(count);
   for (int i = 0; i < count; ++i) {
     const qft_plan_t *p = server->plans[server->key(reqs[i])];
@@ -266,8 +271,10 @@ int qft_server_run(qft_server_t *server, const qft_request_t *reqs, int count,
   qft_server_stats_t st;
   res.assign(count, qft_request_result_t{});
   dev.t0 = std::chrono::steady_clock::now();
-  run_schedule(dev, sr, server->budget, server->max_inflight, res, st);
+  run_schedule(dev, sr, server->budget - plan_bytes, server->max_inflight, res, st);
   st.hbm_bytes = dev.hbm_bytes;
+  st.plan_bytes = plan_bytes;
+  st.peak_reserved_bytes += plan_bytes;
   for (hipEvent_t ev : dev.free_events) hipEventDestroy(ev);
   for (int i = 0; i < count; ++i) results[i] = res[i];
   if (stats) *stats = st;

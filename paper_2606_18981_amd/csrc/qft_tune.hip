@@ -45,11 +45,15 @@ std::string arch_name() {
   return c == std::string::npos ? a : a.substr(0, c);
 }
 
-std::vector<qft_config_t> candidate_grid() {
+// Candidates: tile 2^t elements, register radix 2^r (the qubits fused per
+// register group, the paper's fusion width), spectator widths c and b.
+// Radix 64 (six fused qubits) would hold 128 complex64 data registers per
+// lane, more than two waves per SIMD allow; the kernels stop at radix 32.
+std::vector<qft_config_t> candidate_grid(int tmin = 8, int tmax = 14, int cmax = 5) {
   std::vector<qft_config_t> v;
-  for (int t = 8; t <= 14; ++t)
+  for (int t = tmin; t <= tmax; ++t)
     for (int r = 3; r <= 5; ++r)
-      for (int c = 2; c <= 5; ++c)
+      for (int c = 2; c <= cmax; ++c)
         for (int b = 2; b <= 4; ++b) {
           qft_config_t q;
           memset(&q, 0, sizeof(q));
@@ -230,7 +234,9 @@ int qft_tune_batch(const int *n, const int *cutoff, int count, int norm, int lay
   qft_config_t bc{};
   bool found = false;
   int rc = QFT_OK;
-  for (const qft_config_t &c : candidate_grid()) {
+  // the batch grid: tiles of 2^8..2^13 elements (the batch's transforms have
+  // 2^8..2^20), radix 8..32, spectator widths 2..4
+  for (const qft_config_t &c : candidate_grid(8, 13, 4)) {
     // one plan per distinct shape, shared by the transforms of that shape
     std::map<std::pair<int, int>, qft_plan_t *> plans;
     std::vector<qft_plan_t *> pv(count, nullptr);
@@ -249,11 +255,12 @@ int qft_tune_batch(const int *n, const int *cutoff, int count, int norm, int lay
       pv[i] = it->second;
     }
     if (ok) {
-      int r1 = qft_execute_batch_ex(pv.data(), data, count, QFT_BATCH_EAGER, s);
+      // the first call builds the work list and captures the graph
+      int r1 = qft_execute_batch_ex(pv.data(), data, count, 0, s);
       if (r1 == QFT_OK) {
         hipEventRecord(a, s);
         for (int i = 0; i < reps && r1 == QFT_OK; ++i)
-          r1 = qft_execute_batch_ex(pv.data(), data, count, QFT_BATCH_EAGER, s);
+          r1 = qft_execute_batch_ex(pv.data(), data, count, 0, s);
         hipEventRecord(b, s);
         he = hipEventSynchronize(b);
         if (he != hipSuccess) {
@@ -278,10 +285,8 @@ int qft_tune_batch(const int *n, const int *cutoff, int count, int norm, int lay
   hipStreamDestroy(s);
   if (rc != QFT_OK) return rc;
   if (!found) return set_error(QFT_ERR_UNSUPPORTED, "no configuration ran the batch");
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    for (int i = 0; i < count; ++i) g_table[make_key(n[i], cutoff[i], layout)] = Entry{bc, bms};
-  }
+  // (the per-shape table is left alone: the batch's winner is best for the
+  // batch as a whole, not for each shape alone)
   if (best) *best = bc;
   if (best_ms) *best_ms = bms;
   return QFT_OK;

@@ -25,6 +25,7 @@ QFT_SCHEDULE_FUSED = 0x0
 QFT_SCHEDULE_GATES = 0x4
 QFT_PLAN_NO_WORKSPACE = 0x8
 QFT_INVERSE = 0x10
+QFT_PLAN_TUNED = 0x20
 QFT_CUTOFF_EXACT = -1
 QFT_MAX_PASSES = 8
 QFT_RNG_GAUSSIAN = 0
@@ -236,12 +237,16 @@ class Plan:
 
     def __init__(self, n: int, cutoff: int = -1, norm="unitary", dtype="c64",
                  order="natural", schedule="fused", config=None, workspace: bool = True,
-                 inverse: bool = False):
+                 inverse: bool = False, tuned: bool = False):
+        """tuned=True (and no config): take the tuning table's entry for this
+        shape when there is one (QFT_PLAN_TUNED)."""
         self.n = n
         self.cutoff = cutoff
         self.layout = layout_flags(dtype, order, schedule, inverse)
         if not workspace:
             self.layout |= QFT_PLAN_NO_WORKSPACE
+        if tuned:
+            self.layout |= QFT_PLAN_TUNED
         self.c128 = bool(self.layout & QFT_C128)
         c = _config(config)
         h = lib.qft_plan_config(n, cutoff, _norm(norm), self.layout,
@@ -339,6 +344,21 @@ def execute_batch(plans: Sequence[Plan], tensors, stream=None, graph: bool = Tru
     ph, tp, cnt = _batch_arrays(plans, tensors)
     flags = 0 if graph else QFT_BATCH_EAGER
     _check(lib.qft_execute_batch_ex(ph, tp, cnt, flags, _stream_handle(stream)))
+
+
+class Batch:
+    """A fixed set of (plan, tensor) pairs run as one batch: the arguments
+    are checked and marshalled once, so that each execute() is one call into
+    the library (which replays the set's captured graph)."""
+
+    def __init__(self, plans: Sequence[Plan], tensors):
+        self._ph, self._tp, self._cnt = _batch_arrays(plans, tensors)
+        self._keep = (list(plans), list(tensors))  # keep them alive
+
+    def execute(self, stream=None, graph: bool = True):
+        flags = 0 if graph else QFT_BATCH_EAGER
+        _check(lib.qft_execute_batch_ex(self._ph, self._tp, self._cnt, flags,
+                                        _stream_handle(stream)))
 
 
 def fill_random(x, dist="gaussian", seed: int = 0, stream_id: int = 0, stream=None):

@@ -31,7 +31,8 @@ class RequestResult(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_longlong), ("failed", ctypes.c_longlong),
                 ("peak_reserved_bytes", ctypes.c_size_t), ("peak_inflight", ctypes.c_int),
-                ("wall_seconds", ctypes.c_double), ("hbm_bytes", ctypes.c_double)]
+                ("wall_seconds", ctypes.c_double), ("hbm_bytes", ctypes.c_double),
+                ("plan_bytes", ctypes.c_size_t)]
 
 
 _P = ctypes.c_void_p

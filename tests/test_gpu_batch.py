@@ -1,4 +1,5 @@
-"""GPU tests of the batched launch (uneven sizes, level-by-level group launches in one graph).
+"""GPU tests of the batched launch (uneven sizes, level-by-level group launches in one graph,
+one-pass transforms on a stream of their own).
 
 Each transform in a batch must give exactly the result of running it alone
 (same kernels, same arithmetic) and agree with the FP64 oracle.  Graph
@@ -163,3 +164,25 @@ def test_cache_bound_evicts_oldest(env):
     torch.cuda.synchronize()
     assert np.array_equal(t0.cpu().numpy(), ref)
     plan.close()
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_handle_replays(env, graph):
+    # the reusable Batch handle (arguments marshalled once) gives the lone
+    # results bit for bit on every replay, one-pass and multi-pass transforms
+    # mixed (the one-pass ones run on their own stream)
+    torch, Q = env
+    ns, cuts = I.batch_sizes(1004, count=64, lo=8, hi=18, aqft_frac=0.25, aqft_k=8)
+    plans, xs, hosts, cache = make_batch(torch, Q, ns, cuts, "c64", 8100)
+    ref = alone(torch, Q, plans, hosts, "c64")
+    b = Q.Batch(plans, xs)
+    for rep in range(3):
+        for t, x in zip(xs, hosts):
+            t.copy_(torch.from_numpy(x.astype(np.complex64)))
+        print(f"[gpu] batch handle graph={graph} replay {rep}", flush=True)
+        b.execute(graph=graph)
+        torch.cuda.synchronize()
+        for i, (t, r) in enumerate(zip(xs, ref)):
+            assert np.array_equal(t.cpu().numpy(), r), f"transform {i} (n={ns[i]}) replay {rep}"
+    for p in cache.values():
+        p.close()

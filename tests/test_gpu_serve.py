@@ -81,4 +81,14 @@ def test_budget_admission_on_gpu(env):
     assert st["completed"] == 12
     assert st["peak_inflight"] <= 2
     assert st["peak_reserved_bytes"] <= 20 << 20
+    # the resident plan's tables are charged against the budget
+    plan = Q.Plan(20, -1, "unitary", "c64", "bitrev", workspace=False)
+    assert st["plan_bytes"] == plan.device_bytes > 0
+    assert st["peak_reserved_bytes"] == st["plan_bytes"] + int(res["bytes"][:2].sum())
+    plan.close()
     srv.close()
+    # a budget the plans alone exceed is refused
+    tiny = S.Server(budget_bytes=st["plan_bytes"], max_inflight=4, num_streams=2)
+    with pytest.raises(Q.QftError):
+        tiny.run(reqs)
+    tiny.close()

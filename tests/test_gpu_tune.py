@@ -1,5 +1,6 @@
 """GPU tests of the autotuner: the tuned configuration is recorded, used by
-later plans, and gives oracle-correct results."""
+later plans that ask for it (QFT_PLAN_TUNED) and by no other, and gives
+oracle-correct results; batch tuning leaves the per-shape table alone."""
 
 import numpy as np
 import pytest
@@ -35,7 +36,11 @@ def test_tune_shape_and_reuse(env, tmp_path):
     print(f"[gpu] tuned n={n}: {best} {ms:.4f} ms", flush=True)
     assert ms > 0
     assert Q.tune_lookup(n, -1, "c64") == best
-    plan = Q.Plan(n, -1, "unitary", "c64", "natural")
+    plain = Q.Plan(n, -1, "unitary", "c64", "natural")
+    default = Q._cfg_dict(Q.describe(n, -1, "unitary", "c64", "natural").config)
+    assert Q._cfg_dict(plain.info.config) == default  # the table is not consulted
+    plain.close()
+    plan = Q.Plan(n, -1, "unitary", "c64", "natural", tuned=True)
     assert Q._cfg_dict(plan.info.config) == best
     x = I.gaussian(n, 4)
     t = torch.from_numpy(x.astype(np.complex64)).cuda()
@@ -59,6 +64,18 @@ def test_tune_batch(env):
     best, ms = Q.tune_batch(ns.tolist(), cuts.tolist(), xs, reps=1)
     print(f"[gpu] tuned batch: {best} {ms:.4f} ms", flush=True)
     assert ms > 0
+    # the per-shape table is not written by batch tuning
     for n, k in zip(ns.tolist(), cuts.tolist()):
-        assert Q.tune_lookup(int(n), int(k), "c64") == best
+        assert Q.tune_lookup(int(n), int(k), "c64") is None
+    # the winner, given explicitly, runs the batch with oracle-correct results
+    plans = [Q.Plan(int(n), int(k), "unitary", "c64", "natural", config=best)
+             for n, k in zip(ns.tolist(), cuts.tolist())]
+    hosts = [I.uniform_pm1(int(n), 700 + i) for i, n in enumerate(ns.tolist())]
+    ts = [torch.from_numpy(h.astype(np.complex64)).cuda() for h in hosts]
+    Q.execute_batch(plans, ts)
+    torch.cuda.synchronize()
+    for h, t, k in zip(hosts, ts, cuts.tolist()):
+        assert within(t.cpu().numpy(), O.qft_fused_targets(h, None if k < 0 else int(k)), 1e-5)
+    for p in plans:
+        p.close()
     Q.tune_clear()

@@ -52,7 +52,7 @@ def test_descriptor_layout_matches():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(n=0), dict(n=32), dict(n=-3), dict(norm=7), dict(layout=0x20), dict(layout=0x40),
+    dict(n=0), dict(n=32), dict(n=-3), dict(norm=7), dict(layout=0x80), dict(layout=0x40),
 ])
 def test_invalid_arguments(bad):
     args = dict(n=10, cutoff=-1, norm=0, layout=0)

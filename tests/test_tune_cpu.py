@@ -51,3 +51,19 @@ def test_insert_rejects_invalid_config():
 def test_load_missing_file():
     with pytest.raises(Q.QftError):
         Q.tune_load("/nonexistent/wisdom.jsonl")
+
+
+def test_tune_table_keeps_pass_tiles():
+    # per-pass tile sizes survive a save / load round trip
+    Q.tune_clear()
+    cfg = dict(tile_log2=13, radix_log2=5, spec_log2=3, rev_spec_log2=3,
+               pass_bits=[9, 10, 9], pass_tile_log2=[14, 14, 13])
+    Q.tune_insert(28, -1, "c64", "natural", cfg, 2.4)
+    import tempfile, os
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "wisdom.jsonl")
+        Q.tune_save(path)
+        Q.tune_clear()
+        assert Q.tune_load(path) == 1
+    assert Q.tune_lookup(28, -1, "c64") == cfg
+    Q.tune_clear()
