@@ -603,7 +603,7 @@ __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, con
   // (four-wave form: keep the exchange's LDS addresses from being computed
   // early, where they would be live across the network and spill)
   if constexpr (W4) __builtin_amdgcn_sched_barrier(0);
-  if constexpr (sizeof(Real) == 4) {
+  if constexpr (sizeof(Real) == 4 || W4) {
     exchange_split<Real, RB, W4>(v, lds, d.grp[0], d.grp[1], tid, TR);  // half-tile LDS
   } else {
     exchange<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR, true);
@@ -766,7 +766,7 @@ __device__ __forceinline__ void pass3_tile(const PassDesc &d, uint32_t tile, con
     for (int q = 0; q < RB; ++q) gf[q] = gt[(uint32_t)q * blockDim.x + tid];
   }
   if constexpr (W4) __builtin_amdgcn_sched_barrier(0);  // as in pass2_tile
-  if constexpr (sizeof(Real) == 4) {
+  if constexpr (sizeof(Real) == 4 || W4) {
     exchange_split<Real, RB, W4>(v, lds, d.grp[0], d.grp[1], tid, TR);  // half-tile LDS
   } else {
     exchange<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR, true);
@@ -815,7 +815,8 @@ k_fused_pass3(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
 // instead of one, measured slower: 5.98 against 5.50 ms at n = 28, the
 // late table reads costing more than the second workgroup gains.)
 #define QFT_LEAN_BOUNDS(Real) \
-  __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+  __launch_bounds__(sizeof(Real) == 4 ? 512 : 256)                                            \
+      __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 4 : 2)))
 
 template <typename Real, int RB, int NSTL, bool EXT, bool NT>
 __global__ void QFT_LEAN_BOUNDS(Real)
@@ -843,9 +844,10 @@ k_fused_pass3w(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
                                         reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x);
 }
 
-// The lean form runs every complex64 compile-time pass of 512 threads.
-inline bool lean_form(const PassLaunch &L) { return L.threads == 512; }
-inline bool lean_group(const BatchGroup &g) { return g.threads == 512; }
+// The lean form runs every complex64 compile-time pass of 512 threads
+// (2^14-element tiles) and every complex128 one of 256 threads (2^13).
+inline bool lean_form(const PassLaunch &L, bool c128) { return L.threads == (c128 ? 256 : 512); }
+inline bool lean_group(const BatchGroup &g, bool c128) { return g.threads == (c128 ? 256 : 512); }
 
 int fused_pass_shape(const PassLaunch &L) { return pass_kernel_shape(L); }
 
@@ -862,8 +864,8 @@ static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, 
                                       {QFT_P3(false, true), QFT_P3(true, true)}};
 #undef QFT_P3
       fn = tab3[L.d.nt ? 1 : 0][L.d.ext_tw ? 1 : 0][L.d.lane_swap - 1];
-      if constexpr (sizeof(Real) == 4) {
-        if (lean_form(L)) {
+      {
+        if (lean_form(L, sizeof(Real) == 8)) {
 #define QFT_P3W(E, N) \
   {k_fused_pass3w<Real, 1, E, N>, k_fused_pass3w<Real, 2, E, N>, k_fused_pass3w<Real, 3, E, N>}
           static const K tab3w[2][2][3] = {{QFT_P3W(false, false), QFT_P3W(true, false)},
@@ -882,8 +884,8 @@ static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, 
                                      {QFT_P2(false, true), QFT_P2(true, true)}};
 #undef QFT_P2
       fn = tab[L.d.nt ? 1 : 0][L.d.ext_tw ? 1 : 0][L.d.grp[1].nst - 1];
-      if constexpr (sizeof(Real) == 4) {
-        if (lean_form(L)) {
+      {
+        if (lean_form(L, sizeof(Real) == 8)) {
 #define QFT_P2W(E, N)                                                                        \
   {k_fused_pass2w<Real, 5, 1, E, N>, k_fused_pass2w<Real, 5, 2, E, N>,                       \
    k_fused_pass2w<Real, 5, 3, E, N>, k_fused_pass2w<Real, 5, 4, E, N>,                       \
@@ -1050,8 +1052,8 @@ static hipError_t launch_group_t(const BatchGroup &g, hipStream_t s) {
                                 k_batch_group3<Real, 3, false>, k_batch_group3<Real, 1, true>,
                                 k_batch_group3<Real, 2, true>,  k_batch_group3<Real, 3, true>};
       fn = tab3[g.shape - 11];
-      if constexpr (sizeof(Real) == 4) {
-        if (lean_group(g)) {
+      {
+        if (lean_group(g, sizeof(Real) == 8)) {
           static const K tab3w[6] = {
               k_batch_group3w<Real, 1, false>, k_batch_group3w<Real, 2, false>,
               k_batch_group3w<Real, 3, false>, k_batch_group3w<Real, 1, true>,
@@ -1068,8 +1070,8 @@ static hipError_t launch_group_t(const BatchGroup &g, hipStream_t s) {
           k_batch_group2<Real, 2, true>,  k_batch_group2<Real, 3, true>,
           k_batch_group2<Real, 4, true>,  k_batch_group2<Real, 5, true>};
       fn = tab[g.shape - 1];
-      if constexpr (sizeof(Real) == 4) {
-        if (lean_group(g)) {
+      {
+        if (lean_group(g, sizeof(Real) == 8)) {
           static const K tabw[10] = {
               k_batch_group2w<Real, 1, false>, k_batch_group2w<Real, 2, false>,
               k_batch_group2w<Real, 3, false>, k_batch_group2w<Real, 4, false>,

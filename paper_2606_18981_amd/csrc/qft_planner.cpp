@@ -274,6 +274,15 @@ int plan_fused(HostPlan &p, std::string &err) {
   const int spec = std::min(c.spec_log2, T - 1);
   const int rspec = std::min(c.rev_spec_log2, T - 1);
 
+  // Passes with qubits below them take one more tile bit in three-pass
+  // plans of these sizes (see the tile rule below); the pass split and the
+  // three-or-four-pass choice account for it.
+  auto wide_sizes = [&](int P) {
+    const bool size_ok = p.c128 ? (n >= 26 && n <= 30) : (n >= 28 && n <= 30);
+    return size_ok && !p.bitrev && P == 3 && r_cfg == 5 &&
+           T + 1 <= r_cfg + max_thread_bits(r_cfg, p.c128) && T + 1 <= kMaxTile;
+  };
+
   // ---- pass partition --------------------------------------------------
   // widths[0] is the most significant pass; the last one holds qubit 0
   std::vector<int> widths;
@@ -323,7 +332,8 @@ int plan_fused(HostPlan &p, std::string &err) {
       const int rem = n - hmax;
       const int first = rem - std::max(std::min(amax, (rem + 1) / 2), rem - hmax);
       const int r0 = std::min(r_cfg, first);
-      const int Tw = (!p.c128 && T - first < 4) ? T + 1 : T;  // see the first-pass rule below
+      // see the first-pass and wide-tile rules below
+      const int Tw = ((!p.c128 && T - first < 4) || wide_sizes(3)) ? T + 1 : T;
       const int Tp = std::min(Tw, r0 + max_thread_bits(r0, p.c128));
       const int spec0 = std::max(0, std::min(Tp - first, n - first));
       if ((p.elem_bytes << spec0) < 128) P = 4;
@@ -403,8 +413,13 @@ int plan_fused(HostPlan &p, std::string &err) {
     // rows would be shorter than 128 bytes (n = 30 [10, 10, 10]: 10.89 ms
     // with every pass at 2^14, 11.62 with the last at 2^13, 13.40 before).
     // n = 26, 27 and 31 measured 1-3 % slower with the wider tiles.
-    const bool wide_high = !p.c128 && !p.bitrev && P == 3 && n >= 28 && n <= 30 && r_cfg == 5 &&
-                           T + 1 <= r_cfg + max_thread_bits(r_cfg, p.c128) && T + 1 <= kMaxTile;
+    // Complex128 likewise at 2^26..2^30 elements: 2^13-element tiles of 256
+    // threads in the lean form (220 VGPRs, two waves per SIMD, split
+    // exchange through 64 KiB of LDS: two workgroups per CU).  n = 28
+    // 5.51 -> 4.78 ms (first pass 2.12 -> 1.64 ms with 256-byte rows),
+    // n = 29 12.09 -> 9.66 ms, n = 30 23.6 ms in four passes -> 20.6 ms
+    // in three, n = 26 and 27 3-6 % faster.
+    const bool wide_high = wide_sizes(P);
     for (int i = 0; i < P; ++i) {
       PassGeom g;
       g.m = widths[i];
@@ -546,7 +561,8 @@ int plan_fused(HostPlan &p, std::string &err) {
     L.lds_bytes = d.ngroups > 1 ? (int)(((size_t)1 << Te) * es) : 0;
     // the complex64 two-group kernel exchanges real and imaginary parts in
     // turn through half the tile's LDS (three workgroups per CU at 2^13)
-    if (!p.c128 && (pass2_shape(L) || pass3_shape(L))) L.lds_bytes /= 2;
+    // and so does the lean complex128 form (2^13-element tiles, 256 threads)
+    if ((!p.c128 || L.threads == 256) && (pass2_shape(L) || pass3_shape(L))) L.lds_bytes /= 2;
     L.grid = d.ntiles;
     // Streaming loads and stores pay off where a tile reads whole 128-byte
     // lines: where it reads half lines, the neighbouring tile (run at the

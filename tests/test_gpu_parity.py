@@ -200,34 +200,49 @@ def test_n31_maximum_size(torch_cuda, Q):
 
 
 @pytest.mark.timeout(900)
-def test_n30_c128_four_pass(torch_cuda, Q):
-    """complex128 at n = 30 (16 GiB): the planner's four-pass plan, exact and
-    AQFT, on sampled bins, and Parseval."""
+@pytest.mark.timeout(600)
+def test_n30_c128_whole_vector(torch_cuda, Q):
+    """complex128 at n = 30 (16 GiB): the default three-pass plan (2^13 lean
+    tiles) and an explicit four-pass split with 2^12 tiles, every output
+    element against the oracle's whole-vector form (plain C, FP64), the
+    AQFT on sampled bins, and Parseval."""
     torch = torch_cuda
     n = 30
     print("[gpu] n=30 c128 input", flush=True)
     x = I.gaussian(n, 3000)
     bins = np.random.default_rng(30).choice(1 << n, 12, replace=False)
     nx = float(np.sqrt(np.vdot(x, x).real))
-    print("[gpu] n=30 c128 oracle bins", flush=True)
-    refs = {-1: O.dft_bins(x, bins), 9: O.aqft_bins(x, bins, 9)}
+    print("[gpu] n=30 c128 oracle, whole vector", flush=True)
+    ref = O.qft_state_c(x, None)
+    ref9 = O.aqft_bins(x, bins, 9)
     xd = torch.from_numpy(x).cuda()
     del x
-    bd = torch.from_numpy(bins).cuda()
-    for k in (-1, 9):
-        print(f"[gpu] n=30 c128 cutoff={k}", flush=True)
-        plan = Q.Plan(n, k, "unitary", "c128", "natural")
-        assert plan.info.num_passes == 4
+    four = dict(tile_log2=12, radix_log2=5, spec_log2=2, rev_spec_log2=2,
+                pass_bits=[6, 8, 8, 8], pass_tile_log2=[12, 12, 12, 12])
+    for what, k, cfg, P in (("default", -1, None, 3), ("four-pass", -1, four, 4),
+                            ("default", 9, None, 3)):
+        print(f"[gpu] n=30 c128 {what} cutoff={k}", flush=True)
+        plan = Q.Plan(n, k, "unitary", "c128", "natural", config=cfg)
+        assert plan.info.num_passes == P
         t = xd.clone()
         plan.execute(t)
         torch.cuda.synchronize()
-        y = t[bd].cpu().numpy()
         ny = float(torch.linalg.vector_norm(t))
-        del t
         plan.close()
-        assert close(y, refs[k], "c128")
+        if k < 0:
+            y = t.cpu().numpy()
+            del t
+            e = O.error_norms(y, ref)
+            print(f"[parity] n=30 c128 {what}: rel_l2={e['rel_l2']:.3e} "
+                  f"max_err={e['max_err']:.3e}", flush=True)
+            assert e["rel_l2"] <= TOL["c128"] and e["max_err"] <= TOL["c128"]
+            del y
+        else:
+            y = t[torch.from_numpy(bins).cuda()].cpu().numpy()
+            del t
+            assert close(y, ref9, "c128")
         assert ny == pytest.approx(nx, rel=1e-12)
-    del xd
+    del xd, ref
     torch.cuda.empty_cache()
 
 

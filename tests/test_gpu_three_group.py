@@ -184,3 +184,48 @@ def test_four_wave_batch_bitwise(torch_cuda, Q):
         assert torch.equal(t, a), f"batched n={n} {split} {tiles} differs from the lone run"
     for p in plans:
         p.close()
+
+
+# ---- the lean complex128 forms: 2^13-element tiles of 256 threads ---------
+
+WIDE128 = [([6, 10, 6], [13, 13, 12]), ([5, 11, 6], [13, 13, 12]), ([6, 10, 8], [13, 13, 13])]
+
+
+@pytest.mark.parametrize("split,tiles", WIDE128)
+def test_lean_c128_wide_tiles(torch_cuda, Q, split, tiles):
+    n = sum(split)
+    x = I.gaussian(n, 5700 + n)
+    c = cfg("c128", split, pass_tile_log2=tiles)
+    info = Q.describe(n, -1, "unitary", "c128", "natural", "fused", c)
+    for p, t in enumerate(tiles):
+        assert info.pass_spec[p] == t - split[p]
+    for k, order, norm in ((-1, "natural", "unitary"), (6, "bitrev", "inv_n")):
+        y = run(torch_cuda, Q, x, n, k, norm, "c128", order, c, three=False)
+        ref = O.qft_fused_targets(x, None if k < 0 else k, norm, order)
+        check(y, ref, "c128", f"lean c128 n={n} {split} {tiles} k={k} {order}")
+    y = run(torch_cuda, Q, x, n, -1, "none", "c128", "natural", c, inverse=True, three=False)
+    check(y, O.qft_fused_targets(x, None, "none", "natural", inverse=True), "c128",
+          f"lean c128 inverse n={n} {split}")
+
+
+def test_lean_c128_batch_bitwise(torch_cuda, Q):
+    torch = torch_cuda
+    specs = [(20, -1, [5, 10, 5], [13, 13, 12]), (21, 8, [5, 11, 5], [13, 13, 12]),
+             (22, -1, [6, 10, 6], [13, 12, 13])]
+    plans, xs, alone = [], [], []
+    for i, (n, k, split, tiles) in enumerate(specs):
+        p = Q.Plan(n, k, "unitary", "c128", "natural", "fused",
+                   cfg("c128", split, pass_tile_log2=tiles))
+        plans.append(p)
+        t = torch.from_numpy(I.uniform_pm1(n, 5800 + i)).cuda()
+        xs.append(t)
+        a = t.clone()
+        p.execute(a)
+        alone.append(a)
+    print("[gpu] batch of lean complex128 plans", flush=True)
+    Q.execute_batch(plans, xs, graph=True)
+    torch.cuda.synchronize()
+    for (n, k, split, tiles), t, a in zip(specs, xs, alone):
+        assert torch.equal(t, a), f"batched n={n} {split} {tiles} differs from the lone run"
+    for p in plans:
+        p.close()

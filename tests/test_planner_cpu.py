@@ -99,14 +99,17 @@ def test_pass_partition_covers_each_qubit_once(n, dtype, order):
 
 
 def test_headline_pass_counts():
-    # n = 28 in three HBM passes for both element sizes, n = 30 in three
-    # (complex64) or four (complex128: a three-pass first pass would read
-    # 64-byte rows); n <= 13 (complex64) or <= 12 (complex128) in one
+    # n = 28 and 30 in three HBM passes for both element sizes (complex128
+    # n = 30 reaches 128-byte first-pass rows through its 2^13 tiles; with
+    # 2^12 tiles everywhere it takes four); n <= 13 (complex64) or <= 12
+    # (complex128) in one
     for dt in ("c64", "c128"):
         assert Q.describe(28, dtype=dt).num_passes == 3
-    assert Q.describe(30, dtype="c64").num_passes == 3
-    assert Q.describe(30, dtype="c128").num_passes == 4
-    assert list(Q.describe(30, dtype="c128").pass_bits)[:4] == [6, 8, 8, 8]
+        assert Q.describe(30, dtype=dt).num_passes == 3
+    assert list(Q.describe(30, dtype="c128").pass_bits)[:3] == [10, 10, 10]
+    narrow = dict(pass_tile_log2=[12, 12, 12, 12])
+    assert Q.describe(30, dtype="c128", config=narrow).num_passes == 3  # explicit tiles
+    assert Q.describe(31, dtype="c128").num_passes == 4
     assert Q.describe(13, dtype="c64").num_passes == 1
     assert Q.describe(12, dtype="c128").num_passes == 1
 
@@ -263,7 +266,8 @@ def test_nontemporal_rule():
         return [E.get_pass(n, -1, "unitary", lay, cfg, p)[0].nt for p in range(P)]
     assert nts(28) == [1, 1, 1]        # 256 B rows, 128 B rows (2^14 tiles), contiguous
     assert nts(27) == [1, 0, 1]        # 256 B rows, 64 B rows, contiguous
-    assert nts(27, "c128") == [1, 0, 1]
+    assert nts(27, "c128") == [1, 1, 1]   # 2^13 tiles: 128 B middle rows
+    assert nts(25, "c128") == [1, 0, 1]
     assert nts(24) == [0, 0, 0]        # 128 MiB state: stays cached
     assert nts(25) == [1, 0, 1]        # 256 MiB
     assert nts(24, "c128") == [1, 0, 1]
@@ -293,15 +297,17 @@ def test_group_factor_tables(n, k, dtype):
 
 def test_split_exchange_lds():
     # complex64 two-group passes exchange real and imaginary parts in turn
-    # through half the tile; complex128 ones use the whole tile
-    for dtype, es, half in (("c64", 8, True), ("c128", 16, False)):
+    # through half the tile; complex128 ones use the whole tile, except the
+    # lean 2^13-tile form (256 threads), which splits too
+    for n, dtype, es in ((27, "c64", 8), (27, "c128", 16), (24, "c128", 16)):
         lay = Q.layout_flags(dtype)
-        info = Q.describe(27, dtype=dtype)
+        info = Q.describe(n, dtype=dtype)
         for p in range(info.num_passes):
-            d, launch = E.get_pass(27, -1, "unitary", lay, None, p)
+            d, launch = E.get_pass(n, -1, "unitary", lay, None, p)
             assert info.pass_kernel[p]
             full = (1 << d.T) * es
-            assert launch[1] == (full // 2 if half else full)
+            half = dtype == "c64" or launch[0] == 256
+            assert launch[1] == (full // 2 if half else full), (n, dtype, p)
 
 
 def test_wide_first_pass():
@@ -315,7 +321,7 @@ def test_wide_first_pass():
     assert list(info.pass_spec)[:3] == [4, 3, 3]
     for n, spec in ((28, [5, 4, 4]), (29, [5, 3, 4]), (30, [4, 4, 4])):
         assert list(Q.describe(n, dtype="c64").pass_spec)[:3] == spec
-    assert list(Q.describe(29, dtype="c128").pass_spec)[:3] == [3, 2, 2]  # complex64 only
+    assert list(Q.describe(29, dtype="c128").pass_spec)[:3] == [4, 3, 3]  # 2^13 tiles
     cfg = dict(tile_log2=10, radix_log2=4, spec_log2=3, rev_spec_log2=3)
     n = 21
     info = Q.describe(n, -1, "unitary", "c64", "natural", "fused", cfg)
@@ -380,11 +386,12 @@ def test_three_group_middle_pass_rule():
 
 
 def test_wide_high_pass_tiles():
-    """Complex64 three-pass plans of 2^28..2^30 elements give every pass
-    below which other qubits lie a 2^14-element tile of 512 threads (the
-    four-wave kernels), and the last pass too where its rows would otherwise
-    be shorter than 128 bytes; other sizes, complex128 and bit-reversed plans
-    keep 2^13 (complex128 2^12)."""
+    """Three-pass plans of 2^28..2^30 complex64 or 2^26..2^30 complex128
+    elements give every pass below which other qubits lie one more tile bit
+    (2^14 complex64 tiles of 512 threads, 2^13 complex128 of 256: the lean
+    kernels), and the last pass too where its rows would otherwise be
+    shorter than 128 bytes; other sizes and bit-reversed plans keep 2^13
+    (complex128 2^12)."""
     lay = Q.layout_flags("c64")
     expect = {28: [14, 14, 13], 29: [14, 14, 13], 30: [14, 14, 14]}
     for n, tiles in expect.items():
@@ -398,9 +405,14 @@ def test_wide_high_pass_tiles():
         for p in range(info.num_passes):
             d, _ = E.get_pass(n, -1, "unitary", lay, None, p)
             assert d.T <= 13 or (n == 31 and p == 0), (n, p, d.T)
+    c128 = {24: [12, 12, 12], 25: [12, 12, 12], 26: [13, 13, 12], 28: [13, 13, 12],
+            29: [13, 13, 13], 30: [13, 13, 13]}
+    for n, tiles in c128.items():
+        for p in range(3):
+            d, launch = E.get_pass(n, -1, "unitary", Q.layout_flags("c128"), None, p)
+            assert d.T == tiles[p], (n, p)
+            assert launch[0] == 1 << (tiles[p] - 5)
     for p in range(3):
-        d, _ = E.get_pass(28, -1, "unitary", Q.layout_flags("c128"), None, p)
-        assert d.T == 12
         d, _ = E.get_pass(28, -1, "unitary", Q.layout_flags("c64", "bitrev"), None, p)
         assert d.T == 13
 
