@@ -33,7 +33,7 @@ int qft_tune(int n, int cutoff, int norm, int layout, void *data, int reps,
              qft_config_t *best, double *best_ms);
 
 /* Tune one configuration shared by all transforms of a batch: for each
- * candidate of the batch grid (tile_log2 8..13, radix_log2 3..5, spectator
+ * candidate of the batch grid (tile_log2 8..14, radix_log2 3..5, spectator
  * widths 2..4), plans (n[i], cutoff[i], norm, layout) are built with it and
  * the batch on data[i] is timed through qft_execute_batch (graph launch,
  * after one call that captures it).  The winner and its time are returned;

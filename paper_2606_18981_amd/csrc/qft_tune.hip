@@ -234,9 +234,10 @@ int qft_tune_batch(const int *n, const int *cutoff, int count, int norm, int lay
   qft_config_t bc{};
   bool found = false;
   int rc = QFT_OK;
-  // the batch grid: tiles of 2^8..2^13 elements (the batch's transforms have
-  // 2^8..2^20), radix 8..32, spectator widths 2..4
-  for (const qft_config_t &c : candidate_grid(8, 13, 4)) {
+  // the batch grid: tiles of 2^8..2^14 elements (the batch's transforms have
+  // 2^8..2^20; 2^14 complex64 tiles run the four-wave kernels), radix 8..32,
+  // spectator widths 2..4
+  for (const qft_config_t &c : candidate_grid(8, 14, 4)) {
     // one plan per distinct shape, shared by the transforms of that shape
     std::map<std::pair<int, int>, qft_plan_t *> plans;
     std::vector<qft_plan_t *> pv(count, nullptr);
