@@ -8,6 +8,8 @@
  *  - qft_compare: those metrics between a transform's output and a
  *    reference output already in device memory (for instance the exact
  *    transform of the same input), in one reading pass over both arrays;
+ *  - qft_execute_compare: a transform whose last pass also takes those
+ *    metrics against a reference, so that its output is not read back;
  *  - qft_aqft_expected_error: the expected relative L2 error of the range-k
  *    AQFT against the exact transform for inputs with i.i.d. complex
  *    Gaussian amplitudes, in closed form (host only);
@@ -50,6 +52,30 @@ size_t qft_compare_workspace_bytes(int n);
  * QFT_ERR_POINTER (NULL or misaligned pointer).                           */
 int qft_compare(const void *y, const void *ref, int n, int layout, void *workspace,
                 double *metrics_dev, qft_stream_t stream);
+
+/* Device workspace qft_execute_compare needs for this plan, in bytes (0 for
+ * a NULL plan).                                                            */
+size_t qft_execute_compare_workspace_bytes(const qft_plan_t *plan);
+
+/* Transform dev_ptr in place as qft_execute_ws does (workspace NULL = the
+ * plan's own), and write to metrics_dev the QFT_METRIC_COUNT metrics of
+ * qft_compare between the output y and `ref` (2^n elements of the plan's
+ * element type, in the plan's output order, for instance the exact
+ * transform of the same input), asynchronously on `stream`.  Sec. 4's
+ * accuracy measures of the range-k AQFT taken as the transform runs: with
+ * the fused schedule the last pass compares the tiles it stores with ref
+ * (it reads ref once and never reads y back), and a short reduction of its
+ * per-wave FP64 partials follows; with the gate schedule a separate
+ * comparison pass follows the transform.  The partials are combined in a
+ * fixed order, so a call is deterministic; the sums are the same as
+ * qft_compare's up to FP64 rounding order (the maxima and the argmax are
+ * identical).  ref must not overlap dev_ptr (QFT_ERR_INVALID).
+ * cmp_workspace: device memory of qft_execute_compare_workspace_bytes(plan)
+ * bytes, 8-byte aligned, caller-owned; calls that share it must be ordered
+ * on one stream.  Errors as qft_execute_ws, and QFT_ERR_POINTER for a NULL
+ * or misaligned ref, cmp_workspace or metrics_dev.                          */
+int qft_execute_compare(qft_plan_t *plan, void *dev_ptr, void *workspace, const void *ref,
+                        void *cmp_workspace, double *metrics_dev, qft_stream_t stream);
 
 /* Expected relative L2 error E||(U - U_k) x|| / E||U x|| of the range-k
  * AQFT U_k against the exact QFT U (both unitary) for inputs with i.i.d.

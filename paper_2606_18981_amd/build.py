@@ -25,6 +25,12 @@ HIP_FLAGS = COMMON + [
     "--offload-arch=gfx950",
     # no packed-FP32 instructions in generated device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only where one source expression holds both
+    # (a * b + c), never across statements: the fusion then depends on the
+    # source alone, so every kernel built from the same tile code (the plain
+    # pass, its batched form, the pass that also compares its output)
+    # rounds the same way
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
 ]
 

@@ -68,8 +68,10 @@ void clear_error() { g_last_error.clear(); }
 
 // Enqueue the kernels of a plan.  `ws` may be NULL when the plan needs none.
 // With norm_out, `part` holds the plan's norm_parts_for() partial sums.
+// With cmp (fused schedule only), the last pass also writes the comparison
+// partials of its output against cmp->ref.
 int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm_out,
-                 double *part, bool allow_timing) {
+                 double *part, bool allow_timing, const FusedCompare *cmp) {
   const HostPlan &hp = p->hp;
   hipError_t e = hipSuccess;
   size_t li = 0;
@@ -89,11 +91,20 @@ int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm
       mark(li);
       const void *in = L.in_ws ? ws : dev;
       void *out = L.out_ws ? ws : dev;
-      if (i == 0 && norm_out) {
-        // the first pass also sums |x|^2 of the tiles it loads
-        PassLaunch Ln = L;
-        Ln.d.norm_part = part;
-        e = launch_fused_pass(Ln, hp.c128, in, out, s);
+      const bool first_norm = i == 0 && norm_out;
+      const bool last_cmp = i + 1 == p->launches.size() && cmp;
+      if (first_norm || last_cmp) {
+        // the first pass also sums |x|^2 of the tiles it loads; the last
+        // also compares the tiles it stores with the reference
+        PassLaunch Lx = L;
+        if (first_norm) Lx.d.norm_part = part;
+        if (last_cmp) {
+          Lx.d.cmp_ref = cmp->ref;
+          Lx.d.cmp_part = cmp->part;
+          e = launch_fused_pass_compare(Lx, hp.c128, in, out, s);
+        } else {
+          e = launch_fused_pass(Lx, hp.c128, in, out, s);
+        }
       } else {
         e = launch_fused_pass(L, hp.c128, in, out, s);
       }
@@ -133,6 +144,25 @@ uint32_t norm_parts_for(const qft_plan_s *p) {
   }
   const uint32_t N = 1u << hp.n;
   return std::max(1u, std::min(1024u, N / 4096u));
+}
+
+// Argument checks shared by the execute entry points (no device work).
+int check_execute(qft_plan_s *plan, void *dev_ptr, void *workspace) {
+  if (!plan) return set_error(QFT_ERR_INVALID, "plan is NULL");
+  if (!dev_ptr) return set_error(QFT_ERR_POINTER, "data pointer is NULL");
+  if ((uintptr_t)dev_ptr % plan->hp.elem_bytes)
+    return set_error(QFT_ERR_POINTER, "data pointer is not aligned to the element size");
+  if (plan->hp.ws_bytes && !workspace)
+    return set_error(QFT_ERR_POINTER,
+                     "this plan needs a workspace (pass one with qft_execute_ws)");
+  if (workspace && (uintptr_t)workspace % plan->hp.elem_bytes)
+    return set_error(QFT_ERR_POINTER, "workspace pointer is not aligned to the element size");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  if (dev != plan->device)
+    return set_error(QFT_ERR_INVALID, "the current device is not the plan's device");
+  return QFT_OK;
 }
 
 // ---- per-launch timing ---------------------------------------------------
@@ -225,29 +255,6 @@ static qft_plan_t *make_plan(int n, int cutoff, int norm, int layout, const qft_
   }
   return p;
 }
-
-namespace {
-
-// Argument checks shared by the execute entry points (no device work).
-int check_execute(qft_plan_s *plan, void *dev_ptr, void *workspace) {
-  if (!plan) return set_error(QFT_ERR_INVALID, "plan is NULL");
-  if (!dev_ptr) return set_error(QFT_ERR_POINTER, "data pointer is NULL");
-  if ((uintptr_t)dev_ptr % plan->hp.elem_bytes)
-    return set_error(QFT_ERR_POINTER, "data pointer is not aligned to the element size");
-  if (plan->hp.ws_bytes && !workspace)
-    return set_error(QFT_ERR_POINTER,
-                     "this plan needs a workspace (pass one with qft_execute_ws)");
-  if (workspace && (uintptr_t)workspace % plan->hp.elem_bytes)
-    return set_error(QFT_ERR_POINTER, "workspace pointer is not aligned to the element size");
-  int dev = -1;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
-  if (dev != plan->device)
-    return set_error(QFT_ERR_INVALID, "the current device is not the plan's device");
-  return QFT_OK;
-}
-
-}  // namespace
 
 extern "C" {
 

@@ -93,7 +93,16 @@ struct PassDesc {
   const void *gtab1;          // the same for group 1 of a three-group pass
   double *norm_part;          // non-null: per-wave sums of |x|^2 of the
                               // loaded tile at [tile * parts_per_tile + w]
+  const void *cmp_ref;        // last pass of a compare execute: reference
+                              // output (same layout as the output), or null
+  double *cmp_part;           // its per-wave comparison partials, kCmpSlots
+                              // doubles each, at [tile * parts_per_tile + w]
 };
+
+// Slots of one comparison partial (FP64), in this order: sum |y - r|^2,
+// sum |r|^2, sum |y|^2, Re and Im of sum conj(r) y, max |y - r|^2, max |r|^2
+// and the lowest index where |r|^2 takes that maximum (as a double).
+constexpr int kCmpSlots = 8;
 
 // Partial sums of |x|^2 one workgroup of `threads` threads writes when a pass
 // reduces the norm of its input: one per wave of 64, or one per thread when
@@ -144,5 +153,10 @@ inline int pass_kernel_shape(const PassLaunch &L) {
   const int three = pass3_shape(L);
   return three ? 10 + three : 0;
 }
+
+// The lean (four-wave) form of the compile-time kernels runs every
+// complex64 pass of 512 threads (2^14-element tiles) and every complex128
+// one of 256 threads (2^13).
+inline bool lean_form(const PassLaunch &L, bool c128) { return L.threads == (c128 ? 256 : 512); }
 
 }  // namespace qft

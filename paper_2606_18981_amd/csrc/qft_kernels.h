@@ -16,6 +16,12 @@ hipError_t ensure_lds_limit(const void *fn, int bytes);
 hipError_t launch_fused_pass(const PassLaunch &L, bool c128, const void *in, void *out,
                              hipStream_t s);
 
+// The last pass of a plan with its output also compared with L.d.cmp_ref
+// (the pass kernels' comparison epilogue; defined in qft_metrics.hip).  The
+// last pass has no controls below it: L.d.ext_tw must be 0.
+hipError_t launch_fused_pass_compare(const PassLaunch &L, bool c128, const void *in, void *out,
+                                     hipStream_t s);
+
 // Batched launches (see k_batch_group).
 struct BatchSeg {
   uint32_t first;    // first work item (workgroup) of the segment in its group

@@ -8,12 +8,8 @@
 
 #include "../../include/qft_metrics.h"
 #include "qft_kernels.h"
+#include "qft_pass_tile.h"
 #include "qft_runtime.h"
-
-namespace qft {
-int set_error(int code, const std::string &msg);
-void clear_error();
-}  // namespace qft
 
 using namespace qft;
 
@@ -21,119 +17,94 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxExpectedBits = 20;  // closed form costs 2^M * M terms
-constexpr int kSlots = 8;  // per-workgroup partials, see Part
+constexpr int kMaxCombined = 1024;    // partials left for the finishing workgroup
 
-// interleaved complex element (re, im), as the transforms store it
-template <typename Real>
-struct alignas(2 * sizeof(Real)) elem {
-  Real x, y;
-};
-
-// Sums of one workgroup's share (FP64): |y - r|^2, |r|^2, |y|^2,
-// Re and Im of conj(r) y, the largest |y - r|^2, and the largest |r|^2 with
-// its lowest index.
-struct Part {
-  double d2, r2, y2, cr, ci, md2, mr2, mri;
-};
-
-__device__ __forceinline__ void part_add(Part &a, const Part &b) {
-  a.d2 += b.d2;
-  a.r2 += b.r2;
-  a.y2 += b.y2;
-  a.cr += b.cr;
-  a.ci += b.ci;
-  a.md2 = fmax(a.md2, b.md2);
-  if (b.mr2 > a.mr2 || (b.mr2 == a.mr2 && b.mri < a.mri)) {
-    a.mr2 = b.mr2;
-    a.mri = b.mri;
-  }
+__device__ __forceinline__ CmpPart cmp_load(const double *o) {
+  return CmpPart{o[0], o[1], o[2], o[3], o[4], o[5], o[6], o[7]};
 }
 
-__device__ __forceinline__ Part part_shfl_xor(const Part &p, int off) {
-  Part q;
-  q.d2 = __shfl_xor(p.d2, off, 64);
-  q.r2 = __shfl_xor(p.r2, off, 64);
-  q.y2 = __shfl_xor(p.y2, off, 64);
-  q.cr = __shfl_xor(p.cr, off, 64);
-  q.ci = __shfl_xor(p.ci, off, 64);
-  q.md2 = __shfl_xor(p.md2, off, 64);
-  q.mr2 = __shfl_xor(p.mr2, off, 64);
-  q.mri = __shfl_xor(p.mri, off, 64);
-  return q;
+__device__ __forceinline__ void cmp_store(double *o, const CmpPart &a) {
+  o[0] = a.d2;
+  o[1] = a.r2;
+  o[2] = a.y2;
+  o[3] = a.cr;
+  o[4] = a.ci;
+  o[5] = a.md2;
+  o[6] = a.mr2;
+  o[7] = a.mri;
 }
 
-// Workgroup b reduces the contiguous block [b * per, min(N, (b + 1) * per))
-// and writes its Part to part[b].  Each thread sums its elements in index
-// order, waves combine lanes in a fixed butterfly, then the 4 wave results
-// are combined in order: the result does not depend on scheduling.
-template <typename Real>
-__global__ void __launch_bounds__(kThreads) k_compare_part(const elem<Real> *y,
-                                                           const elem<Real> *r, uint64_t N,
-                                                           uint64_t per, double *part) {
-  __shared__ Part red[kThreads / 64];
-  const uint64_t lo = (uint64_t)blockIdx.x * per;
-  const uint64_t hi = lo + per < N ? lo + per : N;
-  Part p{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1.0, 0.0};
-  for (uint64_t i = lo + threadIdx.x; i < hi; i += kThreads) {
-    const double yx = (double)y[i].x, yy = (double)y[i].y;
-    const double rx = (double)r[i].x, ry = (double)r[i].y;
-    const double dx = yx - rx, dy = yy - ry;
-    const double d2 = dx * dx + dy * dy;
-    const double r2 = rx * rx + ry * ry;
-    p.d2 += d2;
-    p.r2 += r2;
-    p.y2 += yx * yx + yy * yy;
-    p.cr += rx * yx + ry * yy;  // conj(r) * y
-    p.ci += rx * yy - ry * yx;
-    p.md2 = fmax(p.md2, d2);
-    if (r2 > p.mr2) {  // indices rise within a thread: first maximum wins
-      p.mr2 = r2;
-      p.mri = (double)i;
-    }
-  }
+// Combine a workgroup's per-thread partials into one, written to out by
+// thread 0: lanes in a fixed butterfly, then the waves in order, so that
+// the result does not depend on scheduling.
+__device__ __forceinline__ void cmp_reduce_block(CmpPart p, double *out) {
+  __shared__ CmpPart red[kThreads / 64];
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const Part q = part_shfl_xor(p, off);
-    // combine in lane order so that every lane holds the same result
-    Part lo_p = (threadIdx.x & off) ? q : p;
-    const Part hi_p = (threadIdx.x & off) ? p : q;
-    part_add(lo_p, hi_p);
-    p = lo_p;
-  }
+  for (int off = 1; off < 64; off <<= 1) cmp_combine(p, cmp_shfl_xor(p, off));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = p;
   __syncthreads();
   if (threadIdx.x == 0) {
-    Part a = red[0];
-    for (int w = 1; w < kThreads / 64; ++w) part_add(a, red[w]);
-    double *o = part + (size_t)blockIdx.x * kSlots;
-    o[0] = a.d2;
-    o[1] = a.r2;
-    o[2] = a.y2;
-    o[3] = a.cr;
-    o[4] = a.ci;
-    o[5] = a.md2;
-    o[6] = a.mr2;
-    o[7] = a.mri;
+    CmpPart a = red[0];
+    for (int w = 1; w < kThreads / 64; ++w) cmp_combine(a, red[w]);
+    cmp_store(out, a);
   }
 }
 
-// One workgroup: combine the partials in order, then form the metrics.
+// Workgroup b reduces the contiguous block [b * per, min(N, (b + 1) * per))
+// of y and r and writes its partial to part[b].  Each thread sums its
+// elements in index order, with the per-element terms of the comparison
+// folded into a transform's last pass (cmp_accumulate).
 template <typename Real>
-__global__ void __launch_bounds__(kThreads) k_compare_finish(const elem<Real> *y, uint64_t N,
+__global__ void __launch_bounds__(kThreads) k_compare_part(const cplx<Real> *y,
+                                                           const cplx<Real> *r, uint64_t N,
+                                                           uint64_t per, double *part) {
+  const uint64_t lo = (uint64_t)blockIdx.x * per;
+  const uint64_t hi = lo + per < N ? lo + per : N;
+  CmpAcc acc{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1.0, 0xffffffffu};
+  constexpr int U = 4;  // elements in flight per thread
+  uint64_t i = lo + threadIdx.x;
+  for (; i + (U - 1) * kThreads < hi; i += U * kThreads) {
+    cplx<Real> ya[U], ra[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ya[u] = ld_elem<true>(y + i + u * kThreads);  // read once: streaming
+      ra[u] = ld_elem<true>(r + i + u * kThreads);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) cmp_accumulate<Real>(acc, ya[u], ra[u], (uint32_t)(i + u * kThreads));
+  }
+  for (; i < hi; i += kThreads) cmp_accumulate<Real>(acc, y[i], r[i], (uint32_t)i);
+  const CmpPart p{acc.d2, acc.r2, acc.y2, acc.cr, acc.ci, acc.md2, acc.mr2, (double)acc.mi};
+  cmp_reduce_block(p, part + (size_t)blockIdx.x * kCmpSlots);
+}
+
+// Workgroup b combines the partials [b * per, min(count, (b + 1) * per)) of
+// a compare pass into out[b] (each thread in index order, then the block).
+__global__ void __launch_bounds__(kThreads) k_compare_combine(const double *part, uint64_t count,
+                                                              uint64_t per, double *out) {
+  const uint64_t lo = (uint64_t)blockIdx.x * per;
+  const uint64_t hi = lo + per < count ? lo + per : count;
+  CmpPart p{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1.0, 0.0};
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kThreads)
+    cmp_combine(p, cmp_load(part + i * kCmpSlots));
+  cmp_reduce_block(p, out + (size_t)blockIdx.x * kCmpSlots);
+}
+
+// One workgroup: combine the partials in order, then form the metrics (the
+// leakage reads y at the reference's argmax).
+template <typename Real>
+__global__ void __launch_bounds__(kThreads) k_compare_finish(const cplx<Real> *y, uint64_t N,
                                                              const double *part, int nparts,
                                                              double *out) {
-  __shared__ Part red[kThreads];
-  Part p{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1.0, 0.0};
-  for (int b = threadIdx.x; b < nparts; b += kThreads) {
-    const double *o = part + (size_t)b * kSlots;
-    const Part q{o[0], o[1], o[2], o[3], o[4], o[5], o[6], o[7]};
-    part_add(p, q);
-  }
+  __shared__ CmpPart red[kThreads];
+  CmpPart p{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1.0, 0.0};
+  for (int b = threadIdx.x; b < nparts; b += kThreads)
+    cmp_combine(p, cmp_load(part + (size_t)b * kCmpSlots));
   red[threadIdx.x] = p;
   __syncthreads();
   if (threadIdx.x == 0) {
-    Part a = red[0];
-    for (int t = 1; t < kThreads; ++t) part_add(a, red[t]);
+    CmpPart a = red[0];
+    for (int t = 1; t < kThreads; ++t) cmp_combine(a, red[t]);
     const double dn = sqrt(a.d2), rn = sqrt(a.r2), yn = sqrt(a.y2);
     const double rms = rn / sqrt((double)(N > 0 ? N : 1));
     const double md = sqrt(a.md2 > 0.0 ? a.md2 : 0.0);
@@ -156,13 +127,164 @@ int compare_parts(int n) {
   return (int)(want < 1 ? 1 : (want > 1024 ? 1024 : want));
 }
 
+// The separate comparison: one reading pass over y and ref into
+// compare_parts(n) partials at `part`, then the finishing workgroup.
+hipError_t launch_compare(const void *y, const void *ref, int n, bool c128, double *part,
+                          double *metrics, hipStream_t s) {
+  const uint64_t N = 1ull << n;
+  const int parts = compare_parts(n);
+  const uint64_t per = (N + parts - 1) / parts;
+  if (c128) {
+    hipLaunchKernelGGL(k_compare_part<double>, dim3(parts), dim3(kThreads), 0, s,
+                       (const cplx<double> *)y, (const cplx<double> *)ref, N, per, part);
+    hipLaunchKernelGGL(k_compare_finish<double>, dim3(1), dim3(kThreads), 0, s,
+                       (const cplx<double> *)y, N, part, parts, metrics);
+  } else {
+    hipLaunchKernelGGL(k_compare_part<float>, dim3(parts), dim3(kThreads), 0, s,
+                       (const cplx<float> *)y, (const cplx<float> *)ref, N, per, part);
+    hipLaunchKernelGGL(k_compare_finish<float>, dim3(1), dim3(kThreads), 0, s,
+                       (const cplx<float> *)y, N, part, parts, metrics);
+  }
+  return hipGetLastError();
+}
+
+// ---- the comparison folded into a plan's last pass ------------------------
+
+// The pass kernels with the comparison epilogue.  A plan's last pass has no
+// controls below it, so these have no below-pass diagonal (EXT false).
+template <typename Real, int RB>
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? (RB >= 5 ? 256 : RB >= 3 ? 512 : 1024)
+                                                   : (RB >= 5 ? 512 : 1024))
+k_fused_pass_cmp(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  tile_body<Real, RB, true>(d, pass_tile_index(d), in, out,
+                            reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x, true);
+}
+
+template <typename Real, int NSTL, bool NT>
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? 256 : 512)
+k_fused_pass2_cmp(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  pass2_tile<Real, 5, NSTL, false, NT, false, true>(
+      d, pass_tile_index(d), in, out, reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x);
+}
+
+template <typename Real, int NSTL, bool NT>
+__global__ void QFT_LEAN_BOUNDS(Real)
+k_fused_pass2w_cmp(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  pass2_tile<Real, 5, NSTL, false, NT, true, true>(
+      d, pass_tile_index(d), in, out, reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x);
+}
+
+template <typename Real, int S, bool NT>
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? 256 : 512)
+k_fused_pass3_cmp(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  pass3_tile<Real, 5, S, false, NT, false, true>(
+      d, pass_tile_index(d), in, out, reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x);
+}
+
+template <typename Real, int S, bool NT>
+__global__ void QFT_LEAN_BOUNDS(Real)
+k_fused_pass3w_cmp(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  pass3_tile<Real, 5, S, false, NT, true, true>(
+      d, pass_tile_index(d), in, out, reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x);
+}
+
+template <typename Real, int RB>
+hipError_t launch_cmp_t(const PassLaunch &L, const void *in, void *out, hipStream_t s) {
+  using K = void (*)(const PassDesc, const cplx<Real> *, cplx<Real> *);
+  K fn = k_fused_pass_cmp<Real, RB>;
+  if constexpr (RB == 5) {
+    const int shape = pass_kernel_shape(L);
+    const bool lean = lean_form(L, sizeof(Real) == 8);
+    const int nt = L.d.nt ? 1 : 0;
+    if (shape > 10) {
+      static const K tab3[2][3] = {
+          {k_fused_pass3_cmp<Real, 1, false>, k_fused_pass3_cmp<Real, 2, false>,
+           k_fused_pass3_cmp<Real, 3, false>},
+          {k_fused_pass3_cmp<Real, 1, true>, k_fused_pass3_cmp<Real, 2, true>,
+           k_fused_pass3_cmp<Real, 3, true>}};
+      static const K tab3w[2][3] = {
+          {k_fused_pass3w_cmp<Real, 1, false>, k_fused_pass3w_cmp<Real, 2, false>,
+           k_fused_pass3w_cmp<Real, 3, false>},
+          {k_fused_pass3w_cmp<Real, 1, true>, k_fused_pass3w_cmp<Real, 2, true>,
+           k_fused_pass3w_cmp<Real, 3, true>}};
+      fn = (lean ? tab3w : tab3)[nt][L.d.lane_swap - 1];
+    } else if (shape) {
+#define QFT_P2C(K2, N)                                                                \
+  {K2<Real, 1, N>, K2<Real, 2, N>, K2<Real, 3, N>, K2<Real, 4, N>, K2<Real, 5, N>}
+      static const K tab[2][5] = {QFT_P2C(k_fused_pass2_cmp, false),
+                                  QFT_P2C(k_fused_pass2_cmp, true)};
+      static const K tabw[2][5] = {QFT_P2C(k_fused_pass2w_cmp, false),
+                                   QFT_P2C(k_fused_pass2w_cmp, true)};
+#undef QFT_P2C
+      fn = (lean ? tabw : tab)[nt][L.d.grp[1].nst - 1];
+    }
+  }
+  if (L.lds_bytes > 65536) {
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void *>(fn), 163840);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(fn, dim3(L.grid), dim3(L.threads), L.lds_bytes, s, L.d,
+                     (const cplx<Real> *)in, (cplx<Real> *)out);
+  return hipGetLastError();
+}
+
+// Partials of the last pass of a fused plan (one per wave, or per thread
+// below a wave), and the workgroups that combine them.
+uint64_t fused_cmp_parts(const qft_plan_s *p) {
+  const PassLaunch &L = p->launches.back();
+  return (uint64_t)L.d.ntiles * (uint64_t)norm_parts_per_tile(L.threads);
+}
+uint32_t fused_cmp_groups(uint64_t parts) {
+  const uint64_t g = (parts + kThreads - 1) / kThreads;  // at least a partial per thread
+  return (uint32_t)(g < 1 ? 1 : (g > (uint64_t)kMaxCombined ? kMaxCombined : g));
+}
+
+size_t execute_compare_ws_bytes(const qft_plan_s *p) {
+  if (p->hp.schedule != Schedule::Fused)
+    return (size_t)compare_parts(p->hp.n) * kCmpSlots * sizeof(double);
+  const uint64_t parts = fused_cmp_parts(p);
+  return (size_t)(parts + fused_cmp_groups(parts)) * kCmpSlots * sizeof(double);
+}
+
 }  // namespace
+
+namespace qft {
+
+hipError_t launch_fused_pass_compare(const PassLaunch &L, bool c128, const void *in, void *out,
+                                     hipStream_t s) {
+  if (L.d.ext_tw || !L.d.cmp_ref || !L.d.cmp_part) return hipErrorInvalidValue;
+  if (c128) {
+    switch (L.d.r) {
+      case 1: return launch_cmp_t<double, 1>(L, in, out, s);
+      case 2: return launch_cmp_t<double, 2>(L, in, out, s);
+      case 3: return launch_cmp_t<double, 3>(L, in, out, s);
+      case 4: return launch_cmp_t<double, 4>(L, in, out, s);
+      case 5: return launch_cmp_t<double, 5>(L, in, out, s);
+    }
+  } else {
+    switch (L.d.r) {
+      case 1: return launch_cmp_t<float, 1>(L, in, out, s);
+      case 2: return launch_cmp_t<float, 2>(L, in, out, s);
+      case 3: return launch_cmp_t<float, 3>(L, in, out, s);
+      case 4: return launch_cmp_t<float, 4>(L, in, out, s);
+      case 5: return launch_cmp_t<float, 5>(L, in, out, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace qft
 
 extern "C" {
 
 size_t qft_compare_workspace_bytes(int n) {
   if (n < 0 || n > QFT_MAX_QUBITS) return 0;
-  return (size_t)compare_parts(n) * kSlots * sizeof(double);
+  return (size_t)compare_parts(n) * kCmpSlots * sizeof(double);
 }
 
 int qft_compare(const void *y, const void *ref, int n, int layout, void *workspace,
@@ -177,23 +299,65 @@ int qft_compare(const void *y, const void *ref, int n, int layout, void *workspa
     return set_error(QFT_ERR_POINTER, "data pointer is not aligned to the element size");
   if ((uintptr_t)workspace % 8 || (uintptr_t)metrics_dev % 8)
     return set_error(QFT_ERR_POINTER, "workspace or metrics pointer is not 8-byte aligned");
-  const uint64_t N = 1ull << n;
-  const int parts = compare_parts(n);
-  const uint64_t per = (N + parts - 1) / parts;
+  hipError_t e = launch_compare(y, ref, n, c128, (double *)workspace, metrics_dev,
+                                (hipStream_t)stream);
+  if (e != hipSuccess)
+    return set_error(QFT_ERR_HIP, std::string("compare launch: ") + hipGetErrorString(e));
+  return QFT_OK;
+}
+
+size_t qft_execute_compare_workspace_bytes(const qft_plan_t *plan) {
+  return plan ? execute_compare_ws_bytes(plan) : 0;
+}
+
+int qft_execute_compare(qft_plan_t *plan, void *dev_ptr, void *workspace, const void *ref,
+                        void *cmp_workspace, double *metrics_dev, qft_stream_t stream) {
+  clear_error();
+  if (plan && !workspace) workspace = plan->d_ws;
+  int rc = check_execute(plan, dev_ptr, workspace);
+  if (rc != QFT_OK) return rc;
+  const HostPlan &hp = plan->hp;
+  if (!ref || !cmp_workspace || !metrics_dev)
+    return set_error(QFT_ERR_POINTER, "NULL reference, compare workspace or metrics pointer");
+  if ((uintptr_t)ref % hp.elem_bytes)
+    return set_error(QFT_ERR_POINTER, "reference pointer is not aligned to the element size");
+  if ((uintptr_t)cmp_workspace % 8 || (uintptr_t)metrics_dev % 8)
+    return set_error(QFT_ERR_POINTER,
+                     "compare workspace or metrics pointer is not 8-byte aligned");
+  const uintptr_t bytes = (uintptr_t)hp.elem_bytes << hp.n;
+  const uintptr_t r0 = (uintptr_t)ref, d0 = (uintptr_t)dev_ptr;
+  if (r0 < d0 + bytes && d0 < r0 + bytes)
+    return set_error(QFT_ERR_INVALID, "the reference overlaps the transformed array");
   hipStream_t s = (hipStream_t)stream;
-  double *part = (double *)workspace;
-  if (c128) {
-    hipLaunchKernelGGL(k_compare_part<double>, dim3(parts), dim3(kThreads), 0, s,
-                       (const elem<double> *)y, (const elem<double> *)ref, N, per, part);
-    hipLaunchKernelGGL(k_compare_finish<double>, dim3(1), dim3(kThreads), 0, s,
-                       (const elem<double> *)y, N, part, parts, metrics_dev);
+  double *part = (double *)cmp_workspace;
+  hipError_t e = hipSuccess;
+  if (hp.schedule != Schedule::Fused) {
+    rc = enqueue_plan(plan, dev_ptr, workspace, s, nullptr, nullptr, true);
+    if (rc != QFT_OK) return rc;
+    e = launch_compare(dev_ptr, ref, hp.n, hp.c128, part, metrics_dev, s);
   } else {
-    hipLaunchKernelGGL(k_compare_part<float>, dim3(parts), dim3(kThreads), 0, s,
-                       (const elem<float> *)y, (const elem<float> *)ref, N, per, part);
-    hipLaunchKernelGGL(k_compare_finish<float>, dim3(1), dim3(kThreads), 0, s,
-                       (const elem<float> *)y, N, part, parts, metrics_dev);
+    const PassLaunch &last = plan->launches.back();
+    if (last.d.ext_tw || last.out_ws)
+      return set_error(QFT_ERR_UNSUPPORTED,
+                       "the plan's last pass does not end in the data array");
+    const FusedCompare cmp{ref, part};
+    rc = enqueue_plan(plan, dev_ptr, workspace, s, nullptr, nullptr, true, &cmp);
+    if (rc != QFT_OK) return rc;
+    const uint64_t parts = fused_cmp_parts(plan);
+    const uint32_t groups = fused_cmp_groups(parts);
+    const uint64_t per = (parts + groups - 1) / groups;
+    double *comb = part + parts * kCmpSlots;
+    hipLaunchKernelGGL(k_compare_combine, dim3(groups), dim3(kThreads), 0, s, part, parts, per,
+                       comb);
+    const uint64_t N = 1ull << hp.n;
+    if (hp.c128)
+      hipLaunchKernelGGL(k_compare_finish<double>, dim3(1), dim3(kThreads), 0, s,
+                         (const cplx<double> *)dev_ptr, N, comb, (int)groups, metrics_dev);
+    else
+      hipLaunchKernelGGL(k_compare_finish<float>, dim3(1), dim3(kThreads), 0, s,
+                         (const cplx<float> *)dev_ptr, N, comb, (int)groups, metrics_dev);
+    e = hipGetLastError();
   }
-  hipError_t e = hipGetLastError();
   if (e != hipSuccess)
     return set_error(QFT_ERR_HIP, std::string("compare launch: ") + hipGetErrorString(e));
   return QFT_OK;

@@ -178,6 +178,36 @@ void build_groups(PassLaunch &L, const PassGeom &g, int r, int n) {
       groups.push_back(gm);
     }
   }
+  // A multi-group pass whose last group holds the lowest output bits in
+  // registers (the last pass of a bit-reversed-order plan: its pass bit 0 is
+  // global bit 0) would have every lane of a store write to its own row of
+  // memory.  An exchange-only group then puts the lowest output bits on the
+  // lanes: registers on the r tile bits with the highest output positions,
+  // threads on the rest in output order.
+  auto lane_run = [&](const std::vector<int> &thr, const std::vector<int> &pos) {
+    int k = 0;
+    while (k < (int)thr.size() && pos[thr[k]] == k) ++k;  // global bits 0..k-1 on lanes
+    return k;
+  };
+  if (ng >= 2) {
+    std::vector<int> byout(T);
+    for (int q = 0; q < T; ++q) byout[q] = q;
+    std::stable_sort(byout.begin(), byout.end(),
+                     [&](int a, int b) { return outpos[a] < outpos[b]; });
+    const int run_st = lane_run(thr_orders.back(), outpos);
+    // lanes of the exchange-only group's map: the tile's lowest output bits
+    const int run_x = std::min(lane_run(byout, outpos), T - r);
+    if (run_st < 3 && run_x >= run_st + 2) {
+      GroupMap gm;
+      memset(&gm, 0, sizeof(gm));
+      for (int q = 0; q < r; ++q) pos_set(gm.reg_w, q, byout[T - r + q]);
+      for (int b = 0; b < T - r; ++b) pos_set(gm.thr_w, b, byout[b]);
+      gm.jbase = 0;
+      gm.nst = 0;
+      groups.push_back(gm);
+      d.lane_swap = 0;  // the group maps then go through LDS only
+    }
+  }
   d.ngroups = (int)groups.size();
   for (size_t i = 0; i < groups.size(); ++i) d.grp[i] = groups[i];
   for (int q = 0; q < T; ++q) pos_set(d.gpos_w, q, gpos[q]);
@@ -279,7 +309,7 @@ int plan_fused(HostPlan &p, std::string &err) {
   // three-or-four-pass choice account for it.
   auto wide_sizes = [&](int P) {
     const bool size_ok = p.c128 ? (n >= 26 && n <= 30) : (n >= 28 && n <= 30);
-    return size_ok && !p.bitrev && P == 3 && r_cfg == 5 &&
+    return size_ok && P == 3 && r_cfg == 5 &&
            T + 1 <= r_cfg + max_thread_bits(r_cfg, p.c128) && T + 1 <= kMaxTile;
   };
 
@@ -432,7 +462,10 @@ int plan_fused(HostPlan &p, std::string &err) {
           err = "pass_tile_log2 must lie between the pass's qubits and 15";
           return QFT_ERR_INVALID;
         }
-      } else if (wide_high && (i + 1 < P || ((size_t)p.elem_bytes << (T - g.m)) < 128)) {
+      } else if (wide_high &&
+                 (i + 1 < P || (!p.bitrev && ((size_t)p.elem_bytes << (T - g.m)) < 128))) {
+        // (a bit-reversing last pass with short rows; the last pass of a
+        // bit-reversed-order plan stores whole tiles in input order)
         Tq = T + 1;
       } else if (i == 0 && !p.c128 && P >= 3 && T - g.m < 4) {
         // The first pass reads rows 2^lo elements apart; with fewer than 4

@@ -46,13 +46,23 @@ struct qft_plan_s {
 };
 
 namespace qft {
+// The last pass of an execute that also compares its output with a
+// reference output `ref` (same layout), writing `part`: the per-wave
+// comparison partials (kCmpSlots doubles each) of that pass's tiles.
+struct FusedCompare {
+  const void *ref;
+  double *part;
+};
 // norm_out: device double receiving ||x||_2 of the input, or nullptr; part:
 // device buffer of norm_parts_for(p) partial sums (used when norm_out is set);
-// allow_timing: record the plan's per-launch timing events if it has them on
+// allow_timing: record the plan's per-launch timing events if it has them on;
+// cmp: compare in the last pass (fused schedule), or nullptr
 int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm_out,
-                 double *part, bool allow_timing);
+                 double *part, bool allow_timing, const FusedCompare *cmp = nullptr);
 // partial sums of |x|^2 an execute with the input norm needs for this plan
 uint32_t norm_parts_for(const qft_plan_s *p);
+// argument checks shared by the execute entry points (no device work)
+int check_execute(qft_plan_s *plan, void *dev_ptr, void *workspace);
 // drop cached batch launches that use this plan
 void batch_forget_plan(qft_plan_s *plan);
 // tuned configuration for a plan shape, if the tuning table has one

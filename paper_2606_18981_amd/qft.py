@@ -148,6 +148,8 @@ def _load():
         "qft_qubits_for": (I, [ctypes.c_size_t]),
         "qft_compare_workspace_bytes": (ctypes.c_size_t, [I]),
         "qft_compare": (I, [P, P, I, I, P, P, P]),
+        "qft_execute_compare_workspace_bytes": (ctypes.c_size_t, [P]),
+        "qft_execute_compare": (I, [P, P, P, P, P, P, P]),
         "qft_aqft_expected_error": (ctypes.c_double, [I, I]),
         "qft_select_cutoff": (I, [I, ctypes.c_double]),
         "qft_debug_pass_desc_size": (ctypes.c_size_t, []),
@@ -278,15 +280,28 @@ class Plan:
         if x.numel() != (1 << self.n):
             raise ValueError(f"tensor has {x.numel()} elements, plan needs {1 << self.n}")
 
-    def execute(self, x, stream=None, workspace=None, norm_out=None):
+    def execute(self, x, stream=None, workspace=None, norm_out=None, ref=None,
+                metrics_out=None, cmp_workspace=None):
         """In-place transform of the CUDA tensor x (complex64/128, 2^n elements).
         With norm_out (a float64 CUDA tensor), ||x||_2 of the input is written
-        to norm_out[0] by the same call (the paper's scale_in)."""
+        to norm_out[0] by the same call (the paper's scale_in).  With ref (a
+        tensor like x holding a reference output) and metrics_out (a float64
+        CUDA tensor of len(METRIC_NAMES)), the accuracy metrics of the output
+        against ref are written to metrics_out by the same call, the last
+        pass comparing the tiles it stores (qft_execute_compare); see
+        metrics_dict().  cmp_workspace: a CUDA tensor of at least
+        compare_workspace_bytes() bytes, else one kept by the plan."""
         self._check_tensor(x)
         if workspace is not None and \
                 workspace.numel() * workspace.element_size() < self.info.workspace_bytes:
             raise ValueError("workspace too small")
         ws = None if workspace is None else ctypes.c_void_p(workspace.data_ptr())
+        if ref is not None:
+            if norm_out is not None:
+                raise ValueError("norm_out and ref cannot be combined in one call")
+            return self._execute_compare(x, ref, metrics_out, ws, cmp_workspace, stream)
+        if metrics_out is not None:
+            raise ValueError("metrics_out needs ref")
         if norm_out is not None:
             import torch
             if not (norm_out.is_cuda and norm_out.dtype == torch.float64 and norm_out.numel() >= 1):
@@ -301,6 +316,35 @@ class Plan:
         _check(rc)
         return x
 
+    def compare_workspace_bytes(self) -> int:
+        """Device workspace an execute with a reference needs, in bytes."""
+        return int(lib.qft_execute_compare_workspace_bytes(self._h))
+
+    def _execute_compare(self, x, ref, metrics_out, ws, cmp_workspace, stream):
+        import torch
+        self._check_tensor(ref)
+        if metrics_out is None or not (metrics_out.is_cuda and metrics_out.dtype == torch.float64
+                                       and metrics_out.is_contiguous()
+                                       and metrics_out.numel() >= len(METRIC_NAMES)):
+            raise ValueError(f"metrics_out must be a contiguous float64 CUDA tensor of "
+                             f"{len(METRIC_NAMES)} elements")
+        nb = self.compare_workspace_bytes()
+        if cmp_workspace is None:
+            cw = getattr(self, "_cmp_ws", None)
+            if cw is None or cw.numel() * 8 < nb or cw.device != x.device:
+                cw = torch.empty(max(1, (nb + 7) // 8), dtype=torch.float64, device=x.device)
+                self._cmp_ws = cw
+            cmp_workspace = cw
+        elif not cmp_workspace.is_cuda or \
+                cmp_workspace.numel() * cmp_workspace.element_size() < nb:
+            raise ValueError("cmp_workspace too small")
+        _check(lib.qft_execute_compare(self._h, ctypes.c_void_p(x.data_ptr()), ws,
+                                       ctypes.c_void_p(ref.data_ptr()),
+                                       ctypes.c_void_p(cmp_workspace.data_ptr()),
+                                       ctypes.c_void_p(metrics_out.data_ptr()),
+                                       _stream_handle(stream)))
+        return x
+
     def set_timing(self, enable: bool = True):
         _check(lib.qft_plan_set_timing(self._h, int(bool(enable))))
 
@@ -313,6 +357,7 @@ class Plan:
         return list(buf), int(ex.value)
 
     def close(self):
+        self._cmp_ws = None
         if getattr(self, "_h", None) is not None and self._h.value:
             lib.qft_destroy(self._h)
             self._h = ctypes.c_void_p(0)
@@ -465,10 +510,11 @@ def select_cutoff(n: int, rel_l2_budget: float) -> int:
     return k
 
 
-def compare(y, ref, stream=None, workspace=None, out=None):
+def compare(y, ref, stream=None, workspace=None, out=None, as_dict=True):
     """Accuracy metrics of y against ref (CUDA tensors of one complex dtype and
     2^n elements), computed on the device in FP64.  Returns a dict; `out`
-    (a float64 CUDA tensor of 7 elements) receives the raw metrics."""
+    (a float64 CUDA tensor of 7 elements) receives the raw metrics.  With
+    as_dict=False, returns `out` without waiting for the device."""
     import torch
     if y.dtype != ref.dtype or y.numel() != ref.numel():
         raise ValueError("y and ref must have the same dtype and size")
@@ -487,7 +533,13 @@ def compare(y, ref, stream=None, workspace=None, out=None):
     _check(lib.qft_compare(ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(ref.data_ptr()), n, lay,
                            ctypes.c_void_p(workspace.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                            _stream_handle(stream)))
-    vals = out.cpu().tolist()
+    return metrics_dict(out) if as_dict else out
+
+
+def metrics_dict(out) -> dict:
+    """The metrics array of compare() or Plan.execute(ref=...) as a dict
+    (synchronises with the device to read it)."""
+    vals = out[: len(METRIC_NAMES)].cpu().tolist()
     d = dict(zip(METRIC_NAMES, vals))
     d["argmax"] = int(d["argmax"])
     return d

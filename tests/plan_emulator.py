@@ -44,6 +44,8 @@ class PassDesc(ctypes.Structure):
         ("gtab", ctypes.c_void_p),
         ("gtab1", ctypes.c_void_p),
         ("norm_part", ctypes.c_void_p),
+        ("cmp_ref", ctypes.c_void_p),
+        ("cmp_part", ctypes.c_void_p),
     ]
 
 

@@ -498,3 +498,48 @@ def test_emulated_three_group_passes(dtype, split):
     assert O.rel_l2(y, O.qft_fused_targets(x, 6, "unitary", "bitrev")) < tol
     y = E.emulate(x, n, -1, "none", dtype, "natural", cfg, inverse=True)
     assert O.rel_l2(y, O.qft_fused_targets(x, None, "none", "natural", inverse=True)) < tol
+
+
+# ---- the comparison folded into the last pass -------------------------------
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("order", ["natural", "bitrev"])
+@pytest.mark.parametrize("inverse", [False, True])
+def test_last_pass_can_take_the_comparison(dtype, order, inverse):
+    # qft_execute_compare compares in the last pass: that pass must have no
+    # below-pass diagonal (no controls lie below qubit 0) and must write the
+    # caller's array, for every default plan and for explicit splits
+    lay = Q.layout_flags(dtype, order, "fused", inverse)
+    cases = [(n, None) for n in range(1, 32)]
+    cases += [(sum(s), cfg) for s, cfg in (
+        ([7, 6, 11], dict(tile_log2=13, radix_log2=5, spec_log2=3, rev_spec_log2=3,
+                          pass_bits=[7, 6, 11])),
+        ([6, 10, 8], dict(tile_log2=13, radix_log2=5, spec_log2=3, rev_spec_log2=3,
+                          pass_bits=[6, 10, 8], pass_tile_log2=[14, 14, 14])),
+        ([6, 6], dict(tile_log2=10, radix_log2=3)))]
+    for n, cfg in cases:
+        if cfg and dtype == "c128" and cfg.get("pass_tile_log2"):
+            continue
+        for k in (-1, max(0, n // 3)):
+            info = Q.describe(n, k, "unitary", dtype, order, "fused", cfg, inverse=inverse)
+            last = info.num_passes - 1
+            assert info.pass_lo[last] == 0
+            d, launch = E.get_pass(n, k, "unitary", lay, cfg, last)
+            assert d.ext_tw == 0, (n, k, cfg)
+            assert launch[4] == 0, (n, k, cfg)  # out_ws
+            assert not d.cmp_ref and not d.cmp_part
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_bitrev_last_pass_stores_rows(dtype):
+    # the last pass of a bit-reversed-order plan writes in input order, and
+    # its pass bit 0 is global bit 0: its store map must still put the lowest
+    # global bits on the lanes (contiguous rows), through an exchange-only
+    # register group when the last radix group holds them in registers
+    lay = Q.layout_flags(dtype, "bitrev", "fused")
+    for n in range(14, 32):
+        info = Q.describe(n, -1, "unitary", dtype, "bitrev")
+        last = info.num_passes - 1
+        d, launch = E.get_pass(n, -1, "unitary", lay, None, last)
+        lanes = E.P(d.st_thr_w)[: d.T - d.r]
+        assert lanes[:3] == [0, 1, 2], (n, lanes)
