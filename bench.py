@@ -174,8 +174,11 @@ def bench_aqft(torch, Q, n, dtype, cutoffs, steps):
 
 def bench_budget(torch, Q, n, budgets, steps):
     """Cutoff picked by accuracy budget (closed-form expected error), then the
-    measured error against the exact transform of the same input, computed
-    on the device (qft_compare), and the runtime of the picked AQFT."""
+    measured error against the exact transform of the same input, taken on
+    the device by the transform's own last pass (Plan.execute with ref:
+    qft_execute_compare), and the runtime of the picked AQFT: alone, with
+    the metrics taken in its last pass, and followed by the separate
+    comparison pass (qft_compare) instead."""
     N = 1 << n
     x = torch.empty(N, dtype=torch.complex64, device="cuda")
     Q.fill_random(x, "gaussian", seed=1003)
@@ -183,20 +186,42 @@ def bench_budget(torch, Q, n, budgets, steps):
     plan = Q.Plan(n, -1, "unitary", "c64", "natural")
     plan.execute(exact)
     plan.close()
+    mo = torch.empty(len(Q.METRIC_NAMES), dtype=torch.float64, device="cuda")
+    ws = torch.empty(max(1, int(Q.lib.qft_compare_workspace_bytes(n)) // 8), dtype=torch.float64,
+                     device="cuda")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(steps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / steps
+
     rows = []
     for budget in budgets:
         k = Q.select_cutoff(n, budget)
         plan = Q.Plan(n, k, "unitary", "c64", "natural")
         y = x.clone()
-        plan.execute(y)
-        m = Q.compare(y, exact)
+        plan.execute(y, ref=exact, metrics_out=mo)
+        m = Q.metrics_dict(mo)
+        sep = Q.compare(y, exact, workspace=ws)  # the same output, the separate pass
         ms = time_plan(torch, Q, plan, y, steps, 2)  # (transforms y in place)
+        ms_fused = timed(lambda: plan.execute(y, ref=exact, metrics_out=mo))
+        ms_sep = timed(lambda: (plan.execute(y),
+                                Q.compare(y, exact, workspace=ws, out=mo, as_dict=False)))
         del y
         rows.append({"budget": budget, "cutoff": k, "predicted_rel_l2": Q.expected_error(n, k),
                      "measured_rel_l2": m["rel_l2"], "fidelity": m["fidelity"],
-                     "ms": ms, "gates_cr": plan.info.gates_cr})
+                     "leakage": m["leakage"], "max_err": m["max_err"],
+                     "separate_pass_rel_l2": sep["rel_l2"],
+                     "ms": ms, "ms_with_metrics_in_last_pass": ms_fused,
+                     "ms_then_separate_compare": ms_sep, "gates_cr": plan.info.gates_cr})
         plan.close()
-    del x, exact
+    del x, exact, ws
     torch.cuda.empty_cache()
     return rows
 
