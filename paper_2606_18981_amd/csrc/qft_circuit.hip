@@ -31,6 +31,7 @@ constexpr int kMaxTileC128 = 12;  // 2^12 complex128 = 64 KiB of LDS (plus paddi
 constexpr int kLowBits = 6;       // tile positions [0, 6) index the low tables
 constexpr int32_t kNoControl = 0x7fffffff;
 constexpr int kChunk = 8;  // elements a thread scales per read of a diagonal record
+constexpr int kLoadBatch = 16;  // tile loads a thread has in flight at once
 
 // Per element type: high tile bits (T - 6), stage size (tile positions whose
 // 2^K elements a thread holds in registers) and diagonal-run tables per stage.
@@ -73,6 +74,15 @@ struct GateRec {
 // position other than hx).  The tables are built per tile.
 enum OpKind : int32_t { kOpPair = 0, kOpDiag = 2, kOpStage = 3 };
 
+// Pair-operation flags.  kRealMatrix: the 2x2 matrix is real (H, X, Z,
+// rotations about Y, ...), two real multiply-adds per output component
+// instead of four.  kAnchoredRun: every record of the run that follows the
+// pair involves the pair's target and scales only amplitudes where all its
+// qubits are 1 (controlled phases onto the target, phase gates on it), so the
+// run's factor is 1 wherever the target bit is 0 and those elements are
+// skipped.
+enum OpFlags : int32_t { kRealMatrix = 1, kAnchoredRun = 2 };
+
 template <typename Real>
 struct DevOp {
   int32_t kind;
@@ -85,7 +95,9 @@ struct DevOp {
                              // (stage: nlo = number of runs)
   int32_t hx;      // run: high tile position that extends the low table, or -1
   int32_t slot;    // pair: table slot of its run
-  int32_t pad[3];
+  int32_t flags;   // pair: kRealMatrix, kAnchoredRun
+  int32_t apos;    // pair with kAnchoredRun: tile position of its target
+  int32_t pad;
   c2<Real> u[4];   // pair: row-major 2x2
 };
 
@@ -158,21 +170,29 @@ __device__ __forceinline__ void build_tables(const DevOp<Real> &op, const DevDia
   using C = c2<Real>;
   const uint32_t mlo = (1u << TL) - 1u;
   const int hx = op.hx;
+  // an anchored run's factor is 1 wherever its anchor bit is 0
+  const int ap = (op.kind == kOpPair && (op.flags & kAnchoredRun)) ? op.apos : -1;
   if (tid < 128u) {
     if (tid <= mlo || (hx >= 0 && tid <= 2u * mlo + 1u)) {
       const uint32_t e = (tid & mlo) | (hx >= 0 ? ((tid >> TL) & 1u) << hx : 0u);
       C f{(Real)1, (Real)0};
-      const int r1 = op.r0 + op.nlo;
+      const bool skip = ap >= 0 && (ap < TL || ap == hx) && ((e >> ap) & 1u) == 0u;
+      if (!skip) {
+        const int r1 = op.r0 + op.nlo;
 #pragma unroll 4
-      for (int r = op.r0; r < r1; ++r) f = cmul2(f, diag_factor(recs[r], e, base));
+        for (int r = op.r0; r < r1; ++r) f = cmul2(f, diag_factor(recs[r], e, base));
+      }
       tb.lo[tid] = f;
     }
   } else if (tid - 128u < (1u << TH)) {
     const uint32_t j = tid - 128u;
     C f{(Real)1, (Real)0};
-    const int r1 = op.r0 + op.nlo, r2 = r1 + op.nhi;
+    const bool skip = ap >= TL && ((j >> (ap - TL)) & 1u) == 0u;
+    if (!skip) {
+      const int r1 = op.r0 + op.nlo, r2 = r1 + op.nhi;
 #pragma unroll 4
-    for (int r = r1; r < r2; ++r) f = cmul2(f, diag_factor(recs[r], j << TL, base));
+      for (int r = r1; r < r2; ++r) f = cmul2(f, diag_factor(recs[r], j << TL, base));
+    }
     tb.hi[j] = f;
   }
 }
@@ -202,6 +222,26 @@ __device__ __forceinline__ void stage_pair(c2<Real> (&v)[1 << K], uint32_t eb,
     const C a = v[c], b = v[c1];
     const C na = cadd2(cmul2(u0, a), cmul2(u1, b));
     const C nb = cadd2(cmul2(u2, a), cmul2(u3, b));
+    v[c] = take ? na : a;
+    v[c1] = take ? nb : b;
+  }
+}
+
+// The same for a real matrix (u0..u3 the real parts).
+template <typename Real, int K, int J>
+__device__ __forceinline__ void stage_pair_real(c2<Real> (&v)[1 << K], uint32_t eb,
+                                                const uint32_t (&off)[1 << K], int cq,
+                                                uint64_t base, Real u0, Real u1, Real u2,
+                                                Real u3) {
+  using C = c2<Real>;
+#pragma unroll
+  for (int c = 0; c < (1 << K); ++c) {
+    if (c & (1 << J)) continue;
+    const int c1 = c | (1 << J);
+    const bool take = cq == kNoControl || qbit(cq, eb | off[c], base);
+    const C a = v[c], b = v[c1];
+    const C na{u0 * a.x + u1 * b.x, u0 * a.y + u1 * b.y};
+    const C nb{u2 * a.x + u3 * b.x, u2 * a.y + u3 * b.y};
     v[c] = take ? na : a;
     v[c1] = take ? nb : b;
   }
@@ -239,24 +279,41 @@ __device__ __forceinline__ void stage_sweep(c2<Real> *lds, const DevOp<Real> *so
       const DevOp<Real> &op = sops[oi];
       const C u0 = op.u[0], u1 = op.u[1], u2 = op.u[2], u3 = op.u[3];
       const int cq = op.b;
-      switch (op.a) {
-        case 0: stage_pair<Real, K, 0>(v, eb, off, cq, base, u0, u1, u2, u3); break;
-        case 1: if constexpr (K > 1) stage_pair<Real, K, 1>(v, eb, off, cq, base, u0, u1, u2, u3); break;
-        case 2: if constexpr (K > 2) stage_pair<Real, K, 2>(v, eb, off, cq, base, u0, u1, u2, u3); break;
-        case 3: if constexpr (K > 3) stage_pair<Real, K, 3>(v, eb, off, cq, base, u0, u1, u2, u3); break;
-        case 4: if constexpr (K > 4) stage_pair<Real, K, 4>(v, eb, off, cq, base, u0, u1, u2, u3); break;
-        default: break;
+      const int J = op.a;
+      if (op.flags & kRealMatrix) {
+        switch (J) {
+          case 0: stage_pair_real<Real, K, 0>(v, eb, off, cq, base, u0.x, u1.x, u2.x, u3.x); break;
+          case 1: if constexpr (K > 1) stage_pair_real<Real, K, 1>(v, eb, off, cq, base, u0.x, u1.x, u2.x, u3.x); break;
+          case 2: if constexpr (K > 2) stage_pair_real<Real, K, 2>(v, eb, off, cq, base, u0.x, u1.x, u2.x, u3.x); break;
+          case 3: if constexpr (K > 3) stage_pair_real<Real, K, 3>(v, eb, off, cq, base, u0.x, u1.x, u2.x, u3.x); break;
+          case 4: if constexpr (K > 4) stage_pair_real<Real, K, 4>(v, eb, off, cq, base, u0.x, u1.x, u2.x, u3.x); break;
+          default: break;
+        }
+      } else {
+        switch (J) {
+          case 0: stage_pair<Real, K, 0>(v, eb, off, cq, base, u0, u1, u2, u3); break;
+          case 1: if constexpr (K > 1) stage_pair<Real, K, 1>(v, eb, off, cq, base, u0, u1, u2, u3); break;
+          case 2: if constexpr (K > 2) stage_pair<Real, K, 2>(v, eb, off, cq, base, u0, u1, u2, u3); break;
+          case 3: if constexpr (K > 3) stage_pair<Real, K, 3>(v, eb, off, cq, base, u0, u1, u2, u3); break;
+          case 4: if constexpr (K > 4) stage_pair<Real, K, 4>(v, eb, off, cq, base, u0, u1, u2, u3); break;
+          default: break;
+        }
       }
       if (op.nlo + op.nhi + op.ncross > 0) {
         const RunTables<Real> &tb = tabs[op.slot];
         const int hx = op.hx;
+        // an anchored run leaves the elements whose target bit is 0 alone
+        const uint32_t keep = (op.flags & kAnchoredRun) ? 1u << J : 0u;
 #pragma unroll
-        for (int c = 0; c < R; ++c) v[c] = cmul2(table_factor<Real>(tb, eb | off[c], TL, hx), v[c]);
+        for (int c = 0; c < R; ++c)
+          if (keep == 0u || (c & keep))
+            v[c] = cmul2(table_factor<Real>(tb, eb | off[c], TL, hx), v[c]);
         const int rc0 = op.r0 + op.nlo + op.nhi, rc1 = rc0 + op.ncross;
         for (int r = rc0; r < rc1; ++r) {
           const DevDiag<Real> rec = recs[r];
 #pragma unroll
-          for (int c = 0; c < R; ++c) v[c] = cmul2(diag_factor(rec, eb | off[c], base), v[c]);
+          for (int c = 0; c < R; ++c)
+            if (keep == 0u || (c & keep)) v[c] = cmul2(diag_factor(rec, eb | off[c], base), v[c]);
         }
       }
     }
@@ -270,8 +327,13 @@ __device__ __forceinline__ void stage_sweep(c2<Real> *lds, const DevOp<Real> *so
 // pass's operations in order (stages in registers, lone diagonal runs as LDS
 // sweeps), one barrier after each, and store the tile through the pass's
 // relabelling of tile positions (its swaps).
-template <typename Real>
-__global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d, c2<Real> *psi) {
+// (Two waves per SIMD: the LDS of two workgroups fits a CU, and the
+// register budget of two waves is what the stage code needs.)
+// FULL: every stage has Shape::kStageBits positions (tiles of at least that
+// many bits); otherwise stages of 1..kStageBits positions.
+template <typename Real, bool FULL>
+__global__ void __launch_bounds__(kCircThreads) __attribute__((amdgpu_waves_per_eu(2)))
+k_circuit_pass(const CircPass d, c2<Real> *psi) {
   using C = c2<Real>;
   using S = Shape<Real>;
   extern __shared__ __align__(16) unsigned char circ_smem[];
@@ -316,7 +378,20 @@ __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d,
   }
   __syncthreads();
   const uint32_t TE = 1u << d.T;
-  for (uint32_t e = tid; e < TE; e += kCircThreads) lds[lidx(e)] = psi[alo[e & mlo] | ahi[e >> TL]];
+  // the tile's loads, kLoadBatch per thread in flight before any LDS write
+  for (uint32_t e0 = tid; e0 < TE; e0 += kLoadBatch * kCircThreads) {
+    C t[kLoadBatch];
+#pragma unroll
+    for (int i = 0; i < kLoadBatch; ++i) {
+      const uint32_t e = e0 + i * kCircThreads;
+      if (e < TE) t[i] = psi[alo[e & mlo] | ahi[e >> TL]];
+    }
+#pragma unroll
+    for (int i = 0; i < kLoadBatch; ++i) {
+      const uint32_t e = e0 + i * kCircThreads;
+      if (e < TE) lds[lidx(e)] = t[i];
+    }
+  }
   __syncthreads();
   int oi = 0;
   while (oi < d.nops) {
@@ -333,7 +408,10 @@ __global__ void __launch_bounds__(kCircThreads) k_circuit_pass(const CircPass d,
         __syncthreads();
       }
       const uint32_t packed = (uint32_t)op.r0;
-      switch (op.b) {
+      if constexpr (FULL) {
+        stage_sweep<Real, S::kStageBits>(lds, ops + oi + 1, cnt, packed, tabs, recs, base, TL,
+                                         TE, tid);
+      } else switch (op.b) {
         case 1: stage_sweep<Real, 1>(lds, ops + oi + 1, cnt, packed, tabs, recs, base, TL, TE, tid); break;
         case 2: stage_sweep<Real, 2>(lds, ops + oi + 1, cnt, packed, tabs, recs, base, TL, TE, tid); break;
         case 3: stage_sweep<Real, 3>(lds, ops + oi + 1, cnt, packed, tabs, recs, base, TL, TE, tid); break;
@@ -514,6 +592,27 @@ void build_pass_image(const qft_circuit_s *c, int g0, int g1, const std::vector<
       img.ops.push_back(op);
     }
     DevOp<Real> &op = img.ops.back();
+    if (attach) {
+      // anchored: every record involves the pair's target and scales only
+      // amplitudes whose qubits are all 1
+      const int32_t pos = op.a;
+      const c2<Real> one{(Real)1, (Real)0};
+      auto is_one = [&](const c2<Real> &z) { return z.x == one.x && z.y == one.y; };
+      bool anchored = true;
+      for (const DevDiag<Real> &r : run) {
+        const bool ok = r.q1 == r.q0 ? (r.q0 == pos && is_one(r.D[0]))
+                                     : ((r.q1 == pos || r.q0 == pos) && is_one(r.D[0]) &&
+                                        is_one(r.D[1]) && is_one(r.D[2]));
+        if (!ok) {
+          anchored = false;
+          break;
+        }
+      }
+      if (anchored) {
+        op.flags |= kAnchoredRun;
+        op.apos = pos;
+      }
+    }
     op.r0 = (int32_t)img.recs.size();
     op.nlo = (int32_t)lo.size();
     op.nhi = (int32_t)hi.size();
@@ -559,6 +658,7 @@ void build_pass_image(const qft_circuit_s *c, int g0, int g1, const std::vector<
     op.a = lab[tpos[g.kind == kOne ? g.a : g.b]];
     op.b = g.kind == kOne ? kNoControl : enc(g.a);
     for (int j = 0; j < 4; ++j) op.u[j] = cval<Real>(g.u, j);
+    if (g.u[1] == 0.0 && g.u[3] == 0.0 && g.u[5] == 0.0 && g.u[7] == 0.0) op.flags |= kRealMatrix;
     img.ops.push_back(op);
   }
   flush();
@@ -574,8 +674,13 @@ void build_pass_image(const qft_circuit_s *c, int g0, int g1, const std::vector<
 // the stage's table slots.  Each stage is a header followed by its pair
 // operations, whose targets become indices into the stage's (ascending)
 // positions.
+//
+// With T >= kStageBits every stage is padded to kStageBits positions with the
+// highest tile positions it does not use (the extra positions only make each
+// thread's sub-cube larger), so that the kernel needs one stage size only:
+// its code then stays small enough for the instruction cache.
 template <typename Real>
-void form_stages(PassImage<Real> &img) {
+void form_stages(PassImage<Real> &img, int T) {
   const int kmax = Shape<Real>::kStageBits, slots = Shape<Real>::kSlots;
   std::vector<DevOp<Real>> out;
   size_t i = 0;
@@ -597,6 +702,8 @@ void form_stages(PassImage<Real> &img) {
       if (run) ++runs;
       ++j;
     }
+    for (int q = T - 1; q >= 0 && T >= kmax && (int)S.size() < kmax; --q)
+      if (std::find(S.begin(), S.end(), q) == S.end()) S.push_back(q);
     std::sort(S.begin(), S.end());
     DevOp<Real> h;
     memset(&h, 0, sizeof(h));
@@ -719,12 +826,12 @@ int compile(qft_circuit_s *c, int tile_qubits, bool upload) {
     if (c->c128) {
       img64.emplace_back();
       build_pass_image<double>(c, runs[r].first, runs[r].second, tpos, p.TL, img64.back(), p);
-      form_stages<double>(img64.back());
+      form_stages<double>(img64.back(), p.T);
       p.nops = (int)img64.back().ops.size();
     } else {
       img32.emplace_back();
       build_pass_image<float>(c, runs[r].first, runs[r].second, tpos, p.TL, img32.back(), p);
-      form_stages<float>(img32.back());
+      form_stages<float>(img32.back(), p.T);
       p.nops = (int)img32.back().ops.size();
     }
     c->passes.push_back(p);
@@ -752,13 +859,14 @@ size_t circuit_lds_bytes(int T) {
 template <typename Real>
 hipError_t launch_circuit_pass(const CircPass &p, void *dev_ptr, hipStream_t s) {
   const size_t lds = circuit_lds_bytes<Real>(p.T);
+  auto fn = p.T >= Shape<Real>::kStageBits ? k_circuit_pass<Real, true>
+                                           : k_circuit_pass<Real, false>;
   if (lds > 65536) {
-    hipError_t e = ensure_lds_limit(reinterpret_cast<const void *>(&k_circuit_pass<Real>),
+    hipError_t e = ensure_lds_limit(reinterpret_cast<const void *>(fn),
                                     (int)circuit_lds_bytes<Real>(kMaxTile<Real>()));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_circuit_pass<Real>, dim3(p.ntiles), dim3(kCircThreads), lds, s, p,
-                     (c2<Real> *)dev_ptr);
+  hipLaunchKernelGGL(fn, dim3(p.ntiles), dim3(kCircThreads), lds, s, p, (c2<Real> *)dev_ptr);
   return hipGetLastError();
 }
 
