@@ -121,15 +121,18 @@ def pass_kernel_name(info, p, dtype):
     st = "true" if info.pass_streaming[p] else "false"
     r = info.config.radix_log2
     threads = 1 << (info.pass_bits[p] + info.pass_spec[p] - r)
-    wide = dtype == "c64" and threads == 512  # the four-wave form
+    # the lean (four-wave) form: 512-thread complex64, 256-thread complex128
+    wide = threads == (512 if dtype == "c64" else 256)
     if 1 <= sh <= 10:
         nst, ext = (sh - 1) % 5 + 1, "true" if sh > 5 else "false"
-        return (f"k_fused_pass2w<float, 5, {nst}, {ext}, {st}>" if wide
+        return (f"k_fused_pass2w<{real}, 5, {nst}, {ext}, {st}>" if wide
                 else f"k_fused_pass2<{real}, 5, {nst}, {ext}, {st}>")
-    if sh >= 11:
+    if 11 <= sh <= 16:
         s, ext = (sh - 11) % 3 + 1, "true" if sh >= 14 else "false"
-        return (f"k_fused_pass3w<float, {s}, {ext}, {st}>" if wide
+        return (f"k_fused_pass3w<{real}, {s}, {ext}, {st}>" if wide
                 else f"k_fused_pass3<{real}, {s}, {ext}, {st}>")
+    if sh >= 17:
+        return f"k_fused_pass2x<{real}, {sh - 16}, {st}>"
     return f"k_fused_pass<{real}, {r}>"
 
 

@@ -146,7 +146,11 @@ typedef struct qft_plan_info {
                                        (stages of the last group - 1);
                                        11..16: the compile-time three-group
                                        kernel, 11 + 3 * (below-pass
-                                       diagonal) + (qubits - 11)             */
+                                       diagonal) + (qubits - 11);
+                                       17..21: the two-group kernel with a
+                                       store exchange (the last pass of a
+                                       bit-reversed-order plan), 16 + (stages
+                                       of the last group)                    */
   int pass_streaming[QFT_MAX_PASSES]; /* pass p uses non-temporal access    */
   qft_config_t config;
   long long gates_h, gates_cr, gates_swap;

@@ -145,13 +145,30 @@ inline int pass3_shape(const PassLaunch &L) {
   return three ? 1 + (d.ext_tw ? 3 : 0) + (s - 1) : 0;
 }
 
+// 0, or nst (1..5) for a last pass with the two-group shape whose stores go
+// through a third, exchange-only register group (the last pass of a
+// bit-reversed-order plan, which holds the lowest output bits in registers
+// for its final stages), with no below-pass diagonal and a full-tile LDS
+// area of at most 64 KiB.
+inline int pass2x_shape(const PassLaunch &L) {
+  const PassDesc &d = L.d;
+  const bool ok = d.r == 5 && d.ngroups == 3 && !d.ext_tw && d.grp[0].nst == d.r &&
+                  d.grp[0].jbase > 0 && d.grp[1].jbase == 0 && d.grp[1].nst >= 1 &&
+                  d.grp[1].nst <= d.r && d.grp[2].nst == 0 && d.lane_swap == 0 &&
+                  L.threads == (1 << (d.T - d.r)) && L.lds_bytes <= 65536;
+  return ok ? d.grp[1].nst : 0;
+}
+
 // Kernel of a pass: 0 generic, 1..10 the two-group kernel (pass2_shape),
-// 11..16 the three-group kernel (10 + pass3_shape).
+// 11..16 the three-group kernel (10 + pass3_shape), 17..21 the two-group
+// kernel with the store exchange (16 + pass2x_shape).
 inline int pass_kernel_shape(const PassLaunch &L) {
   const int two = pass2_shape(L);
   if (two) return two;
   const int three = pass3_shape(L);
-  return three ? 10 + three : 0;
+  if (three) return 10 + three;
+  const int twox = pass2x_shape(L);
+  return twox ? 16 + twox : 0;
 }
 
 // The lean (four-wave) form of the compile-time kernels runs every

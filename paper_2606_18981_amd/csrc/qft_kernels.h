@@ -51,7 +51,8 @@ hipError_t launch_batch_group(bool c128, const BatchGroup &g, hipStream_t s);
 // Kernel of a pass (pass_kernel_shape): 0 for the generic pass kernel;
 // 1..10 for the compile-time two-group kernel (radix 32, the first group
 // full, the last holding pass bit 0); 11..16 for the compile-time
-// three-group kernel (the last group reached by cross-lane swaps).
+// three-group kernel (the last group reached by cross-lane swaps); 17..21
+// for the two-group kernel that stores through an exchange-only third group.
 int fused_pass_shape(const PassLaunch &L);
 
 // Gate-by-gate sweeps (unfused circuit, Fig. 1).

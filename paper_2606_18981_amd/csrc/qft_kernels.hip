@@ -55,6 +55,17 @@ k_fused_pass2(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
                                       reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x);
 }
 
+// The last pass of a bit-reversed-order plan: the two-group shape, then the
+// exchange-only group that puts the lowest output bits on the lanes.
+template <typename Real, int NSTL, bool NT>
+__global__ void __launch_bounds__(sizeof(Real) == 8 ? 256 : 512)
+k_fused_pass2x(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
+  extern __shared__ __align__(16) unsigned char qft_smem[];
+  const uint32_t tile = pass_tile_index(d);
+  pass2_tile<Real, 5, NSTL, false, NT, false, false, true>(
+      d, tile, in, out, reinterpret_cast<cplx<Real> *>(qft_smem), threadIdx.x);
+}
+
 template <typename Real, int S, bool EXT, bool NT>
 __global__ void __launch_bounds__(sizeof(Real) == 8 ? 256 : 512)
 k_fused_pass3(const PassDesc d, const cplx<Real> *in, cplx<Real> *out) {
@@ -92,7 +103,15 @@ static hipError_t launch_pass_t(const PassLaunch &L, const void *in, void *out, 
   auto fn = k_fused_pass<Real, RB>;
   if constexpr (RB == 5) {
     const int shape = fused_pass_shape(L);
-    if (shape > 10) {
+    if (shape > 16) {
+      using K = void (*)(const PassDesc, const cplx<Real> *, cplx<Real> *);
+#define QFT_P2X(N)                                                                          \
+  {k_fused_pass2x<Real, 1, N>, k_fused_pass2x<Real, 2, N>, k_fused_pass2x<Real, 3, N>,      \
+   k_fused_pass2x<Real, 4, N>, k_fused_pass2x<Real, 5, N>}
+      static const K tabx[2][5] = {QFT_P2X(false), QFT_P2X(true)};
+#undef QFT_P2X
+      fn = tabx[L.d.nt ? 1 : 0][shape - 17];
+    } else if (shape > 10) {
       using K = void (*)(const PassDesc, const cplx<Real> *, cplx<Real> *);
 #define QFT_P3(E, N) \
   {k_fused_pass3<Real, 1, E, N>, k_fused_pass3<Real, 2, E, N>, k_fused_pass3<Real, 3, E, N>}
@@ -282,7 +301,10 @@ template <typename Real, int RB>
 static hipError_t launch_group_t(const BatchGroup &g, hipStream_t s) {
   auto fn = k_batch_group<Real, RB>;
   if constexpr (RB == 5) {
-    if (g.shape > 10) {
+    if (g.shape > 16) {
+      // the store-exchange shape: the generic kernel (its tile's full LDS
+      // area is what the plan allots)
+    } else if (g.shape > 10) {
       using K = void (*)(const BatchSeg *, int, const PassDesc *, const BatchIO *);
       static const K tab3[6] = {k_batch_group3<Real, 1, false>, k_batch_group3<Real, 2, false>,
                                 k_batch_group3<Real, 3, false>, k_batch_group3<Real, 1, true>,

@@ -201,7 +201,9 @@ hipError_t launch_cmp_t(const PassLaunch &L, const void *in, void *out, hipStrea
     const int shape = pass_kernel_shape(L);
     const bool lean = lean_form(L, sizeof(Real) == 8);
     const int nt = L.d.nt ? 1 : 0;
-    if (shape > 10) {
+    if (shape > 16) {
+      // the store-exchange shape: the generic kernel (full-tile LDS)
+    } else if (shape > 10) {
       static const K tab3[2][3] = {
           {k_fused_pass3_cmp<Real, 1, false>, k_fused_pass3_cmp<Real, 2, false>,
            k_fused_pass3_cmp<Real, 3, false>},

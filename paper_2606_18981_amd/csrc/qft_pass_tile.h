@@ -687,7 +687,10 @@ __device__ __forceinline__ void tile_body(const PassDesc &d, uint32_t tile, cons
 // the below-pass diagonal's table entries are issued after the exchange and
 // the factors are applied in two steps, so that fewer registers are live.
 // CMP: also compare the stored tile with d.cmp_ref (store_compare_tile).
-template <typename Real, int RB, int NSTL, bool EXT, bool NT, bool W4 = false, bool CMP = false>
+// OX: store through the exchange-only third group (pass2x_shape), through
+// the full-tile LDS area.
+template <typename Real, int RB, int NSTL, bool EXT, bool NT, bool W4 = false, bool CMP = false,
+          bool OX = false>
 __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, const cplx<Real> *in,
                                            cplx<Real> *out, cplx<Real> *lds, uint32_t tid) {
   using C = cplx<Real>;
@@ -727,7 +730,7 @@ __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, con
   // (four-wave form: keep the exchange's LDS addresses from being computed
   // early, where they would be live across the network and spill)
   if constexpr (W4) __builtin_amdgcn_sched_barrier(0);
-  if constexpr (sizeof(Real) == 4 || W4) {
+  if constexpr ((sizeof(Real) == 4 || W4) && !OX) {
     exchange_split<Real, RB, W4>(v, lds, d.grp[0], d.grp[1], tid, TR);  // half-tile LDS
   } else {
     exchange<Real, RB>(v, lds, d.grp[0], d.grp[1], tid, TR, true);
@@ -754,6 +757,7 @@ __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, con
     }
   }
   conj_if<RB>(v, d.conj_out != 0);
+  if constexpr (OX) exchange<Real, RB>(v, lds, d.grp[1], d.grp[2], tid, TR, true);
   const uint32_t obase = d.reverse ? rev_bits(base, d.n) : base;
   if constexpr (CMP)
     store_compare_tile<Real, RB, NT, kCmpPre, W4 ? 1 : 2>(d, v, rv, out, obase | st_thr, tile,

@@ -273,7 +273,7 @@ void build_group_tables(HostPlan &p) {
   p.off_gtab1.assign(p.passes.size(), 0);
   for (size_t i = 0; i < p.passes.size(); ++i) {
     const PassLaunch &L = p.passes[i];
-    if (pass2_shape(L)) {
+    if (pass2_shape(L) || pass2x_shape(L)) {
       p.off_gtab[i] = add_group_table(p, L, L.d.grp[0]);
     } else if (pass3_shape(L)) {
       p.off_gtab[i] = add_group_table(p, L, L.d.grp[0]);

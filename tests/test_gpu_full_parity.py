@@ -160,3 +160,62 @@ def test_default_splits_whole_vector(torch_cuda, Q, n):
         check_parity(y, ref, dtype, f"n={n} {dtype} default split")
         del y
     torch.cuda.empty_cache()
+
+
+def _bitrev_index(torch, n):
+    k = torch.arange(1 << n, device="cuda", dtype=torch.int64)
+    r = torch.zeros_like(k)
+    for b in range(n):
+        r |= ((k >> b) & 1) << (n - 1 - b)
+    return r
+
+
+@pytest.mark.timeout(300)
+def test_bitrev_order_large(torch_cuda, Q):
+    """Bit-reversed-order plans at the sizes where their last pass stores
+    through an exchange-only register group and their high passes take the
+    wider tiles.  n = 24: whole vector against the oracle, both element
+    types.  n = 28 (complex64) and 27 (complex128): against the natural-order
+    output of the same input read in bit-reversed order (the natural-order
+    plans are pinned to the oracle above), to the same bars."""
+    torch = torch_cuda
+    n = 24
+    x = I.gaussian(n, 2600)
+    print(f"[oracle] n={n} whole vector (bit-reversed order)", flush=True)
+    ref = O.qft_state_c(x)
+    rev = _bitrev_index(torch, n).cpu().numpy()
+    ref_br = np.empty_like(ref)
+    ref_br[rev] = ref
+    for dtype in ("c64", "c128"):
+        print(f"[gpu] n={n} {dtype} bitrev", flush=True)
+        plan = Q.Plan(n, -1, "unitary", dtype, "bitrev")
+        t = torch.from_numpy(x.astype(np.complex64 if dtype == "c64" else np.complex128)).cuda()
+        plan.execute(t)
+        y = t.cpu().numpy()
+        plan.close()
+        check_parity(y, ref_br, dtype, f"n={n} {dtype} bitrev")
+    for n, dtype in ((28, "c64"), (27, "c128")):
+        print(f"[gpu] n={n} {dtype} bitrev against natural", flush=True)
+        tdt = torch.complex64 if dtype == "c64" else torch.complex128
+        xd = torch.empty(1 << n, dtype=tdt, device="cuda")
+        Q.fill_random(xd, "gaussian", seed=2700 + n, stream_id=0)
+        outs = {}
+        for order in ("natural", "bitrev"):
+            plan = Q.Plan(n, -1, "unitary", dtype, order)
+            t = xd.clone()
+            plan.execute(t)
+            plan.close()
+            outs[order] = t
+        r = _bitrev_index(torch, n)
+        a = outs["bitrev"][r].to(torch.complex128)
+        b = outs["natural"].to(torch.complex128)
+        del r, outs
+        d = a - b
+        rel = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(b))
+        rms = float(torch.linalg.vector_norm(b)) / 2.0 ** (n / 2)
+        mx = float(d.abs().max()) / rms
+        print(f"[parity] n={n} {dtype} bitrev vs natural: rel_l2={rel:.3e} max_err={mx:.3e}",
+              flush=True)
+        assert rel <= TOL[dtype] and mx <= TOL[dtype]
+        del a, b, d, xd
+        torch.cuda.empty_cache()

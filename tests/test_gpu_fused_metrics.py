@@ -5,8 +5,8 @@ functions) on the same output and reference, over every kind of last pass:
 the generic kernel (tiles smaller than a wave, radix below 32), the
 two-group and three-group compile-time kernels, their four-wave forms,
 inverse transforms (conjugation on store), bit-reversed output (whose last
-pass stores through an exchange-only register group), the AQFT, and the
-gate schedule.
+pass stores through an exchange-only register group: the generic kernel
+takes the comparison there), the AQFT, and the gate schedule.
 
 Bars: the output must equal a plain execute's bit for bit (the comparison
 only reads); the sums-based metrics agree with qft_compare's to 1e-12
@@ -107,7 +107,8 @@ CASES = [
     (13, -1, "c128", "bitrev", False, "fused", dict(tile_log2=9, radix_log2=4), "generic"),
     (16, 6, "c64", "natural", False, "fused", None, "two"),
     (16, -1, "c128", "natural", True, "fused", None, "two"),
-    (16, -1, "c128", "bitrev", True, "fused", None, "generic"),  # + store exchange
+    (16, -1, "c128", "bitrev", True, "fused", None, "two-x"),
+    (20, 5, "c64", "bitrev", False, "fused", None, "two-x"),
     (20, -1, "c64", "natural", True, "fused", None, "two"),
     (24, 8, "c64", "natural", False, "fused", cfg("c64", [7, 6, 11]), "three"),
     (24, -1, "c64", "natural", True, "fused", cfg("c64", [7, 6, 11]), "three"),
@@ -128,6 +129,8 @@ def last_kernel_kind(Q, plan, dtype, config):
     kern = info.pass_kernel[info.num_passes - 1]
     if kern == 0:
         return "generic"
+    if kern >= 17:
+        return "two-x"  # with the store exchange (a bit-reversed-order last pass)
     kind = "three" if kern > 10 else "two"
     tiles = (config or {}).get("pass_tile_log2")
     if tiles and tiles[-1] == (14 if dtype == "c64" else 13):

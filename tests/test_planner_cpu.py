@@ -390,8 +390,9 @@ def test_wide_high_pass_tiles():
     elements give every pass below which other qubits lie one more tile bit
     (2^14 complex64 tiles of 512 threads, 2^13 complex128 of 256: the lean
     kernels), and the last pass too where its rows would otherwise be
-    shorter than 128 bytes; other sizes and bit-reversed plans keep 2^13
-    (complex128 2^12)."""
+    shorter than 128 bytes; other sizes keep 2^13 (complex128 2^12).
+    Bit-reversed-order plans widen their high passes only: their last pass
+    stores whole tiles in input order."""
     lay = Q.layout_flags("c64")
     expect = {28: [14, 14, 13], 29: [14, 14, 13], 30: [14, 14, 14]}
     for n, tiles in expect.items():
@@ -412,9 +413,10 @@ def test_wide_high_pass_tiles():
             d, launch = E.get_pass(n, -1, "unitary", Q.layout_flags("c128"), None, p)
             assert d.T == tiles[p], (n, p)
             assert launch[0] == 1 << (tiles[p] - 5)
-    for p in range(3):
-        d, _ = E.get_pass(28, -1, "unitary", Q.layout_flags("c64", "bitrev"), None, p)
-        assert d.T == 13
+    for n, tiles in {28: [14, 14, 13], 30: [14, 14, 13]}.items():
+        for p in range(3):
+            d, _ = E.get_pass(n, -1, "unitary", Q.layout_flags("c64", "bitrev"), None, p)
+            assert d.T == tiles[p], (n, p, d.T)
 
 
 def test_pass_tile_config():
@@ -543,3 +545,16 @@ def test_bitrev_last_pass_stores_rows(dtype):
         d, launch = E.get_pass(n, -1, "unitary", lay, None, last)
         lanes = E.P(d.st_thr_w)[: d.T - d.r]
         assert lanes[:3] == [0, 1, 2], (n, lanes)
+        assert d.grp[d.ngroups - 1].nst == 0
+        if d.m <= 10:
+            # the compile-time two-group kernel with the store exchange runs
+            # it, its group-0 factors from the planner's per-thread table
+            assert d.ngroups == 3
+            assert info.pass_kernel[last] == 16 + d.grp[1].nst, (n, info.pass_kernel[last])
+        else:
+            # a three-group pass plus the exchange: the generic kernel
+            assert d.ngroups == 4 and info.pass_kernel[last] == 0
+        if n in (14, 20, 28):
+            W = E.get_tables(n, -1, "unitary", lay, None)[0]
+            image, dt = E.get_table_image(n, -1, "unitary", lay, None)
+            assert E.check_group_table(d, launch, image, dt, W, group=0)
