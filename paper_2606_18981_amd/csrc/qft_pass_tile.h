@@ -717,7 +717,14 @@ __device__ __forceinline__ void pass2_tile(const PassDesc &d, uint32_t tile, con
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) v[rho] = ld_elem<NT>(src + deposit_reg<RB>(rho, d.ld_reg_w));
   }
-  conj_if<RB>(v, d.conj_in != 0);
+  // (four-wave form: a uniform branch; the branch-free sign flip keeps the
+  // compiler from starting the first network before every load is back and
+  // spills the 128-VGPR budget)
+  if constexpr (W4) {
+    if (d.conj_in) conj_regs<Real, RB>(v);
+  } else {
+    conj_if<RB>(v, d.conj_in != 0);
+  }
   if (d.norm_part) norm_partial<Real, RB>(v, d.norm_part, tile, tid);
 
   // (four-wave form: scheduling fences around the first network keep the
@@ -873,7 +880,14 @@ __device__ __forceinline__ void pass3_tile(const PassDesc &d, uint32_t tile, con
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) v[rho] = ld_elem<NT>(src + deposit_reg<RB>(rho, d.ld_reg_w));
   }
-  conj_if<RB>(v, d.conj_in != 0);
+  // (four-wave form: a uniform branch; the branch-free sign flip keeps the
+  // compiler from starting the first network before every load is back and
+  // spills the 128-VGPR budget)
+  if constexpr (W4) {
+    if (d.conj_in) conj_regs<Real, RB>(v);
+  } else {
+    conj_if<RB>(v, d.conj_in != 0);
+  }
   if (d.norm_part) norm_partial<Real, RB>(v, d.norm_part, tile, tid);
 
   // (four-wave form: scheduling fences around the first network keep the
