@@ -32,9 +32,11 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = (
     "csrc/qft_kernels.hip",
     "csrc/qft_kernels.h",
+    "csrc/qft_pass_tile.h",
     "csrc/qft_internal.h",
     "csrc/qft_planner.cpp",
     "csrc/qft_planner.h",
+    "build.py",  # the compiler flags
 )
 
 PASS_PREFIX = "void qft::k_fused_pass"

@@ -151,21 +151,22 @@ def test_fused_metrics_match_separate(env, n, k, dtype, order, inverse, schedule
     plan.close()
 
 
-@pytest.mark.parametrize("n,dtype", [(28, "c64"), (26, "c128")])
-def test_fused_metrics_default_plans_large(env, n, dtype):
+@pytest.mark.parametrize("n,dtype,order", [(28, "c64", "natural"), (26, "c128", "natural"),
+                                           (28, "c64", "bitrev")])
+def test_fused_metrics_default_plans_large(env, n, dtype, order):
     # the default plans of the headline sizes, AQFT against the exact
     # transform: the measured error sits at the closed-form expectation
     torch, Q = env
     k = 10
-    print(f"[gpu] fused metrics default plan n={n} {dtype} k={k}", flush=True)
+    print(f"[gpu] fused metrics default plan n={n} {dtype} {order} k={k}", flush=True)
     x = torch.empty(1 << n, dtype=tdtype(torch, dtype), device="cuda")
     Q.fill_random(x, "gaussian", seed=9200 + n, stream_id=0)
     ref = x.clone()
-    ep = Q.Plan(n, -1, "unitary", dtype, "natural")
+    ep = Q.Plan(n, -1, "unitary", dtype, order)
     ep.execute(ref)
     ep.close()
-    plan = Q.Plan(n, k, "unitary", dtype, "natural")
-    got = check_against_separate(torch, Q, plan, x, ref, f"default n={n} {dtype} k={k}")
+    plan = Q.Plan(n, k, "unitary", dtype, order)
+    got = check_against_separate(torch, Q, plan, x, ref, f"default n={n} {dtype} {order} k={k}")
     assert got["rel_l2"] == pytest.approx(Q.expected_error(n, k), rel=0.05)
     plan.close()
     del x, ref
