@@ -331,9 +331,13 @@ __device__ __forceinline__ void stage_sweep(c2<Real> *lds, const DevOp<Real> *so
 // register budget of two waves is what the stage code needs.)
 // FULL: every stage has Shape::kStageBits positions (tiles of at least that
 // many bits); otherwise stages of 1..kStageBits positions.
+// The operations and diagonal records come in as their own read-only,
+// non-aliasing arguments: the compiler then reads them (wave-uniform) with
+// scalar loads instead of vector loads through the vector cache.
 template <typename Real, bool FULL>
 __global__ void __launch_bounds__(kCircThreads) __attribute__((amdgpu_waves_per_eu(2)))
-k_circuit_pass(const CircPass d, c2<Real> *psi) {
+k_circuit_pass(const CircPass d, c2<Real> *__restrict__ psi,
+               const DevOp<Real> *__restrict__ ops, const DevDiag<Real> *__restrict__ recs) {
   using C = c2<Real>;
   using S = Shape<Real>;
   extern __shared__ __align__(16) unsigned char circ_smem[];
@@ -351,8 +355,6 @@ k_circuit_pass(const CircPass d, c2<Real> *psi) {
   for (int b = 0; b < d.nfree; ++b) base |= (uint64_t)((tile >> b) & 1u) << pos_get(d.free_w, b);
   const int TL = d.TL, TH = d.T - d.TL;
   const uint32_t mlo = (1u << TL) - 1u;
-  const DevOp<Real> *ops = (const DevOp<Real> *)d.ops;
-  const DevDiag<Real> *recs = (const DevDiag<Real> *)d.recs;
   // element e of the tile is psi[alo[e & mlo] | ahi[e >> TL]]
   if (tid < 64u) {
     if (tid <= mlo) {
@@ -866,7 +868,8 @@ hipError_t launch_circuit_pass(const CircPass &p, void *dev_ptr, hipStream_t s) 
                                     (int)circuit_lds_bytes<Real>(kMaxTile<Real>()));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(fn, dim3(p.ntiles), dim3(kCircThreads), lds, s, p, (c2<Real> *)dev_ptr);
+  hipLaunchKernelGGL(fn, dim3(p.ntiles), dim3(kCircThreads), lds, s, p, (c2<Real> *)dev_ptr,
+                     (const DevOp<Real> *)p.ops, (const DevDiag<Real> *)p.recs);
   return hipGetLastError();
 }
 
