@@ -69,7 +69,8 @@ size_t qft_execute_compare_workspace_bytes(const qft_plan_t *plan);
  * comparison pass follows the transform.  The partials are combined in a
  * fixed order, so a call is deterministic; the sums are the same as
  * qft_compare's up to FP64 rounding order (the maxima and the argmax are
- * identical).  ref must not overlap dev_ptr (QFT_ERR_INVALID).
+ * identical).  ref must not overlap dev_ptr or the workspace
+ * (QFT_ERR_INVALID).
  * cmp_workspace: device memory of qft_execute_compare_workspace_bytes(plan)
  * bytes, 8-byte aligned, caller-owned; calls that share it must be ordered
  * on one stream.  Errors as qft_execute_ws, and QFT_ERR_POINTER for a NULL

@@ -330,6 +330,12 @@ int qft_execute_compare(qft_plan_t *plan, void *dev_ptr, void *workspace, const 
   const uintptr_t r0 = (uintptr_t)ref, d0 = (uintptr_t)dev_ptr;
   if (r0 < d0 + bytes && d0 < r0 + bytes)
     return set_error(QFT_ERR_INVALID, "the reference overlaps the transformed array");
+  if (workspace && hp.ws_bytes) {
+    // the passes before the last one write the workspace
+    const uintptr_t w0 = (uintptr_t)workspace;
+    if (r0 < w0 + hp.ws_bytes && w0 < r0 + bytes)
+      return set_error(QFT_ERR_INVALID, "the reference overlaps the plan's workspace");
+  }
   hipStream_t s = (hipStream_t)stream;
   double *part = (double *)cmp_workspace;
   hipError_t e = hipSuccess;

@@ -225,6 +225,14 @@ def test_fused_metrics_errors(env):
     mo = torch.empty(len(Q.METRIC_NAMES), dtype=torch.float64, device="cuda")
     with pytest.raises(Q.QftError):
         plan.execute(x, ref=x, metrics_out=mo)  # the reference overlaps the data
+    # ... or the workspace the earlier passes of a multi-pass plan write
+    p16 = Q.Plan(16, -1, "unitary", "c64", "natural")
+    x16 = torch.zeros(1 << 16, dtype=torch.complex64, device="cuda")
+    ws = torch.empty(p16.info.workspace_bytes // 8, dtype=torch.complex64, device="cuda")
+    assert ws.numel() == x16.numel()
+    with pytest.raises(Q.QftError):
+        p16.execute(x16, workspace=ws, ref=ws, metrics_out=mo)
+    p16.close()
     with pytest.raises(ValueError):
         plan.execute(x, ref=x.clone(), metrics_out=mo.float())
     with pytest.raises(ValueError):
