@@ -161,10 +161,30 @@ struct RunTables {
   c2<Real> hi[1 << Shape<Real>::kHighBits];
 };
 
+// Product of the factors of records [r0, r1) at tile element e.  The
+// records are read four at a time before any is used, so that their scalar
+// loads are in flight together rather than one round trip per record.
+template <typename Real>
+__device__ __forceinline__ c2<Real> record_product(const DevDiag<Real> *__restrict__ recs, int r0,
+                                                   int r1, uint32_t e, uint64_t base) {
+  c2<Real> f{(Real)1, (Real)0};
+  int r = r0;
+  for (; r + 4 <= r1; r += 4) {
+    DevDiag<Real> rr[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) rr[k] = recs[r + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) f = cmul2(f, diag_factor(rr[k], e, base));
+  }
+  for (; r < r1; ++r) f = cmul2(f, diag_factor(recs[r], e, base));
+  return f;
+}
+
 // The factor tables of a diagonal run for this tile: thread j < 2^(TL+1)
 // computes low entry j, thread 128 + j high entry j.
 template <typename Real>
-__device__ __forceinline__ void build_tables(const DevOp<Real> &op, const DevDiag<Real> *recs,
+__device__ __forceinline__ void build_tables(const DevOp<Real> &op,
+                                             const DevDiag<Real> *__restrict__ recs,
                                              RunTables<Real> &tb, int TL, int TH, uint64_t base,
                                              uint32_t tid) {
   using C = c2<Real>;
@@ -177,22 +197,14 @@ __device__ __forceinline__ void build_tables(const DevOp<Real> &op, const DevDia
       const uint32_t e = (tid & mlo) | (hx >= 0 ? ((tid >> TL) & 1u) << hx : 0u);
       C f{(Real)1, (Real)0};
       const bool skip = ap >= 0 && (ap < TL || ap == hx) && ((e >> ap) & 1u) == 0u;
-      if (!skip) {
-        const int r1 = op.r0 + op.nlo;
-#pragma unroll 4
-        for (int r = op.r0; r < r1; ++r) f = cmul2(f, diag_factor(recs[r], e, base));
-      }
+      if (!skip) f = record_product<Real>(recs, op.r0, op.r0 + op.nlo, e, base);
       tb.lo[tid] = f;
     }
   } else if (tid - 128u < (1u << TH)) {
     const uint32_t j = tid - 128u;
     C f{(Real)1, (Real)0};
     const bool skip = ap >= TL && ((j >> (ap - TL)) & 1u) == 0u;
-    if (!skip) {
-      const int r1 = op.r0 + op.nlo, r2 = r1 + op.nhi;
-#pragma unroll 4
-      for (int r = r1; r < r2; ++r) f = cmul2(f, diag_factor(recs[r], j << TL, base));
-    }
+    if (!skip) f = record_product<Real>(recs, op.r0 + op.nlo, op.r0 + op.nlo + op.nhi, j << TL, base);
     tb.hi[j] = f;
   }
 }
