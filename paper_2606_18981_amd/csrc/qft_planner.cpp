@@ -308,7 +308,7 @@ int plan_fused(HostPlan &p, std::string &err) {
   // plans of these sizes (see the tile rule below); the pass split and the
   // three-or-four-pass choice account for it.
   auto wide_sizes = [&](int P) {
-    const bool size_ok = p.c128 ? (n >= 26 && n <= 30) : (n >= 28 && n <= 30);
+    const bool size_ok = p.c128 ? (n >= 25 && n <= 30) : (n >= 28 && n <= 30);
     return size_ok && P == 3 && r_cfg == 5 &&
            T + 1 <= r_cfg + max_thread_bits(r_cfg, p.c128) && T + 1 <= kMaxTile;
   };
@@ -443,12 +443,13 @@ int plan_fused(HostPlan &p, std::string &err) {
     // rows would be shorter than 128 bytes (n = 30 [10, 10, 10]: 10.89 ms
     // with every pass at 2^14, 11.62 with the last at 2^13, 13.40 before).
     // n = 26, 27 and 31 measured 1-3 % slower with the wider tiles.
-    // Complex128 likewise at 2^26..2^30 elements: 2^13-element tiles of 256
+    // Complex128 likewise at 2^25..2^30 elements: 2^13-element tiles of 256
     // threads in the lean form (220 VGPRs, two waves per SIMD, split
     // exchange through 64 KiB of LDS: two workgroups per CU).  n = 28
     // 5.51 -> 4.78 ms (first pass 2.12 -> 1.64 ms with 256-byte rows),
     // n = 29 12.09 -> 9.66 ms, n = 30 23.6 ms in four passes -> 20.6 ms
-    // in three, n = 26 and 27 3-6 % faster.
+    // in three, n = 26 and 27 3-6 % faster, n = 25 0.67 -> 0.63 ms (middle
+    // pass 0.23 -> 0.20 ms with 128-byte rows); n = 24 within noise.
     const bool wide_high = wide_sizes(P);
     for (int i = 0; i < P; ++i) {
       PassGeom g;

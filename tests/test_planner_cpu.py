@@ -267,7 +267,7 @@ def test_nontemporal_rule():
     assert nts(28) == [1, 1, 1]        # 256 B rows, 128 B rows (2^14 tiles), contiguous
     assert nts(27) == [1, 0, 1]        # 256 B rows, 64 B rows, contiguous
     assert nts(27, "c128") == [1, 1, 1]   # 2^13 tiles: 128 B middle rows
-    assert nts(25, "c128") == [1, 0, 1]
+    assert nts(25, "c128") == [1, 1, 1]   # 2^13 tiles: 128 B middle rows
     assert nts(24) == [0, 0, 0]        # 128 MiB state: stays cached
     assert nts(25) == [1, 0, 1]        # 256 MiB
     assert nts(24, "c128") == [1, 0, 1]
@@ -386,7 +386,7 @@ def test_three_group_middle_pass_rule():
 
 
 def test_wide_high_pass_tiles():
-    """Three-pass plans of 2^28..2^30 complex64 or 2^26..2^30 complex128
+    """Three-pass plans of 2^28..2^30 complex64 or 2^25..2^30 complex128
     elements give every pass below which other qubits lie one more tile bit
     (2^14 complex64 tiles of 512 threads, 2^13 complex128 of 256: the lean
     kernels), and the last pass too where its rows would otherwise be
@@ -406,7 +406,7 @@ def test_wide_high_pass_tiles():
         for p in range(info.num_passes):
             d, _ = E.get_pass(n, -1, "unitary", lay, None, p)
             assert d.T <= 13 or (n == 31 and p == 0), (n, p, d.T)
-    c128 = {24: [12, 12, 12], 25: [12, 12, 12], 26: [13, 13, 12], 28: [13, 13, 12],
+    c128 = {24: [12, 12, 12], 25: [13, 13, 12], 26: [13, 13, 12], 28: [13, 13, 12],
             29: [13, 13, 13], 30: [13, 13, 13]}
     for n, tiles in c128.items():
         for p in range(3):
