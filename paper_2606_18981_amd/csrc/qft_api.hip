@@ -76,19 +76,20 @@ int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm
   hipError_t e = hipSuccess;
   size_t li = 0;
   const bool timing = p->timing && allow_timing;
-  auto mark = [&](size_t i) {
-    if (timing) hipEventRecord(p->timer.slot(i), s);
+  auto mark = [&](size_t i) -> hipError_t {
+    return timing ? hipEventRecord(p->timer.slot(i), s) : hipSuccess;
   };
   const uint32_t nparts = norm_out ? norm_parts_for(p) : 0;
   if (norm_out && hp.schedule == Schedule::Gates) {
     e = launch_norm_sweep(dev, hp.n, hp.c128, part, nparts, s);
     if (e != hipSuccess) return hip_error(e, "norm sweep launch");
   }
-  if (timing) p->timer.begin(p->num_launches());
+  if (timing && (e = p->timer.begin(p->num_launches())) != hipSuccess)
+    return hip_error(e, "timing events");
   if (hp.schedule == Schedule::Fused) {
     for (size_t i = 0; i < p->launches.size(); ++i) {
       const PassLaunch &L = p->launches[i];
-      mark(li);
+      if ((e = mark(li)) != hipSuccess) return hip_error(e, "timing event record");
       const void *in = L.in_ws ? ws : dev;
       void *out = L.out_ws ? ws : dev;
       const bool first_norm = i == 0 && norm_out;
@@ -113,7 +114,7 @@ int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm
     }
   } else {
     for (const Gate &g : hp.gates) {
-      mark(li);
+      if ((e = mark(li)) != hipSuccess) return hip_error(e, "timing event record");
       if (g.kind == 0) e = launch_h(dev, hp.n, g.a, hp.c128, s);
       else if (g.kind == 1) e = launch_cphase(dev, hp.n, g.a, g.b, g.re, g.im, hp.c128, s);
       else e = launch_swap(dev, hp.n, g.a, g.b, hp.c128, s);
@@ -121,13 +122,13 @@ int enqueue_plan(qft_plan_s *p, void *dev, void *ws, hipStream_t s, double *norm
       ++li;
     }
     if (hp.gate_norm != 1.0) {
-      mark(li);
+      if ((e = mark(li)) != hipSuccess) return hip_error(e, "timing event record");
       e = launch_scale(dev, hp.n, hp.gate_norm, hp.c128, s);
       if (e != hipSuccess) return hip_error(e, "scale launch");
       ++li;
     }
   }
-  mark(li);
+  if ((e = mark(li)) != hipSuccess) return hip_error(e, "timing event record");
   if (timing) p->timer.end();
   if (norm_out) {
     e = launch_norm_finish(part, nparts, norm_out, s);
@@ -169,21 +170,23 @@ int check_execute(qft_plan_s *plan, void *dev_ptr, void *workspace) {
 
 hipEvent_t LaunchTimer::slot(size_t i) { return events[cur_base + i]; }
 
-void LaunchTimer::begin(int launches) {
+hipError_t LaunchTimer::begin(int launches) {
   nl = launches;
   const size_t need = (size_t)(execs + 1) * (size_t)(launches + 1);
   while (events.size() < need) {
     hipEvent_t ev;
-    hipEventCreate(&ev);
+    const hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
     events.push_back(ev);
   }
   cur_base = (size_t)execs * (size_t)(launches + 1);
+  return hipSuccess;
 }
 
 void LaunchTimer::end() { ++execs; }
 
 void LaunchTimer::release() {
-  for (hipEvent_t ev : events) hipEventDestroy(ev);
+  for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
   events.clear();
   execs = 0;
 }
@@ -229,7 +232,7 @@ static qft_plan_t *make_plan(int n, int cutoff, int norm, int layout, const qft_
     e = hipMemcpy(p->d_tables, hp.tables.data(), hp.tables.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       hip_error(e, "table upload");
-      hipFree(p->d_tables);
+      (void)hipFree(p->d_tables);
       delete p;
       return nullptr;
     }
@@ -238,7 +241,7 @@ static qft_plan_t *make_plan(int n, int cutoff, int norm, int layout, const qft_
     e = hipMalloc(&p->d_ws, hp.ws_bytes);
     if (e != hipSuccess) {
       hip_error(e, "workspace allocation");
-      if (p->d_tables) hipFree(p->d_tables);
+      if (p->d_tables) (void)hipFree(p->d_tables);
       delete p;
       return nullptr;
     }
@@ -330,9 +333,9 @@ void qft_destroy(qft_plan_t *plan) {
   if (!plan) return;
   batch_forget_plan(plan);
   plan->timer.release();
-  if (plan->d_tables) hipFree(plan->d_tables);
-  if (plan->d_ws) hipFree(plan->d_ws);
-  if (plan->d_norm) hipFree(plan->d_norm);
+  if (plan->d_tables) (void)hipFree(plan->d_tables);
+  if (plan->d_ws) (void)hipFree(plan->d_ws);
+  if (plan->d_norm) (void)hipFree(plan->d_norm);
   delete plan;
 }
 

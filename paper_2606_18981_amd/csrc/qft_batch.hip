@@ -58,18 +58,18 @@ struct BatchEntry {
   hipEvent_t join_ev[kForkStreams - 1] = {};
 
   void release() {
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
-    for (void *w : workspaces) hipFree(w);
-    if (d_mem) hipFree(d_mem);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (void *w : workspaces) (void)hipFree(w);
+    if (d_mem) (void)hipFree(d_mem);
     for (hipStream_t &st : side) {
-      if (st) hipStreamDestroy(st);
+      if (st) (void)hipStreamDestroy(st);
       st = nullptr;
     }
-    if (fork_ev) hipEventDestroy(fork_ev);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
     fork_ev = nullptr;
     for (hipEvent_t &ev : join_ev) {
-      if (ev) hipEventDestroy(ev);
+      if (ev) (void)hipEventDestroy(ev);
       ev = nullptr;
     }
     exec = nullptr;
@@ -305,7 +305,7 @@ int capture_entry(BatchEntry *e) {
     if (le != hipSuccess) he = le;
   }
   if (he == hipSuccess) he = hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0);
-  hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs);
   if (he != hipSuccess) return hip_error(he, "batch graph capture");
   return QFT_OK;
 }
@@ -317,7 +317,8 @@ void batch_forget_plan(qft_plan_s *plan) {
   for (size_t i = 0; i < g_cache.size();) {
     BatchEntry *e = g_cache[i];
     if (std::find(e->plans.begin(), e->plans.end(), plan) != e->plans.end()) {
-      hipDeviceSynchronize();
+      // (a device error here is sticky: the caller's next call reports it)
+      (void)hipDeviceSynchronize();
       e->release();
       delete e;
       g_cache.erase(g_cache.begin() + i);
@@ -380,7 +381,12 @@ int qft_execute_batch_ex(qft_plan_t *const *plans, void *const *dev_ptrs, int co
     if (g_cache.size() >= kMaxCachedSets) {
       // the oldest set may still run on some stream: wait for the device
       // before its graph, workspaces and streams are released
-      hipDeviceSynchronize();
+      const hipError_t he = hipDeviceSynchronize();
+      if (he != hipSuccess) {
+        e->release();
+        delete e;
+        return hip_error(he, "batch cache eviction");
+      }
       g_cache.front()->release();
       delete g_cache.front();
       g_cache.erase(g_cache.begin());

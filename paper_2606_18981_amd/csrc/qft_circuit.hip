@@ -495,7 +495,7 @@ namespace {
 int check_qubit(const qft_circuit_s *c, int q) { return q >= 0 && q < c->n; }
 
 void drop_compiled(qft_circuit_s *c) {
-  if (c->d_gates) hipFree(c->d_gates);
+  if (c->d_gates) (void)hipFree(c->d_gates);
   c->d_gates = nullptr;
   c->passes.clear();
   c->gate_begin.clear();

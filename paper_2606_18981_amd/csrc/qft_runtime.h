@@ -18,7 +18,7 @@ struct LaunchTimer {
   size_t cur_base = 0;
   int nl = 0;
   hipEvent_t slot(size_t i);
-  void begin(int launches);
+  hipError_t begin(int launches);  // creates the events it needs
   void end();
   void release();
 };

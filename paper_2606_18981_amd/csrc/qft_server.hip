@@ -37,11 +37,12 @@ struct BlockPool {
     void *p = nullptr;
     *err = hipMalloc(&p, bytes);
     if (*err != hipSuccess) {
-      // give cached blocks of other sizes back and retry once
-      hipDeviceSynchronize();
+      // give cached blocks of other sizes back and retry once (the retry
+      // reports any device error)
+      (void)hipDeviceSynchronize();
       for (auto &kv : free_blocks)
         for (void *q : kv.second) {
-          hipFree(q);
+          (void)hipFree(q);
           all.erase(std::find(all.begin(), all.end(), q));
         }
       free_blocks.clear();
@@ -55,7 +56,7 @@ struct BlockPool {
     if (p) free_blocks[bytes].push_back(p);
   }
   void clear() {
-    for (void *p : all) hipFree(p);
+    for (void *p : all) (void)hipFree(p);
     all.clear();
     free_blocks.clear();
   }
@@ -72,7 +73,7 @@ struct qft_server_s {
   BlockPool pool;
   ~qft_server_s() {
     for (auto &kv : plans) qft_destroy(kv.second);
-    for (hipStream_t s : streams) hipStreamDestroy(s);
+    for (hipStream_t s : streams) (void)hipStreamDestroy(s);
     pool.clear();
   }
   PlanKey key(const qft_request_t &r) const {
@@ -219,7 +220,7 @@ qft_server_t *qft_server_create(size_t hbm_budget_bytes, int max_inflight, int n
 
 void qft_server_destroy(qft_server_t *server) {
   if (!server) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();  // nothing of the server may still run
   delete server;
 }
 
@@ -275,7 +276,7 @@ int qft_server_run(qft_server_t *server, const qft_request_t *reqs, int count,
   st.hbm_bytes = dev.hbm_bytes;
   st.plan_bytes = plan_bytes;
   st.peak_reserved_bytes += plan_bytes;
-  for (hipEvent_t ev : dev.free_events) hipEventDestroy(ev);
+  for (hipEvent_t ev : dev.free_events) (void)hipEventDestroy(ev);
   for (int i = 0; i < count; ++i) results[i] = res[i];
   if (stats) *stats = st;
   return st.failed ? QFT_ERR_HIP : QFT_OK;

@@ -114,20 +114,37 @@ bool get_str(const char *line, const char *key, std::string *v) {
   return true;
 }
 
+// The tuner's stream and its two timing events; on failure nothing stays
+// allocated.
+int tuner_resources(hipStream_t *s, hipEvent_t *a, hipEvent_t *b) {
+  hipError_t he = hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+  if (he != hipSuccess) return hip_error(he, "tuner stream");
+  if ((he = hipEventCreate(a)) != hipSuccess) {
+    (void)hipStreamDestroy(*s);
+    return hip_error(he, "tuner events");
+  }
+  if ((he = hipEventCreate(b)) != hipSuccess) {
+    (void)hipEventDestroy(*a);
+    (void)hipStreamDestroy(*s);
+    return hip_error(he, "tuner events");
+  }
+  return QFT_OK;
+}
+
 int time_plan(qft_plan_t *p, void *data, int reps, hipStream_t s, hipEvent_t a, hipEvent_t b,
               double *ms) {
   int rc = qft_execute(p, data, s);
   if (rc != QFT_OK) return rc;
-  hipEventRecord(a, s);
+  hipError_t he = hipEventRecord(a, s);
+  if (he != hipSuccess) return hip_error(he, "tuner timing");
   for (int i = 0; i < reps; ++i) {
     rc = qft_execute(p, data, s);
     if (rc != QFT_OK) return rc;
   }
-  hipEventRecord(b, s);
-  hipError_t he = hipEventSynchronize(b);
-  if (he != hipSuccess) return hip_error(he, "tuner timing");
+  if ((he = hipEventRecord(b, s)) != hipSuccess) return hip_error(he, "tuner timing");
+  if ((he = hipEventSynchronize(b)) != hipSuccess) return hip_error(he, "tuner timing");
   float f = 0.f;
-  hipEventElapsedTime(&f, a, b);
+  if ((he = hipEventElapsedTime(&f, a, b)) != hipSuccess) return hip_error(he, "tuner timing");
   *ms = f / reps;
   return QFT_OK;
 }
@@ -184,10 +201,10 @@ int qft_tune(int n, int cutoff, int norm, int layout, void *data, int reps, qft_
   if (cands.empty()) return set_error(QFT_ERR_UNSUPPORTED, "no valid configuration");
   hipStream_t s;
   hipEvent_t a, b;
-  hipError_t he = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-  if (he != hipSuccess) return hip_error(he, "tuner stream");
-  hipEventCreate(&a);
-  hipEventCreate(&b);
+  {
+    const int r = tuner_resources(&s, &a, &b);
+    if (r != QFT_OK) return r;
+  }
   double bms = 1e300;
   qft_config_t bc = cands[0];
   int rc = QFT_OK;
@@ -206,9 +223,9 @@ int qft_tune(int n, int cutoff, int norm, int layout, void *data, int reps, qft_
       bc = c;
     }
   }
-  hipEventDestroy(a);
-  hipEventDestroy(b);
-  hipStreamDestroy(s);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipStreamDestroy(s);
   if (rc != QFT_OK) return rc;
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -226,10 +243,11 @@ int qft_tune_batch(const int *n, const int *cutoff, int count, int norm, int lay
     return set_error(QFT_ERR_INVALID, "invalid batch tuning arguments");
   hipStream_t s;
   hipEvent_t a, b;
-  hipError_t he = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-  if (he != hipSuccess) return hip_error(he, "tuner stream");
-  hipEventCreate(&a);
-  hipEventCreate(&b);
+  {
+    const int r = tuner_resources(&s, &a, &b);
+    if (r != QFT_OK) return r;
+  }
+  hipError_t he = hipSuccess;
   double bms = 1e300;
   qft_config_t bc{};
   bool found = false;
@@ -259,16 +277,16 @@ int qft_tune_batch(const int *n, const int *cutoff, int count, int norm, int lay
       // the first call builds the work list and captures the graph
       int r1 = qft_execute_batch_ex(pv.data(), data, count, 0, s);
       if (r1 == QFT_OK) {
-        hipEventRecord(a, s);
-        for (int i = 0; i < reps && r1 == QFT_OK; ++i)
+        he = hipEventRecord(a, s);
+        for (int i = 0; i < reps && r1 == QFT_OK && he == hipSuccess; ++i)
           r1 = qft_execute_batch_ex(pv.data(), data, count, 0, s);
-        hipEventRecord(b, s);
-        he = hipEventSynchronize(b);
+        if (he == hipSuccess) he = hipEventRecord(b, s);
+        if (he == hipSuccess) he = hipEventSynchronize(b);
+        float f = 0.f;
+        if (he == hipSuccess && r1 == QFT_OK) he = hipEventElapsedTime(&f, a, b);
         if (he != hipSuccess) {
           rc = hip_error(he, "batch tuner timing");
         } else if (r1 == QFT_OK) {
-          float f = 0.f;
-          hipEventElapsedTime(&f, a, b);
           const double ms = f / reps;
           if (ms < bms) {
             bms = ms;
@@ -281,9 +299,9 @@ int qft_tune_batch(const int *n, const int *cutoff, int count, int norm, int lay
     for (auto &kv : plans) qft_destroy(kv.second);
     if (rc != QFT_OK) break;
   }
-  hipEventDestroy(a);
-  hipEventDestroy(b);
-  hipStreamDestroy(s);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipStreamDestroy(s);
   if (rc != QFT_OK) return rc;
   if (!found) return set_error(QFT_ERR_UNSUPPORTED, "no configuration ran the batch");
   // (the per-shape table is left alone: the batch's winner is best for the
